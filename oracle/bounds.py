@@ -1,0 +1,151 @@
+"""Truncation-error bounds and the pruning arithmetic (sections 4-6).
+
+  E_DH(p)  = W_R e^{-dmin^2/4h^2} C(D+p-1,D-1) r_R^p / sqrt(F(p))          (Lemma 4)
+  E_DL(p)  = W_R e^{-dmin^2/4h^2} C(D+p-1,D-1) r_Q^p / sqrt(F(p))          (Lemma 5)
+  E_H2L(p) = W_R e^{-dmin^2/4h^2} C(D+p-1,D-1) / sqrt(F(p))
+             * ( r_Q^p + (sqrt2 r_R)^p C(D+p-1,D) (sqrt2 r_Q)^{I(sqrt2 r_Q)} ) (Lemma 6)
+  E_FD     = W_R (K(dmin) - K(dmax)) / 2                                    (section 5)
+  with F(p) = (floor(p/D)!)^{D-p'} (ceil(p/D)!)^{p'},  p' = p mod D,
+  r_R = max_{r in R} |x_r - x_R|_inf / h,  r_Q likewise,
+  I(x) = 0 for x <= 1, p-1 otherwise.
+
+Lemma 6's printed formula is ambiguous about which bracket term the factor
+(sqrt2 r_Q)^I multiplies; the proof attaches it to the E_1 part only, and that
+is the reading implemented here.
+
+Every value that decides a pruning is computed in a fixed order of
+round-to-nearest double operations with the own exponential of exp64, so the
+decisions can be reproduced bit for bit: the product is always
+((W_R * g) * c(D,p)) * tail with g = exp64(-dmin^2 * inv_4h2), and powers are
+left-to-right repeated products.
+
+Pinned by tests/test_oracle_bounds.py: on random node pairs the true
+truncation error of each method (computed with the series of `series`) never
+exceeds the bound, and the bound is not vacuous (the worst ratio is within a
+modest factor of 1).
+"""
+
+import math
+
+SQRT2 = 1.4142135623730951  # nearest double to sqrt(2)
+
+
+def powi(x, p):
+    """x^p for an integer p >= 0 as the left-to-right product x*x*...*x."""
+    v = 1.0
+    for _ in range(p):
+        v = v * x
+    return v
+
+
+def bound_const(D, p):
+    """C(D+p-1, D-1) / sqrt(F(p)), F as in the module docstring (Lemma 4)."""
+    q, pp = divmod(p, D)
+    ceil_q = q + 1 if pp else q
+    F = math.factorial(q) ** (D - pp) * math.factorial(ceil_q) ** pp
+    return float(math.comb(D + p - 1, D - 1)) / math.sqrt(float(F))
+
+
+def e_dh(W_R, g, D, p, r_R):
+    """Lemma 4 with g = exp(-dmin^2/4h^2)."""
+    return ((W_R * g) * bound_const(D, p)) * powi(r_R, p)
+
+
+def e_dl(W_R, g, D, p, r_Q):
+    """Lemma 5 with g = exp(-dmin^2/4h^2)."""
+    return ((W_R * g) * bound_const(D, p)) * powi(r_Q, p)
+
+
+def e_h2l(W_R, g, D, p, r_Q, r_R):
+    """Lemma 6 with g = exp(-dmin^2/4h^2)."""
+    sq = SQRT2 * r_Q
+    itail = 1.0 if sq <= 1.0 else powi(sq, p - 1)
+    second = (powi(SQRT2 * r_R, p) * float(math.comb(D + p - 1, D))) * itail
+    return ((W_R * g) * bound_const(D, p)) * (powi(r_Q, p) + second)
+
+
+def e_fd(W_R, kmin, kmax):
+    """Section 5: E_FD = W_R (K(dmin) - K(dmax)) / 2."""
+    return 0.5 * (W_R * (kmin - kmax))
+
+
+def need(E, W_R, L, W, eps_alg):
+    """Token a pruning with absolute error E costs (section 5):
+    W E / (eps L) - W_R.  Negative values are deposits.  E = 0 deposits the
+    whole W_R; a zero lower bound L makes any positive error unaffordable."""
+    if E == 0.0:
+        return -W_R
+    if L == 0.0:
+        return math.inf
+    return (W * E) / (eps_alg * L) - W_R
+
+
+def box_dist2(loQ, hiQ, loR, hiR):
+    """(dmin^2, dmax^2) between two boxes, summed over d in order (section 5:
+    the distance bounds come from the bounding boxes)."""
+    smin = 0.0
+    smax = 0.0
+    for d in range(len(loQ)):
+        gap = loQ[d] - hiR[d]
+        other = loR[d] - hiQ[d]
+        if other > gap:
+            gap = other
+        if gap < 0.0:
+            gap = 0.0
+        far = hiQ[d] - loR[d]
+        other = hiR[d] - loQ[d]
+        if other > far:
+            far = other
+        smin = smin + gap * gap
+        smax = smax + far * far
+    return smin, smax
+
+
+INF_COST = (1 << 63) - 1
+
+
+def _sat_mul(a, b):
+    v = a * b
+    return v if v < INF_COST else INF_COST
+
+
+def _pow_int(D, e):
+    v = 1
+    for _ in range(e):
+        v = _sat_mul(v, D)
+    return v
+
+
+def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R):
+    """Figure 6.  Smallest feasible order per method, cost model
+    c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1},
+    c_Direct = D N_Q N_R, first minimum in the order DH, DL, H2L, DIRECT.
+    Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
+    found = {}
+    for name, fn in (("DH", lambda p: e_dh(W_R, g, D, p, r_R)),
+                     ("DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
+                     ("H2L", lambda p: e_h2l(W_R, g, D, p, r_Q, r_R))):
+        for p in range(1, plimit + 1):
+            E = fn(p)
+            if E <= maxerr:
+                found[name] = (p, E)
+                break
+    costs = []
+    for name in ("DH", "DL", "H2L"):
+        if name in found:
+            p = found[name][0]
+            if name == "DH":
+                c = _sat_mul(N_Q, _pow_int(D, p + 1))
+            elif name == "DL":
+                c = _sat_mul(N_R, _pow_int(D, p + 1))
+            else:
+                c = _pow_int(D, 2 * p + 1)
+        else:
+            c = INF_COST
+        costs.append(c)
+    costs.append(_sat_mul(D, _sat_mul(N_Q, N_R)))
+    best = min(costs)
+    for i, name in enumerate(("DH", "DL", "H2L")):
+        if costs[i] == best and name in found:
+            return name, found[name][0], found[name][1]
+    return "DIRECT", 0, math.inf

@@ -1,0 +1,233 @@
+"""The dual-tree Gaussian summation with token error control (sections 5-6,
+Figures 1, 6, 7, 8), run level by level.
+
+The paper states the recursion depth first (Figure 1) and notes that the order
+of the node-pair visits is free (it can also be driven by a priority queue).
+This oracle visits the node pairs breadth first: a frontier of (Q, R) pairs is
+refined one level at a time, and every pair of the frontier is either resolved
+(finite difference, a series expansion, or an exhaustive base case) or split
+into child pairs.  It is the schedule the GPU library follows, so the pair
+lists it records are the ones the library must reproduce bit for bit.
+
+Per bandwidth h, with W = sum_r w_r and eps_alg = (1 - rho) eps (rho is the
+share of eps reserved for floating-point rounding):
+
+  state per query node Q: token budget T_Q (starts at 0, section 5), Lpush_Q
+  (lower bound on the contribution of the reference nodes already resolved
+  against Q or an ancestor), Gest_Q, local coefficients lco_Q of order pL_Q.
+
+  For each frontier segment (Q; R_1..R_k), the R_j in left-to-right tree order:
+   1. lower bound on G over Q (the running G_Q^min of section 5):
+        L = Lpush_Q + sum_j W_Rj K(dmax(Q,R_j))        (sequential in j)
+      and, when the queries are the references themselves, L = max(L, wmin_Q)
+      because every query receives its own term w_q K(0) = w_q.
+   2. for j = 1..k, with t the running token (Figure 7):
+        FD if need(E_FD) <= t: t -= need, Gest_Q += W_R (K(dmin)+K(dmax))/2;
+        else bestMethod(maxerr = eps_alg (W_R + t) L / W) (Figure 6); if it is
+        not DIRECT: t -= need(E_A), record (Q, R, p) for DH, DL or H2L;
+        else if both are leaves: exhaustive base case, t += W_R (E_EX = 0);
+        else split: both internal -> 4 child pairs, otherwise split the
+        internal one.
+      Every resolved pair adds W_R K(dmax) to Lpush_Q.
+      need(E) = W E / (eps_alg L) - W_R (section 5; see bounds.need).
+   3. child segments inherit the final t and Lpush_Q by copy: a token is a
+      per-query-point budget (proof of Theorem 2), valid for every point of Q.
+
+  After the traversal the recorded work is executed (the contributions are
+  additive and no decision depends on them): base cases add exact sums,
+  DH adds the Hermite series at each query, DL and H2L add local
+  coefficients.  Then the post-pass of Figure 8 runs top down: Gest and L2L
+  translated local coefficients are pushed to the children, and at a leaf
+  every query receives gx + gdh + Gest_Q + EVALL(lco_Q).
+
+Decisions depend only on the tree geometry, weights, counts and h: they are
+computed in IEEE double with the own exponential (exp64) in a fixed operation
+order, which is what makes them reproducible bit for bit.  Every query result
+satisfies |G~ - G| <= eps_alg G (Theorem 2), plus rounding.
+
+Readings of the paper taken here (each also listed in the design notes):
+  * the base case weights each kernel value by w_r (Figure 7 omits it);
+  * Figure 8's "G_q^est = EVALL + G_Q^est" adds to the base-case and DH sums;
+  * the token update uses W E_A/(eps G_Q^min) - W_R, the dimensionally
+    consistent form of section 5 with an absolute E_A;
+  * G_Q^min is the box lower bound described in step 1 (the paper does not
+    say how it is initialised or propagated in a level-wise traversal);
+  * pL_Q is the largest order of any local contribution at Q or above.
+"""
+
+import math
+
+import numpy as np
+
+from .bounds import best_method, box_dist2, e_fd, need
+from .exp64 import exp64
+from .kdtree import attach_moments, build_kdtree
+from .multiindex import num_terms, plimit_for
+from .series import direct_local, eval_hermite, eval_local, h2l, l2l, scale_moments
+
+FD, DH, DL, H2L, BASE, SPLIT = 0, 1, 2, 3, 4, 5
+CODE = {"DH": DH, "DL": DL, "H2L": H2L}
+METHODS = ("dito", "dfdo", "dfd")
+
+
+class Result:
+    pass
+
+
+def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
+             method="dito", mono=None, trace=False):
+    """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
+    decision trace: a list of (h_index, level, Q, R, code, p) tuples."""
+    xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
+    if mono is None:
+        mono = xq is xr
+    xq = xr if mono else np.atleast_2d(np.asarray(xq, dtype=np.float64))
+    w = np.asarray(w, dtype=np.float64)
+    hs = np.atleast_1d(np.asarray(hs, dtype=np.float64))
+    if method not in METHODS:
+        raise ValueError(method)
+    D = xr.shape[1]
+    P = plimit if plimit else plimit_for(D)
+    rt = build_kdtree(xr, w, leaf_size)
+    qt = rt if mono else build_kdtree(xq, None, leaf_size)
+    if method == "dito":
+        attach_moments(rt, P)
+    eps_alg = (1.0 - eps_round_share) * eps
+    res = Result()
+    res.rtree, res.qtree, res.plimit = rt, qt, P
+    res.G = np.zeros((len(hs), xq.shape[0]))
+    res.trace = [] if trace else None
+    res.counts = np.zeros((len(hs), 6), dtype=np.int64)
+    for k, h in enumerate(hs):
+        res.G[k] = _one_bandwidth(k, float(h), qt, rt, xq, mono, P, eps_alg, method, res)
+    return res
+
+
+def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
+    D = rt.D
+    use_tokens = method in ("dito", "dfdo")
+    use_fmm = method == "dito"
+    inv_2h2 = 1.0 / (2.0 * h * h)
+    inv_4h2 = 0.5 * inv_2h2
+    inv_h = 1.0 / h
+    Wtot = float(rt.W[0])
+    nQ = qt.n_nodes
+    C = num_terms(D, P)
+    Gest = np.zeros(nQ)
+    lco = np.zeros((nQ, C))
+    pL = np.zeros(nQ, dtype=np.int64)
+    work = []  # (code, Q, R, p) in emission order
+    segs = [(0, 0.0, 0.0, [0])]
+    level = 0
+    while segs:
+        nxt = []
+        for Q, t, Lp, Rs in segs:
+            qleaf = qt.left[Q] < 0
+            geo = []
+            L = Lp
+            for R in Rs:
+                dmin2, dmax2 = box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])
+                kmax = exp64(-dmax2 * inv_2h2)
+                geo.append((dmin2, kmax))
+                L = L + float(rt.W[R]) * kmax
+            if mono and float(qt.wmin[Q]) > L:
+                L = float(qt.wmin[Q])
+            split = []
+            for j, R in enumerate(Rs):
+                WR = float(rt.W[R])
+                dmin2, kmax = geo[j]
+                kmin = exp64(-dmin2 * inv_2h2)
+                nd = need(e_fd(WR, kmin, kmax), WR, L, Wtot, eps_alg)
+                code, p = None, 0
+                if nd <= (t if use_tokens else 0.0):
+                    if use_tokens:
+                        t = t - nd
+                    Gest[Q] = Gest[Q] + 0.5 * (WR * (kmin + kmax))
+                    code = FD
+                elif use_fmm:
+                    tt = t if use_tokens else 0.0
+                    maxerr = ((eps_alg * (WR + tt)) * L) / Wtot
+                    g = exp64(-dmin2 * inv_4h2)
+                    name, p, E = best_method(D, P, maxerr, WR, g, float(qt.rinf[Q]) * inv_h,
+                                             float(rt.rinf[R]) * inv_h,
+                                             int(qt.count[Q]), int(rt.count[R]))
+                    if name != "DIRECT":
+                        if use_tokens:
+                            t = t - need(E, WR, L, Wtot, eps_alg)
+                        code = CODE[name]
+                    else:
+                        p = 0
+                if code is None:
+                    if qleaf and rt.left[R] < 0:
+                        if use_tokens:
+                            t = t + WR
+                        code = BASE
+                    else:
+                        code = SPLIT
+                if code == SPLIT:
+                    split.append(R)
+                else:
+                    Lp = Lp + WR * kmax
+                    if code != FD:
+                        work.append((code, Q, R, p))
+                res.counts[hk, code] += 1
+                if res.trace is not None:
+                    res.trace.append((hk, level, Q, R, code, p))
+            if split:
+                newR = []
+                for R in split:
+                    if rt.left[R] < 0:
+                        newR.append(R)
+                    else:
+                        newR.extend((int(rt.left[R]), int(rt.left[R]) + 1))
+                if qleaf:
+                    nxt.append((Q, t, Lp, newR))
+                else:
+                    l = int(qt.left[Q])
+                    nxt.append((l, t, Lp, list(newR)))
+                    nxt.append((l + 1, t, Lp, list(newR)))
+        segs = nxt
+        level += 1
+
+    # Execute the recorded work.
+    M = xq.shape[0]
+    gx = np.zeros(M)
+    gdh = np.zeros(M)
+    xr, w = rt.x, rt.w
+    for code, Q, R, p in work:
+        qpts = qt.perm[qt.begin[Q]:qt.end[Q]]
+        rpts = rt.perm[rt.begin[R]:rt.end[R]]
+        if code == BASE:
+            d2 = np.zeros((len(qpts), len(rpts)))
+            for d in range(D):
+                diff = xq[qpts, d][:, None] - xr[rpts, d][None, :]
+                d2 += diff * diff
+            gx[qpts] += np.exp(-d2 / (2.0 * h * h)) @ w[rpts]
+        elif code == DH:
+            A = scale_moments(rt.moments[R], D, p, h)
+            gdh[qpts] += eval_hermite(A, p, rt.ctr[R], xq[qpts], h)
+        elif code == DL:
+            lco[Q, :num_terms(D, p)] += direct_local(xr[rpts], w[rpts], p, qt.ctr[Q], h)
+            pL[Q] = max(pL[Q], p)
+        elif code == H2L:
+            A = scale_moments(rt.moments[R], D, p, h)
+            lco[Q, :num_terms(D, p)] += h2l(A, p, rt.ctr[R], qt.ctr[Q], h)
+            pL[Q] = max(pL[Q], p)
+
+    # Post-pass (Figure 8), top down in breadth-first node order.
+    G = np.zeros(M)
+    for Q in range(nQ):
+        if qt.left[Q] >= 0:
+            for c in (int(qt.left[Q]), int(qt.left[Q]) + 1):
+                Gest[c] = Gest[c] + Gest[Q]
+                if pL[Q] > 0:
+                    n = num_terms(D, pL[Q])
+                    lco[c, :n] += l2l(lco[Q, :n], pL[Q], qt.ctr[Q], qt.ctr[c], h)
+                    pL[c] = max(pL[c], pL[Q])
+        else:
+            qpts = qt.perm[qt.begin[Q]:qt.end[Q]]
+            val = gx[qpts] + gdh[qpts] + Gest[Q]
+            if pL[Q] > 0:
+                val = val + eval_local(lco[Q], pL[Q], qt.ctr[Q], xq[qpts], h)
+            G[qpts] = val
+    return G
