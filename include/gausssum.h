@@ -1,0 +1,164 @@
+/*
+ * gausssum.h - C ABI of the MI355X (gfx950) Gaussian summation library.
+ *
+ * Computes, for every query point x_q and every bandwidth h in a list,
+ *
+ *     G_h(x_q) = sum_{r=1}^{N} w_r exp(-|x_q - x_r|^2 / (2 h^2))
+ *
+ * (Lee & Gray, "Faster Gaussian Summation: Theory and Experiment", section 1),
+ * either exhaustively or with the dual-tree algorithm of sections 5-6, which
+ * guarantees |G~(x_q) - G(x_q)| <= eps G(x_q) for every query (Theorem 2).
+ *
+ * Conventions for every entry point:
+ *   - Nothing is thrown across the ABI; every call returns a gs_status.
+ *   - The caller owns all input and output buffers.  The library never keeps
+ *     a caller pointer after a call returns.
+ *   - Array pointers may point to host memory or to device memory of the
+ *     context's device; the library inspects each pointer.  Host inputs are
+ *     copied to the device inside the call; a host output is written back
+ *     before the call returns.
+ *   - A failed call leaves outputs unspecified and the context reusable; the
+ *     reason is available from gs_last_error().
+ *   - A context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef GAUSSSUM_H
+#define GAUSSSUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_ctx gs_ctx;
+typedef int32_t gs_status;
+
+enum {
+  GS_OK = 0,
+  GS_EINVAL = -1,     /* invalid argument or input value */
+  GS_ENOMEM = -2,     /* device or host allocation failed */
+  GS_EDEVICE = -3,    /* a HIP runtime call failed */
+  GS_EOVERFLOW = -4,  /* a size exceeds what the library can index */
+  GS_EINTERNAL = -5   /* internal consistency check failed */
+};
+
+/* Summation method (section 7 names the dual-tree variants). */
+enum {
+  GS_DUALTREE = 0,    /* finite difference + O(D^p) expansions + token rule (DITO) */
+  GS_EXHAUSTIVE = 1,  /* all M*N terms, no tree */
+  GS_DFD = 2,         /* finite difference only, local pruning rule (no tokens) */
+  GS_DFDO = 3         /* finite difference only, with the token rule of section 5 */
+};
+
+/* How the series method is chosen for a node pair (Figure 6). */
+enum {
+  GS_RULE = 0,        /* the paper's cost model */
+  GS_LEARNED = 1      /* the learned pair policy; every choice is still certified by
+                         the error bound, and the rule decides when it is not */
+};
+
+typedef struct gs_options {
+  int32_t struct_size;      /* sizeof(gs_options); set by gs_default_options */
+  int32_t leaf_size;        /* max points per kd-tree leaf (default 64, 1..1024) */
+  int32_t plimit;           /* max expansion order; <= 0 selects the section 6
+                               table (D=2:8, 3:6, 5:4, 6:2, >6:1) */
+  int32_t method;           /* GS_DUALTREE, GS_EXHAUSTIVE, GS_DFD, GS_DFDO */
+  int32_t policy;           /* GS_RULE or GS_LEARNED */
+  int32_t monochromatic;    /* -1: auto (queries == refs and M == N), 0: no, 1: yes */
+  int32_t blocking;         /* 1 (default): return after the results are written;
+                               0: device outputs may still be in flight on the
+                               context's stream when the call returns */
+  int32_t keep_trace;       /* 1: keep the trees and the per-pair decision trace for
+                               gs_get_tree / gs_get_trace (slow; for testing) */
+  int32_t log_pairs;        /* 1: record policy-training features and costs */
+  int32_t fmm_mask;         /* series methods bestMethod may choose (Figure 6): bit 0
+                               DH, bit 1 DL, bit 2 H2L; 0 or 7 allows all (ablations) */
+  double eps_round_share;   /* share of eps reserved for floating-point rounding
+                               (default 0.1); the pruning test uses (1-share)*eps */
+} gs_options;
+
+typedef struct gs_stats {
+  int32_t struct_size;      /* set by the caller to sizeof(gs_stats) */
+  int32_t n_h;              /* bandwidths in the last call */
+  int32_t levels;           /* frontier levels of the last traversal */
+  int32_t plimit;           /* expansion order limit used */
+  int64_t pairs[6];         /* resolved node pairs over all h: FD, DH, DL, H2L,
+                               BASE, and SPLIT decisions */
+  int64_t base_pair_evals;  /* point-pair kernel evaluations in base cases */
+  int64_t frontier_peak;    /* largest frontier (pairs over all h) */
+  int64_t policy_calls;     /* pairs on which the learned policy was consulted */
+  int64_t policy_fallbacks; /* of those, choices the bound rejected (rule used) */
+  double t_stage_ms, t_tree_ms, t_moments_ms, t_traverse_ms, t_work_ms, t_post_ms;
+  double t_total_ms;        /* wall time of the last gauss_sum call */
+} gs_stats;
+
+/* Fill *opt with the defaults listed above. */
+void gs_default_options(gs_options* opt);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to run on
+ * (for example torch's current stream), or NULL to let the context create its
+ * own stream.  The context owns its device workspace. */
+gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream);
+
+/* Free the context and its workspace.  NULL is a no-op. */
+gs_status gs_destroy(gs_ctx* ctx);
+
+/* Multi-bandwidth Gaussian summation (section 1) to relative error eps per query
+ * (Theorem 2).
+ *   queries    [M][D] row-major doubles; may equal `refs` (monochromatic: each
+ *              query also receives its own term w_q)
+ *   refs       [N][D] row-major doubles
+ *   weights    [N] doubles, each > 0 (section 1 requires w_r > 0)
+ *   bandwidths [n_h] doubles, each > 0
+ *   eps        relative error tolerance, 0 < eps < 1 (ignored by GS_EXHAUSTIVE)
+ *   G_out      [n_h][M] doubles in the caller's query order
+ *   opt        options, or NULL for defaults
+ * Errors: GS_EINVAL for M, N, n_h < 1, D < 1 or D > 64, any NaN or infinite
+ * coordinate, any weight <= 0, any bandwidth <= 0, eps outside (0,1), or an
+ * option out of range. */
+gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double* refs,
+                    const double* weights, int64_t N, int32_t D, const double* bandwidths,
+                    int32_t n_h, double eps, double* G_out, const gs_options* opt);
+
+/* Statistics of the last gauss_sum call.  out->struct_size must be set. */
+gs_status gs_get_stats(gs_ctx* ctx, gs_stats* out);
+
+/* Per-bandwidth node-pair counts of the last dual-tree call: counts[n_h][6] in
+ * the order FD, DH, DL, H2L, BASE, SPLIT (host pointer). */
+gs_status gs_get_pair_counts(gs_ctx* ctx, int64_t* counts);
+
+/* Message describing the last non-OK status on this context; owned by the
+ * context and valid until its next call. */
+const char* gs_last_error(gs_ctx* ctx);
+
+/* kd-tree of the last call made with keep_trace = 1 (section 6, Figure 5).
+ * which: 0 = reference tree, 1 = query tree (the same tree when monochromatic).
+ * All pointers are host pointers and may be NULL to skip a field; first call
+ * with everything NULL to read *n_nodes and *n_points.
+ *   perm[n_points]   original point index at each tree position
+ *   begin/count/left[n_nodes]  point range and left child (-1 for a leaf; the
+ *                    right child is left+1); nodes are numbered breadth first
+ *   lo/hi/ctr[n_nodes][D], rinf/W/wmin[n_nodes] as defined in the tree builder */
+gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_points,
+                      int32_t* perm, int32_t* begin, int32_t* count, int32_t* left,
+                      double* lo, double* hi, double* ctr, double* rinf, double* W,
+                      double* wmin);
+
+/* Decision trace of the last call made with keep_trace = 1: one record per
+ * decided node pair, int32 [n][6] = (bandwidth index, level, Q node, R node,
+ * code, order p) with code 0 FD, 1 DH, 2 DL, 3 H2L, 4 base case, 5 split
+ * (Figure 7).  records may be NULL to read *n_records first. */
+gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records);
+
+/* Multi-index set of the O(D^p) expansions (section 2): every alpha with
+ * |alpha| < p, ordered by degree and, inside a degree, in decreasing
+ * lexicographic order (for D = 2, p = 2: (0,0), (1,0), (0,1)).  Writes
+ * *n_terms = C(D+p-1, D) and, if alpha is not NULL, alpha[n_terms][D] (host
+ * pointer).  GS_EINVAL unless 1 <= D <= 64 and 1 <= p <= 10. */
+gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAUSSSUM_H */

@@ -116,15 +116,18 @@ def _pow_int(D, e):
     return v
 
 
-def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R):
+def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7):
     """Figure 6.  Smallest feasible order per method, cost model
     c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1},
     c_Direct = D N_Q N_R, first minimum in the order DH, DL, H2L, DIRECT.
-    Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
+    `mask` restricts the candidate methods (bit 0 DH, 1 DL, 2 H2L) for
+    ablations.  Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
     found = {}
-    for name, fn in (("DH", lambda p: e_dh(W_R, g, D, p, r_R)),
-                     ("DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
-                     ("H2L", lambda p: e_h2l(W_R, g, D, p, r_Q, r_R))):
+    for bit, name, fn in ((1, "DH", lambda p: e_dh(W_R, g, D, p, r_R)),
+                          (2, "DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
+                          (4, "H2L", lambda p: e_h2l(W_R, g, D, p, r_Q, r_R))):
+        if not mask & bit:
+            continue
         for p in range(1, plimit + 1):
             E = fn(p)
             if E <= maxerr:

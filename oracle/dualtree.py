@@ -75,7 +75,7 @@ class Result:
 
 
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
-             method="dito", mono=None, trace=False):
+             method="dito", mono=None, trace=False, fmm_mask=7):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
     decision trace: a list of (h_index, level, Q, R, code, p) tuples."""
     xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
@@ -98,6 +98,7 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.G = np.zeros((len(hs), xq.shape[0]))
     res.trace = [] if trace else None
     res.counts = np.zeros((len(hs), 6), dtype=np.int64)
+    res.fmm_mask = fmm_mask
     for k, h in enumerate(hs):
         res.G[k] = _one_bandwidth(k, float(h), qt, rt, xq, mono, P, eps_alg, method, res)
     return res
@@ -150,7 +151,8 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                     g = exp64(-dmin2 * inv_4h2)
                     name, p, E = best_method(D, P, maxerr, WR, g, float(qt.rinf[Q]) * inv_h,
                                              float(rt.rinf[R]) * inv_h,
-                                             int(qt.count[Q]), int(rt.count[R]))
+                                             int(qt.count[Q]), int(rt.count[R]),
+                                             mask=res.fmm_mask)
                     if name != "DIRECT":
                         if use_tokens:
                             t = t - need(E, WR, L, Wtot, eps_alg)

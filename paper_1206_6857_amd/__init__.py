@@ -1,1 +1,190 @@
-"""MI355X (gfx950) Gaussian summation library: Python binding package."""
+"""MI355X (gfx950) multi-bandwidth Gaussian summation (Lee & Gray, "Faster
+Gaussian Summation: Theory and Experiment").
+
+Python binding of the C ABI in include/gausssum.h.  The functions here only
+marshal arguments: all arithmetic runs in the HIP library libgausssum.so.
+Arrays may be NumPy arrays (host) or torch tensors (host or device); torch is
+used only for device memory and streams.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GS_DFD, GS_DFDO, GS_DUALTREE, GS_EXHAUSTIVE, GS_LEARNED, GS_RULE,  # noqa: F401
+                   GsOptions, GsStats)
+
+
+class GaussSumError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_lib.STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def gs_default_options():
+    opt = GsOptions()
+    _lib.load().gs_default_options(ctypes.byref(opt))
+    return opt
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class _Arr:
+    """Pointer to a contiguous float64 buffer (NumPy or torch), kept alive."""
+
+    def __init__(self, x, writable=False):
+        if _is_torch(x):
+            import torch
+            if x.dtype != torch.float64:
+                raise TypeError("tensors must be float64")
+            if not x.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+            self.obj, self.ptr, self.is_cuda = x, x.data_ptr(), x.is_cuda
+        else:
+            a = np.asarray(x)
+            if writable:
+                if a.dtype != np.float64 or not a.flags.c_contiguous:
+                    raise TypeError("output arrays must be C-contiguous float64")
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+            self.obj, self.ptr, self.is_cuda = a, a.ctypes.data, False
+        self.shape = tuple(x.shape)
+
+
+class Context:
+    """Owns a gs_ctx: device workspace and a HIP stream (gs_create/gs_destroy)."""
+
+    def __init__(self, device=0, stream=None):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        st = lib.gs_create(ctypes.byref(h), int(device), stream)
+        if st != 0:
+            raise GaussSumError(st, "gs_create failed on device %d" % device)
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return _lib.load().gs_last_error(self._h).decode()
+
+    def _check(self, st):
+        if st != 0:
+            raise GaussSumError(st, self.last_error())
+
+    def gauss_sum(self, queries, refs, weights, bandwidths, eps, out=None, **opts):
+        """G[n_h][M] = sum_r w_r exp(-|q - r|^2 / 2h^2) to relative error eps.
+        queries may be the same object as refs (monochromatic).  Options:
+        method ('dualtree', 'exhaustive', 'dfd', 'dfdo'), policy ('rule',
+        'learned'), leaf_size, plimit, monochromatic, eps_round_share,
+        keep_trace, log_pairs, blocking."""
+        lib = _lib.load()
+        same = queries is refs
+        r = _Arr(refs)
+        q = r if same else _Arr(queries)
+        w = _Arr(weights)
+        hsrc = bandwidths
+        if not _is_torch(hsrc):
+            hsrc = np.atleast_1d(np.asarray(hsrc, dtype=np.float64))
+        hb = _Arr(hsrc)
+        if len(r.shape) != 2 or len(q.shape) != 2:
+            raise ValueError("queries and refs must be 2-D [n][D]")
+        M, D = q.shape
+        N = r.shape[0]
+        n_h = int(np.prod(hb.shape)) if hb.shape else 1
+        if out is None:
+            if q.is_cuda or r.is_cuda:
+                import torch
+                out = torch.empty((n_h, M), dtype=torch.float64, device=(q.obj if q.is_cuda else r.obj).device)
+            else:
+                out = np.empty((n_h, M), dtype=np.float64)
+        o = _Arr(out, writable=True)
+        opt = gs_default_options()
+        for k, v in opts.items():
+            if k == "method":
+                v = _lib.METHODS[v] if isinstance(v, str) else int(v)
+            elif k == "policy":
+                v = _lib.POLICIES[v] if isinstance(v, str) else int(v)
+            if not hasattr(opt, k):
+                raise TypeError("unknown option %r" % k)
+            setattr(opt, k, v)
+        if any(a.is_cuda for a in (q, r, w, hb, o)):
+            import torch
+            torch.cuda.current_stream().synchronize()
+        st = lib.gauss_sum(self._h, q.ptr, M, r.ptr, w.ptr, N, D, hb.ptr, n_h, float(eps), o.ptr,
+                           ctypes.byref(opt))
+        self._check(st)
+        return out
+
+    def stats(self):
+        s = GsStats()
+        s.struct_size = ctypes.sizeof(GsStats)
+        self._check(_lib.load().gs_get_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def pair_counts(self, n_h):
+        out = np.zeros((n_h, 6), dtype=np.int64)
+        self._check(_lib.load().gs_get_pair_counts(self._h, out.ctypes.data))
+        return out
+
+    def get_tree(self, which, D):
+        """Tree arrays of the last call made with keep_trace=1 (gs_get_tree)."""
+        lib = _lib.load()
+        nn, npnt = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt), *([None] * 10)))
+        n, p = nn.value, npnt.value
+        t = {"perm": np.zeros(p, np.int32), "begin": np.zeros(n, np.int32),
+             "count": np.zeros(n, np.int32), "left": np.zeros(n, np.int32),
+             "lo": np.zeros((n, D)), "hi": np.zeros((n, D)), "ctr": np.zeros((n, D)),
+             "rinf": np.zeros(n), "W": np.zeros(n), "wmin": np.zeros(n)}
+        order = ["perm", "begin", "count", "left", "lo", "hi", "ctr", "rinf", "W", "wmin"]
+        self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt),
+                                    *[t[k].ctypes.data for k in order]))
+        return t
+
+    def get_trace(self):
+        """Decision records (h, level, Q, R, code, p) of the last keep_trace call."""
+        lib = _lib.load()
+        n = ctypes.c_int64()
+        self._check(lib.gs_get_trace(self._h, ctypes.byref(n), None))
+        rec = np.zeros((n.value, 6), dtype=np.int32)
+        self._check(lib.gs_get_trace(self._h, ctypes.byref(n), rec.ctypes.data))
+        return rec
+
+
+def gs_multi_indices(D, p):
+    """Library's multi-index set with |alpha| < p (host-side table; no GPU)."""
+    lib = _lib.load()
+    n = ctypes.c_int64()
+    st = lib.gs_multi_indices(int(D), int(p), ctypes.byref(n), None)
+    if st != 0:
+        raise GaussSumError(st, "invalid D or p")
+    out = np.zeros((n.value, D), dtype=np.int32)
+    lib.gs_multi_indices(int(D), int(p), ctypes.byref(n), out.ctypes.data)
+    return out
+
+
+_default = {}
+
+
+def default_context(device=0):
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def gauss_sum(queries, refs, weights, bandwidths, eps, out=None, device=0, **opts):
+    """Module-level gauss_sum on a per-device default context."""
+    return default_context(device).gauss_sum(queries, refs, weights, bandwidths, eps, out=out, **opts)

@@ -1,0 +1,84 @@
+"""ctypes binding of libgausssum.so (include/gausssum.h).
+
+Argument marshalling only: every computation runs in the HIP library.  If the
+library has not been built, loading fails loudly; there is no fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgausssum.so")
+
+GS_OK, GS_EINVAL, GS_ENOMEM, GS_EDEVICE, GS_EOVERFLOW, GS_EINTERNAL = 0, -1, -2, -3, -4, -5
+GS_DUALTREE, GS_EXHAUSTIVE, GS_DFD, GS_DFDO = 0, 1, 2, 3
+GS_RULE, GS_LEARNED = 0, 1
+METHODS = {"dualtree": GS_DUALTREE, "dito": GS_DUALTREE, "exhaustive": GS_EXHAUSTIVE,
+           "dfd": GS_DFD, "dfdo": GS_DFDO}
+POLICIES = {"rule": GS_RULE, "learned": GS_LEARNED}
+STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_EDEVICE",
+                -4: "GS_EOVERFLOW", -5: "GS_EINTERNAL"}
+
+# Every function the header declares; tests check that the library exports them.
+EXPORTED = ["gs_default_options", "gs_create", "gs_destroy", "gauss_sum", "gs_get_stats",
+            "gs_get_pair_counts", "gs_last_error", "gs_get_tree", "gs_get_trace",
+            "gs_multi_indices"]
+
+
+class GsOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("plimit", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("policy", ctypes.c_int32), ("monochromatic", ctypes.c_int32),
+                ("blocking", ctypes.c_int32), ("keep_trace", ctypes.c_int32),
+                ("log_pairs", ctypes.c_int32), ("fmm_mask", ctypes.c_int32),
+                ("eps_round_share", ctypes.c_double)]
+
+
+class GsStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("n_h", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("plimit", ctypes.c_int32),
+                ("pairs", ctypes.c_int64 * 6), ("base_pair_evals", ctypes.c_int64),
+                ("frontier_peak", ctypes.c_int64), ("policy_calls", ctypes.c_int64),
+                ("policy_fallbacks", ctypes.c_int64),
+                ("t_stage_ms", ctypes.c_double), ("t_tree_ms", ctypes.c_double),
+                ("t_moments_ms", ctypes.c_double), ("t_traverse_ms", ctypes.c_double),
+                ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgausssum.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgausssum.so is not built (run __graft_entry__.build()); "
+                           "there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.gs_default_options.argtypes = [ctypes.POINTER(GsOptions)]
+    lib.gs_default_options.restype = None
+    lib.gs_create.argtypes = [ctypes.POINTER(P), i32, P]
+    lib.gs_create.restype = i32
+    lib.gs_destroy.argtypes = [P]
+    lib.gs_destroy.restype = i32
+    lib.gauss_sum.argtypes = [P, P, i64, P, P, i64, i32, P, i32, f64, P, ctypes.POINTER(GsOptions)]
+    lib.gauss_sum.restype = i32
+    lib.gs_get_stats.argtypes = [P, ctypes.POINTER(GsStats)]
+    lib.gs_get_stats.restype = i32
+    lib.gs_get_pair_counts.argtypes = [P, P]
+    lib.gs_get_pair_counts.restype = i32
+    lib.gs_last_error.argtypes = [P]
+    lib.gs_last_error.restype = ctypes.c_char_p
+    lib.gs_get_tree.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)] + [P] * 10
+    lib.gs_get_tree.restype = i32
+    lib.gs_get_trace.argtypes = [P, ctypes.POINTER(i64), P]
+    lib.gs_get_trace.restype = i32
+    lib.gs_multi_indices.argtypes = [i32, i32, ctypes.POINTER(i64), P]
+    lib.gs_multi_indices.restype = i32
+    _lib = lib
+    return lib

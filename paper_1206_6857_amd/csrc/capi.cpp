@@ -1,0 +1,343 @@
+// C ABI entry points: argument validation, staging of caller buffers, device
+// workspace, and orchestration of the kernels of the other translation units.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gausssum.h"
+#include "gs_internal.h"
+#include "gs_host.h"
+
+using namespace gs;
+
+// ------------------------------------------------------------------ helpers
+
+namespace gs {
+
+void* Workspace::get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hipError_t* err) {
+  Buf& b = bufs[name];
+  if (bytes == 0) bytes = 16;
+  if (b.cap < bytes) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    size_t cap = std::max(bytes, b.cap + b.cap / 2);
+    hipError_t e = hipMalloc(&b.p, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      b.cap = 0;
+      *err = e;
+      return nullptr;
+    }
+    b.cap = cap;
+  }
+  (void)ctx;
+  return b.p;
+}
+
+void Workspace::release_all() {
+  for (auto& kv : bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  bufs.clear();
+}
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace gs
+
+struct gs_ctx : gs::gs_ctx_base {};
+
+#define GS_FAIL(ctx, code, msg)    \
+  do {                             \
+    (ctx)->err = (msg);            \
+    return (code);                 \
+  } while (0)
+
+#define GS_HIP(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t _e = (call);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
+      (ctx)->err = std::string("HIP error in ") + #call + ": " + hipGetErrorString(_e); \
+      return _e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EDEVICE;                      \
+    }                                                                                 \
+  } while (0)
+
+template <class T>
+static T* wsget(gs_ctx* ctx, const char* name, size_t count, gs_status* st) {
+  hipError_t e = hipSuccess;
+  void* p = ctx->ws.get(name, count * sizeof(T), ctx, &e);
+  if (!p) {
+    ctx->err = std::string("device allocation failed for workspace '") + name + "' (" +
+               std::to_string(count * sizeof(T)) + " bytes): " + hipGetErrorString(e);
+    *st = GS_ENOMEM;
+  }
+  return static_cast<T*>(p);
+}
+
+#define WS(T, name, count)                          \
+  ({                                                \
+    gs_status _st = GS_OK;                          \
+    T* _p = wsget<T>(ctx, name, (size_t)(count), &_st); \
+    if (!_p) return _st;                            \
+    _p;                                             \
+  })
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+void gs_default_options(gs_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = (int32_t)sizeof(gs_options);
+  opt->leaf_size = 64;
+  opt->plimit = 0;
+  opt->method = GS_DUALTREE;
+  opt->policy = GS_RULE;
+  opt->monochromatic = -1;
+  opt->blocking = 1;
+  opt->keep_trace = 0;
+  opt->log_pairs = 0;
+  opt->eps_round_share = 0.1;
+}
+
+gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return GS_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return GS_EDEVICE;
+  }
+  gs_ctx* ctx = new (std::nothrow) gs_ctx();
+  if (!ctx) return GS_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return GS_EDEVICE;
+  }
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->own_stream = false;
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return GS_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  *out = ctx;
+  return GS_OK;
+}
+
+gs_status gs_destroy(gs_ctx* ctx) {
+  if (!ctx) return GS_OK;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  ctx->ws.release_all();
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return GS_OK;
+}
+
+const char* gs_last_error(gs_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+gs_status gs_get_stats(gs_ctx* ctx, gs_stats* out) {
+  if (!ctx || !out) return GS_EINVAL;
+  if (out->struct_size < (int32_t)sizeof(gs_stats)) GS_FAIL(ctx, GS_EINVAL, "gs_stats.struct_size too small");
+  *out = ctx->stats;
+  out->struct_size = (int32_t)sizeof(gs_stats);
+  return GS_OK;
+}
+
+gs_status gs_get_pair_counts(gs_ctx* ctx, int64_t* counts) {
+  if (!ctx || !counts) return GS_EINVAL;
+  std::copy(ctx->pair_counts.begin(), ctx->pair_counts.end(), counts);
+  return GS_OK;
+}
+
+gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_points,
+                      int32_t* perm, int32_t* begin, int32_t* count, int32_t* left, double* lo,
+                      double* hi, double* ctr, double* rinf, double* W, double* wmin) {
+  if (!ctx || which < 0 || which > 1) return GS_EINVAL;
+  const HostTree& t = ctx->host_tree[which];
+  if (!t.valid) GS_FAIL(ctx, GS_EINVAL, "no tree kept: call gauss_sum with keep_trace = 1 first");
+  if (n_nodes) *n_nodes = t.n_nodes;
+  if (n_points) *n_points = t.n_points;
+  auto cp = [](auto* dst, const auto& v) {
+    if (dst) std::copy(v.begin(), v.end(), dst);
+  };
+  cp(perm, t.perm);
+  cp(begin, t.begin);
+  cp(count, t.count);
+  cp(left, t.left);
+  cp(lo, t.lo);
+  cp(hi, t.hi);
+  cp(ctr, t.ctr);
+  cp(rinf, t.rinf);
+  cp(W, t.W);
+  cp(wmin, t.wmin);
+  return GS_OK;
+}
+
+gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha) {
+  if (D < 1 || D > kMaxD || p < 1 || p > kMaxPlimit || !n_terms) return GS_EINVAL;
+  auto mis = multi_indices(D, p);
+  *n_terms = (int64_t)mis.size();
+  if (alpha)
+    for (size_t i = 0; i < mis.size(); ++i)
+      for (int d = 0; d < D; ++d) alpha[i * D + d] = mis[i][d];
+  return GS_OK;
+}
+
+gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records) {
+  if (!ctx || !n_records) return GS_EINVAL;
+  *n_records = (int64_t)(ctx->trace.size() / 6);
+  if (records) std::copy(ctx->trace.begin(), ctx->trace.end(), records);
+  return GS_OK;
+}
+
+gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double* refs,
+                    const double* weights, int64_t N, int32_t D, const double* bandwidths,
+                    int32_t n_h, double eps, double* G_out, const gs_options* opt_in) {
+  if (!ctx) return GS_EINVAL;
+  ctx->err.clear();
+  gs_options opt;
+  gs_default_options(&opt);
+  if (opt_in) {
+    if (opt_in->struct_size != (int32_t)sizeof(gs_options))
+      GS_FAIL(ctx, GS_EINVAL, "gs_options.struct_size does not match this library");
+    opt = *opt_in;
+  }
+  if (!queries || !refs || !weights || !bandwidths || !G_out)
+    GS_FAIL(ctx, GS_EINVAL, "null array pointer");
+  if (M < 1 || N < 1 || n_h < 1) GS_FAIL(ctx, GS_EINVAL, "M, N and n_h must be >= 1");
+  if (D < 1 || D > kMaxD) GS_FAIL(ctx, GS_EINVAL, "D must be in [1, 64]");
+  if (M > INT32_MAX / 2 || N > INT32_MAX / 2) GS_FAIL(ctx, GS_EOVERFLOW, "M and N must be < 2^30");
+  if (n_h > 4096) GS_FAIL(ctx, GS_EINVAL, "at most 4096 bandwidths per call");
+  if (opt.method < GS_DUALTREE || opt.method > GS_DFDO) GS_FAIL(ctx, GS_EINVAL, "unknown method");
+  if (opt.method != GS_EXHAUSTIVE && !(eps > 0.0 && eps < 1.0))
+    GS_FAIL(ctx, GS_EINVAL, "eps must be in (0, 1)");
+  if (opt.leaf_size < 1 || opt.leaf_size > 1024) GS_FAIL(ctx, GS_EINVAL, "leaf_size must be in [1, 1024]");
+  if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
+    GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");
+  if (opt.policy != GS_RULE && opt.policy != GS_LEARNED) GS_FAIL(ctx, GS_EINVAL, "unknown policy");
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  const double t_start = now_ms();
+  hipStream_t st = ctx->stream;
+
+  // Bandwidths on the host.
+  std::vector<double> hs(n_h);
+  if (is_device_pointer(bandwidths)) {
+    GS_HIP(ctx, hipMemcpyAsync(hs.data(), bandwidths, n_h * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_HIP(ctx, hipStreamSynchronize(st));
+  } else {
+    std::copy(bandwidths, bandwidths + n_h, hs.begin());
+  }
+  for (double h : hs)
+    if (!(h > 0.0) || !std::isfinite(h)) GS_FAIL(ctx, GS_EINVAL, "every bandwidth must be finite and > 0");
+
+  const bool mono = opt.monochromatic == 1 || (opt.monochromatic == -1 && queries == refs && M == N);
+  if (mono && M != N) GS_FAIL(ctx, GS_EINVAL, "monochromatic requires M == N");
+
+  // Stage inputs on the device (validated, -0.0 canonicalised).
+  int* bad = WS(int, "bad_flag", 1);
+  GS_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), st));
+  auto stage = [&](const double* src, int64_t n, const char* raw_name, const char* soa_name,
+                   const char* aos_name, double** soa, double** aos) -> gs_status {
+    const double* dsrc = src;
+    if (!is_device_pointer(src)) {
+      double* raw = WS(double, raw_name, n * D);
+      GS_HIP(ctx, hipMemcpyAsync(raw, src, n * D * sizeof(double), hipMemcpyHostToDevice, st));
+      dsrc = raw;
+    }
+    *soa = WS(double, soa_name, n * D);
+    *aos = WS(double, aos_name, n * D);
+    GS_HIP(ctx, launch_stage_points(dsrc, n, D, *soa, *aos, bad, st));
+    return GS_OK;
+  };
+  DeviceInputs in;
+  in.M = M;
+  in.N = N;
+  in.D = D;
+  in.mono = mono;
+  gs_status s = stage(refs, N, "raw_r", "r_soa", "r_aos", &in.r_soa, &in.r_aos);
+  if (s != GS_OK) return s;
+  if (mono) {
+    in.q_soa = in.r_soa;
+    in.q_aos = in.r_aos;
+  } else {
+    s = stage(queries, M, "raw_q", "q_soa", "q_aos", &in.q_soa, &in.q_aos);
+    if (s != GS_OK) return s;
+  }
+  in.w = WS(double, "w", N);
+  if (is_device_pointer(weights))
+    GS_HIP(ctx, hipMemcpyAsync(in.w, weights, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    GS_HIP(ctx, hipMemcpyAsync(in.w, weights, N * sizeof(double), hipMemcpyHostToDevice, st));
+  GS_HIP(ctx, launch_check_positive(in.w, N, bad, st));
+  int bad_h = 0;
+  GS_HIP(ctx, hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  GS_HIP(ctx, hipStreamSynchronize(st));
+  if (bad_h & 1) GS_FAIL(ctx, GS_EINVAL, "a coordinate is NaN or infinite");
+  if (bad_h & 2) GS_FAIL(ctx, GS_EINVAL, "every weight must be finite and > 0");
+  const double t_staged = now_ms();
+
+  // Output buffer.
+  const bool out_dev = is_device_pointer(G_out);
+  double* Gd = out_dev ? G_out : WS(double, "G_tmp", (int64_t)n_h * M);
+
+  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  ctx->stats.struct_size = sizeof(gs_stats);
+  ctx->stats.n_h = n_h;
+  ctx->stats.t_stage_ms = t_staged - t_start;
+  ctx->pair_counts.assign((size_t)n_h * 6, 0);
+  ctx->trace.clear();
+  ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
+
+  if (opt.method == GS_EXHAUSTIVE) {
+    float* rec = WS(float, "ex_rec", N * exhaustive_record_stride(D));
+    unsigned long long* wb = WS(unsigned long long, "wmax_bits", 1);
+    GS_HIP(ctx, launch_exhaustive_records(in.r_aos, in.w, N, D, rec, wb, st));
+    double* partial = WS(double, "ex_partial", exhaustive_partial_elems(M, N, n_h));
+    GS_HIP(ctx, launch_exhaustive(in.q_aos, M, rec, N, D, hs.data(), n_h, wb, partial, Gd, st));
+  } else {
+    s = run_dualtree(ctx, in, hs, eps, opt, Gd);
+    if (s != GS_OK) return s;
+  }
+  if (!out_dev) {
+    GS_HIP(ctx, hipMemcpyAsync(G_out, Gd, (size_t)n_h * M * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_HIP(ctx, hipStreamSynchronize(st));
+  } else if (opt.blocking) {
+    GS_HIP(ctx, hipStreamSynchronize(st));
+  }
+  ctx->stats.t_total_ms = now_ms() - t_start;
+  return GS_OK;
+}
+
+}  // extern "C"

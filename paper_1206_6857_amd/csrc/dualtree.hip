@@ -1,0 +1,666 @@
+// Orchestration of the dual-tree summation (sections 5-6): trees, moments,
+// level-synchronous traversal, work lists, post-pass.
+//
+//   1. kd-trees of references (and of queries unless monochromatic)
+//   2. raw Hermite moments to PLIMIT: leaves from points, H2H upward (Fig. 5)
+//   3. traversal, one frontier level per iteration, all bandwidths at once:
+//      decide (token rule) -> scan of per-segment counts -> emit (Figure 7)
+//   4. the recorded work: DL then H2L into local coefficients, DH into
+//      per-query sums, base cases into per-query sums
+//   5. post-pass: Gest and L2L down the query tree, EVALL at the leaves
+//      (Figure 8), results scattered to the caller's query order.
+// The host reads back only the per-level totals it needs to size buffers.
+#include <cstring>  // rocprim uses memset without including it
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gs_host.h"
+#include "gs_internal.h"
+#include "gs_series.h"
+#include "gs_traverse.h"
+#include "gs_tree.h"
+
+namespace gs {
+
+namespace {
+
+#define DT_FAIL(code, msg) \
+  do {                     \
+    ctx->err = (msg);      \
+    return (code);         \
+  } while (0)
+
+#define DT_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (call);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
+      ctx->err = std::string("HIP error in ") + #call + ": " + hipGetErrorString(_e); \
+      return _e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EDEVICE;                      \
+    }                                                                                 \
+  } while (0)
+
+template <class T>
+T* buf(gs_ctx_base* ctx, const std::string& name, size_t count, gs_status* st) {
+  hipError_t e = hipSuccess;
+  void* p = ctx->ws.get(name, count * sizeof(T), ctx, &e);
+  if (!p) {
+    ctx->err = "device allocation failed for workspace '" + name + "' (" +
+               std::to_string(count * sizeof(T)) + " bytes)";
+    *st = GS_ENOMEM;
+  }
+  return static_cast<T*>(p);
+}
+
+// Grow a named buffer to hold `need` elements, keeping its first `used`.
+template <class T>
+T* grow(gs_ctx_base* ctx, const std::string& name, size_t used, size_t need, hipStream_t s,
+        gs_status* st) {
+  Buf& b = ctx->ws.bufs[name];
+  const size_t bytes = std::max<size_t>(need, 1) * sizeof(T);
+  if (b.cap >= bytes) return static_cast<T*>(b.p);
+  size_t cap = std::max(bytes, b.cap * 2);
+  void* np = nullptr;
+  if (hipMalloc(&np, cap) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = "device allocation failed while growing '" + name + "'";
+    *st = GS_ENOMEM;
+    return nullptr;
+  }
+  if (b.p && used)
+    (void)hipMemcpyAsync(np, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, s);
+  if (b.p) {
+    (void)hipStreamSynchronize(s);
+    hipFree(b.p);
+  }
+  b.p = np;
+  b.cap = cap;
+  return static_cast<T*>(np);
+}
+
+#define BUF(T, name, count)                                   \
+  ({                                                          \
+    gs_status _st = GS_OK;                                    \
+    T* _p = buf<T>(ctx, std::string(name), (size_t)(count), &_st); \
+    if (!_p) return _st;                                      \
+    _p;                                                       \
+  })
+
+#define GROW(T, name, used, need)                                          \
+  ({                                                                       \
+    gs_status _st = GS_OK;                                                 \
+    T* _p = grow<T>(ctx, std::string(name), (size_t)(used), (size_t)(need), st, &_st); \
+    if (!_p) return _st;                                                   \
+    _p;                                                                    \
+  })
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------ host tables
+
+int plimit_table(int D) {
+  switch (D) {
+    case 1: return 10;
+    case 2: return 8;
+    case 3: return 6;
+    case 4: return 5;
+    case 5: return 4;
+    case 6: return 2;
+    default: return 1;
+  }
+}
+
+uint64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  if (k > n - k) k = n - k;
+  uint64_t c = 1;
+  for (int i = 1; i <= k; ++i) c = c * (uint64_t)(n - k + i) / (uint64_t)i;
+  return c;
+}
+
+uint64_t fact(int n) {
+  uint64_t f = 1;
+  for (int i = 2; i <= n; ++i) f *= (uint64_t)i;
+  return f;
+}
+
+// C(D+p-1, D-1) / sqrt((floor(p/D)!)^{D-p'} (ceil(p/D)!)^{p'}), p' = p mod D (Lemma 4).
+double bound_const(int D, int p) {
+  const int q = p / D, pp = p % D;
+  const int cq = pp ? q + 1 : q;
+  uint64_t F = 1;
+  for (int i = 0; i < D - pp; ++i) F *= fact(q);
+  for (int i = 0; i < pp; ++i) F *= fact(cq);
+  return (double)binom(D + p - 1, D - 1) / std::sqrt((double)F);
+}
+
+void degree_block(int D, int deg, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+  if (D == 1) {
+    cur.push_back(deg);
+    out.push_back(cur);
+    cur.pop_back();
+    return;
+  }
+  for (int first = deg; first >= 0; --first) {
+    cur.push_back(first);
+    degree_block(D - 1, deg - first, cur, out);
+    cur.pop_back();
+  }
+}
+
+}  // namespace
+
+std::vector<std::vector<int>> multi_indices(int D, int p) {
+  std::vector<std::vector<int>> out;
+  std::vector<int> cur;
+  for (int deg = 0; deg < p; ++deg) degree_block(D, deg, cur, out);
+  return out;
+}
+
+namespace {
+
+struct HostSeries {
+  std::vector<int8_t> alpha;
+  std::vector<int32_t> deg, nterms, h2h_start, l2l_start;
+  std::vector<double> inv_fact, l2l_coef;
+  std::vector<int2> h2h_pairs, l2l_pairs;
+  int C = 0;
+};
+
+HostSeries make_series_tables(int D, int P) {
+  HostSeries T;
+  auto mis = multi_indices(D, P);
+  T.C = (int)mis.size();
+  std::vector<uint64_t> afact(T.C);
+  for (int i = 0; i < T.C; ++i) {
+    int dg = 0;
+    uint64_t f = 1;
+    for (int d = 0; d < D; ++d) {
+      T.alpha.push_back((int8_t)mis[i][d]);
+      dg += mis[i][d];
+      f *= fact(mis[i][d]);
+    }
+    T.deg.push_back(dg);
+    afact[i] = f;
+    T.inv_fact.push_back(1.0 / (double)f);
+  }
+  for (int p = 0; p <= P; ++p) T.nterms.push_back((int32_t)binom(D + p - 1, D));
+  auto index_of = [&](const std::vector<int>& a) {
+    for (int i = 0; i < T.C; ++i)
+      if (mis[i] == a) return i;
+    return -1;
+  };
+  T.h2h_start.push_back(0);
+  for (int g = 0; g < T.C; ++g) {
+    for (int a = 0; a < T.C; ++a) {
+      bool le = true;
+      std::vector<int> diff(D);
+      for (int d = 0; d < D; ++d) {
+        if (mis[a][d] > mis[g][d]) le = false;
+        diff[d] = mis[g][d] - mis[a][d];
+      }
+      if (le) T.h2h_pairs.push_back(make_int2(a, index_of(diff)));
+    }
+    T.h2h_start.push_back((int32_t)T.h2h_pairs.size());
+  }
+  T.l2l_start.push_back(0);
+  for (int a = 0; a < T.C; ++a) {
+    for (int b = 0; b < T.C; ++b) {
+      bool ge = true;
+      std::vector<int> diff(D);
+      uint64_t df = 1;
+      for (int d = 0; d < D; ++d) {
+        if (mis[b][d] < mis[a][d]) ge = false;
+        diff[d] = mis[b][d] - mis[a][d];
+      }
+      if (!ge) continue;
+      for (int d = 0; d < D; ++d) df *= fact(diff[d]);
+      T.l2l_pairs.push_back(make_int2(b, index_of(diff)));
+      T.l2l_coef.push_back((double)afact[b] / ((double)afact[a] * (double)df));
+    }
+    T.l2l_start.push_back((int32_t)T.l2l_pairs.size());
+  }
+  return T;
+}
+
+__global__ void init_level0_kernel(int n_h, FrontierLevel f) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_h) return;
+  f.h[k] = k;
+  f.Q[k] = 0;
+  f.off[k] = k;
+  f.len[k] = 1;
+  f.T[k] = 0.0;
+  f.Lp[k] = 0.0;
+  f.R[k] = 0;
+}
+
+__global__ void group_keys_kernel(int n, const int4* __restrict__ grp, int nQ,
+                                  unsigned long long* __restrict__ key, int32_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = (unsigned long long)grp[i].x * (unsigned long long)nQ + (unsigned long long)grp[i].y;
+  idx[i] = i;
+}
+
+template <class T>
+hipError_t upload(const std::vector<T>& v, T* dst, hipStream_t s) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+// Builds one tree into workspace buffers prefixed by `pre`.
+static gs_status build_tree(gs_ctx_base* ctx, const char* pre, const double* xs, const double* w,
+                            int64_t n, int D, int leaf_size, DevTree& t, hipStream_t st) {
+  const std::string P(pre);
+  const int64_t cap = tree_node_capacity(n, leaf_size);
+  t.capacity = cap;
+  t.begin = BUF(int32_t, P + "begin", cap);
+  t.count = BUF(int32_t, P + "count", cap);
+  t.left = BUF(int32_t, P + "left", cap);
+  t.depth = BUF(int32_t, P + "depth", cap);
+  t.perm = BUF(int32_t, P + "perm", n);
+  t.leaf_of_pos = BUF(int32_t, P + "leafpos", n);
+  t.lo = BUF(double, P + "lo", cap * D);
+  t.hi = BUF(double, P + "hi", cap * D);
+  t.ctr = BUF(double, P + "ctr", cap * D);
+  t.rinf = BUF(double, P + "rinf", cap);
+  t.W = BUF(double, P + "W", cap);
+  t.wmin = BUF(double, P + "wmin", cap);
+  TreeBuildArgs a;
+  a.n = n;
+  a.D = D;
+  a.leaf_size = leaf_size;
+  a.xs = xs;
+  a.w = w;
+  a.ids = BUF(int32_t, "tb_ids", n);
+  a.lists = BUF(int32_t, "tb_lists", n * (D + 1));
+  a.lists_alt = BUF(int32_t, "tb_lists_alt", n * (D + 1));
+  a.pos_node = BUF(int32_t, "tb_pos", n);
+  a.pos_node_alt = BUF(int32_t, "tb_pos_alt", n);
+  a.isleft = BUF(int32_t, "tb_isleft", n);
+  a.flags = BUF(int32_t, "tb_flags", n * (D + 1));
+  a.scan = BUF(int32_t, "tb_scan", n * (D + 1));
+  a.splitdim = BUF(int32_t, "tb_splitdim", cap);
+  a.n_children = BUF(int32_t, "tb_nchild", 1);
+  a.sort_keys = BUF(double, "tb_sortkeys", n);
+  a.temp_bytes = tree_sort_temp_bytes(n, D);
+  a.temp = BUF(char, "tb_temp", a.temp_bytes);
+  hipError_t e = build_tree_device(a, t, t.level_begin, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->err = std::string("tree build failed: ") + hipGetErrorString(e);
+    return GS_EDEVICE;
+  }
+  return GS_OK;
+}
+
+static gs_status keep_tree(gs_ctx_base* ctx, const DevTree& t, int D, HostTree& h, hipStream_t st) {
+  const int64_t nn = t.n_nodes, np = t.n_points;
+  h.n_nodes = nn;
+  h.n_points = np;
+  h.perm.resize(np);
+  h.begin.resize(nn);
+  h.count.resize(nn);
+  h.left.resize(nn);
+  h.lo.resize(nn * D);
+  h.hi.resize(nn * D);
+  h.ctr.resize(nn * D);
+  h.rinf.resize(nn);
+  h.W.resize(nn);
+  h.wmin.resize(nn);
+  auto cp = [&](auto& v, const auto* src) {
+    return hipMemcpyAsync(v.data(), src, v.size() * sizeof(v[0]), hipMemcpyDeviceToHost, st);
+  };
+  DT_HIP(cp(h.perm, t.perm));
+  DT_HIP(cp(h.begin, t.begin));
+  DT_HIP(cp(h.count, t.count));
+  DT_HIP(cp(h.left, t.left));
+  DT_HIP(cp(h.lo, t.lo));
+  DT_HIP(cp(h.hi, t.hi));
+  DT_HIP(cp(h.ctr, t.ctr));
+  DT_HIP(cp(h.rinf, t.rinf));
+  DT_HIP(cp(h.W, t.W));
+  DT_HIP(cp(h.wmin, t.wmin));
+  DT_HIP(hipStreamSynchronize(st));
+  h.valid = true;
+  return GS_OK;
+}
+
+gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vector<double>& hs,
+                       double eps, const gs_options& opt, double* G_dev) {
+  hipStream_t st = ctx->stream;
+  const int D = in.D;
+  const int64_t N = in.N, Mq = in.M;
+  const int n_h = (int)hs.size();
+  const bool use_fmm = opt.method == GS_DUALTREE;
+  const bool use_tokens = opt.method != GS_DFD;
+  int P = opt.plimit > 0 ? opt.plimit : plimit_table(D);
+  if (P > kMaxPlimit) DT_FAIL(GS_EINVAL, "plimit must be <= 10");
+  if (!use_fmm) P = 1;
+  if ((int64_t)binom(D + P - 1, D) > kMaxTerms || D * P > 64)
+    DT_FAIL(GS_EINVAL, "plimit too large for this dimension (need C(D+p-1,D) <= 286 and D*p <= 64)");
+  gs_stats& S = ctx->stats;
+  S.plimit = P;
+  double t0 = now_ms();
+
+  // 1. Trees.
+  DevTree rt, qt_own;
+  gs_status s = build_tree(ctx, "rt_", in.r_soa, in.w, N, D, opt.leaf_size, rt, st);
+  if (s != GS_OK) return s;
+  DevTree* qtp = &rt;
+  if (!in.mono) {
+    s = build_tree(ctx, "qt_", in.q_soa, nullptr, Mq, D, opt.leaf_size, qt_own, st);
+    if (s != GS_OK) return s;
+    qtp = &qt_own;
+  }
+  DevTree& qt = *qtp;
+  const int nR = (int)rt.n_nodes, nQ = (int)qt.n_nodes;
+  double* xr_perm = BUF(double, "xr_perm", N * D);
+  double* wr_perm = BUF(double, "wr_perm", N);
+  DT_HIP(launch_gather_rows(in.r_aos, rt.perm, N, D, xr_perm, st));
+  DT_HIP(launch_gather(in.w, rt.perm, N, wr_perm, st));
+  double* xq_perm = xr_perm;
+  if (!in.mono) {
+    xq_perm = BUF(double, "xq_perm", Mq * D);
+    DT_HIP(launch_gather_rows(in.q_aos, qt.perm, Mq, D, xq_perm, st));
+  }
+  unsigned long long* wmax_bits = BUF(unsigned long long, "wmax_bits", 1);
+  DT_HIP(launch_max_positive(in.w, N, wmax_bits, st));
+  double Wtot = 0.0;
+  DT_HIP(hipMemcpyAsync(&Wtot, rt.W, sizeof(double), hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  double t1 = now_ms();
+  S.t_tree_ms = t1 - t0;
+
+  // 2. Series tables and moments.
+  HostSeries hsr = make_series_tables(D, P);
+  const int C = hsr.C;
+  SeriesTables T;
+  T.D = D;
+  T.P = P;
+  T.C = C;
+  {
+    int8_t* alpha = BUF(int8_t, "ts_alpha", hsr.alpha.size());
+    int32_t* deg = BUF(int32_t, "ts_deg", hsr.deg.size());
+    double* invf = BUF(double, "ts_invf", hsr.inv_fact.size());
+    int32_t* nterms = BUF(int32_t, "ts_nterms", hsr.nterms.size());
+    int32_t* hs0 = BUF(int32_t, "ts_h2hs", hsr.h2h_start.size());
+    int2* hp = BUF(int2, "ts_h2hp", hsr.h2h_pairs.size());
+    int32_t* ls0 = BUF(int32_t, "ts_l2ls", hsr.l2l_start.size());
+    int2* lp = BUF(int2, "ts_l2lp", hsr.l2l_pairs.size());
+    double* lc = BUF(double, "ts_l2lc", hsr.l2l_coef.size());
+    DT_HIP(upload(hsr.alpha, alpha, st));
+    DT_HIP(upload(hsr.deg, deg, st));
+    DT_HIP(upload(hsr.inv_fact, invf, st));
+    DT_HIP(upload(hsr.nterms, nterms, st));
+    DT_HIP(upload(hsr.h2h_start, hs0, st));
+    DT_HIP(upload(hsr.h2h_pairs, hp, st));
+    DT_HIP(upload(hsr.l2l_start, ls0, st));
+    DT_HIP(upload(hsr.l2l_pairs, lp, st));
+    DT_HIP(upload(hsr.l2l_coef, lc, st));
+    T.alpha = alpha;
+    T.deg = deg;
+    T.inv_fact = invf;
+    T.nterms = nterms;
+    T.h2h_start = hs0;
+    T.h2h_pairs = hp;
+    T.l2l_start = ls0;
+    T.l2l_pairs = lp;
+    T.l2l_coef = lc;
+  }
+  NodeView rv{rt.begin, rt.count, rt.left, rt.ctr, rt.lo, rt.hi};
+  NodeView qv{qt.begin, qt.count, qt.left, qt.ctr, qt.lo, qt.hi};
+  double* Mom = nullptr;
+  if (use_fmm) {
+    Mom = BUF(double, "moments", (int64_t)nR * C);
+    DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, st));
+    for (int lv = (int)rt.level_begin.size() - 2; lv >= 0; --lv)
+      DT_HIP(launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st));
+  }
+  DT_HIP(hipStreamSynchronize(st));
+  double t2 = now_ms();
+  S.t_moments_ms = t2 - t1;
+
+  // Per-bandwidth constants.  The three reciprocals enter pruning decisions
+  // and are formed exactly like this by any reproduction of the decisions.
+  std::vector<double> h_inv2h2(n_h), h_inv4h2(n_h), h_invh(n_h), h_sc(n_h);
+  std::vector<float> h_s2(n_h);
+  for (int k = 0; k < n_h; ++k) {
+    const double h = hs[k];
+    h_inv2h2[k] = 1.0 / (2.0 * h * h);
+    h_inv4h2[k] = 0.5 * h_inv2h2[k];
+    h_invh[k] = 1.0 / h;
+    h_sc[k] = 1.0 / std::sqrt(2.0 * h * h);
+    h_s2[k] = (float)(1.4426950408889634 / (2.0 * h * h));
+  }
+  double* d_inv2h2 = BUF(double, "h_inv2h2", n_h);
+  double* d_inv4h2 = BUF(double, "h_inv4h2", n_h);
+  double* d_invh = BUF(double, "h_invh", n_h);
+  double* d_sc = BUF(double, "h_sc", n_h);
+  float* d_s2 = BUF(float, "h_s2", n_h);
+  DT_HIP(upload(h_inv2h2, d_inv2h2, st));
+  DT_HIP(upload(h_inv4h2, d_inv4h2, st));
+  DT_HIP(upload(h_invh, d_invh, st));
+  DT_HIP(upload(h_sc, d_sc, st));
+  DT_HIP(upload(h_s2, d_s2, st));
+
+  DecideConst dc;
+  std::memset(&dc, 0, sizeof(dc));
+  dc.D = D;
+  dc.P = P;
+  dc.mono = in.mono ? 1 : 0;
+  dc.use_tokens = use_tokens ? 1 : 0;
+  dc.use_fmm = use_fmm ? 1 : 0;
+  dc.Wtot = Wtot;
+  dc.eps_alg = (1.0 - opt.eps_round_share) * eps;
+  dc.fmm_mask = (opt.fmm_mask & 7) ? (opt.fmm_mask & 7) : 7;
+  for (int p = 1; p <= P; ++p) {
+    dc.bconst[p] = bound_const(D, p);
+    dc.binomD[p] = (double)binom(D + p - 1, D);
+  }
+
+  // Per (h, query node) and per (h, query point) state.
+  double* Gest = BUF(double, "Gest", (int64_t)n_h * nQ);
+  int32_t* pL = BUF(int32_t, "pL", (int64_t)n_h * nQ);
+  double* lco = use_fmm ? BUF(double, "lco", (int64_t)n_h * nQ * C) : nullptr;
+  double* gx = BUF(double, "gx", (int64_t)n_h * Mq);
+  double* gdh = BUF(double, "gdh", (int64_t)n_h * Mq);
+  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 1);
+  DT_HIP(hipMemsetAsync(Gest, 0, sizeof(double) * n_h * nQ, st));
+  DT_HIP(hipMemsetAsync(pL, 0, sizeof(int32_t) * n_h * nQ, st));
+  if (lco) DT_HIP(hipMemsetAsync(lco, 0, sizeof(double) * n_h * nQ * C, st));
+  DT_HIP(hipMemsetAsync(gx, 0, sizeof(double) * n_h * Mq, st));
+  DT_HIP(hipMemsetAsync(gdh, 0, sizeof(double) * n_h * Mq, st));
+  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 1), st));
+
+  // 3. Traversal.
+  TreeView qtv{qt.lo, qt.hi, qt.rinf, qt.W, qt.wmin, qt.count, qt.left};
+  TreeView rtv{rt.lo, rt.hi, rt.rinf, rt.W, rt.wmin, rt.count, rt.left};
+  auto level_bufs = [&](int which, int64_t nseg, int64_t npair, FrontierLevel& f) -> gs_status {
+    const std::string p = which ? "f1_" : "f0_";
+    f.h = BUF(int32_t, p + "h", nseg);
+    f.Q = BUF(int32_t, p + "Q", nseg);
+    f.off = BUF(int32_t, p + "off", nseg);
+    f.len = BUF(int32_t, p + "len", nseg);
+    f.T = BUF(double, p + "T", nseg);
+    f.Lp = BUF(double, p + "Lp", nseg);
+    f.R = BUF(int32_t, p + "R", npair);
+    return GS_OK;
+  };
+  FrontierLevel cur, nxt;
+  int64_t nseg = n_h, npair = n_h;
+  s = level_bufs(0, nseg, npair, cur);
+  if (s != GS_OK) return s;
+  hipLaunchKernelGGL(init_level0_kernel, dim3((unsigned)ceil_div(n_h, 64)), dim3(64), 0, st, n_h, cur);
+  DT_HIP(hipGetLastError());
+  WorkLists wl;
+  int64_t used_ent[4] = {0, 0, 0, 0}, used_grp[4] = {0, 0, 0, 0};
+  const char* tname[4] = {"dh", "dl", "h2l", "base"};
+  for (int x = 0; x < 4; ++x) {
+    wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], 0, 1024);
+    wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], 0, 256);
+  }
+  int level = 0;
+  int which = 0;
+  std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
+  int64_t peak = 0;
+  std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
+  std::vector<int8_t> tr_code, tr_p;
+  while (nseg > 0) {
+    peak = std::max(peak, npair);
+    double* s_kmax = BUF(double, "s_kmax", npair);
+    double* s_dmin2 = BUF(double, "s_dmin2", npair);
+    int8_t* code = BUF(int8_t, "p_code", npair);
+    int8_t* pord = BUF(int8_t, "p_ord", npair);
+    SegCount* cnt = BUF(SegCount, "seg_cnt", nseg);
+    SegCount* incl = BUF(SegCount, "seg_incl", nseg);
+    const size_t tb = scan_counts_temp_bytes((int)nseg);
+    void* temp = BUF(char, "scan_temp", tb);
+    DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, s_kmax,
+                         s_dmin2, code, pord, Gest, cnt, hcount, hcount + n_h * 6, nullptr, st));
+    DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
+    SegCount tot;
+    DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    if (opt.keep_trace) {
+      tr_h.resize(nseg);
+      tr_Q.resize(nseg);
+      tr_off.resize(nseg);
+      tr_len.resize(nseg);
+      tr_R.resize(npair);
+      tr_code.resize(npair);
+      tr_p.resize(npair);
+      DT_HIP(hipMemcpyAsync(tr_h.data(), cur.h, nseg * 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_Q.data(), cur.Q, nseg * 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_off.data(), cur.off, nseg * 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_len.data(), cur.len, nseg * 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_R.data(), cur.R, npair * 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_code.data(), code, npair, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(tr_p.data(), pord, npair, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipStreamSynchronize(st));
+      for (int64_t k = 0; k < nseg; ++k)
+        for (int j = 0; j < tr_len[k]; ++j) {
+          const int64_t o = tr_off[k] + j;
+          const int32_t rec[6] = {tr_h[k], level, tr_Q[k], tr_R[o], tr_code[o], tr_p[o]};
+          ctx->trace.insert(ctx->trace.end(), rec, rec + 6);
+        }
+    }
+    dh_level_begin.push_back(used_grp[0]);
+    LevelOffsets lo;
+    for (int x = 0; x < 4; ++x) {
+      wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], used_ent[x], used_ent[x] + tot.v[2 + x]);
+      wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], used_grp[x], used_grp[x] + tot.v[6 + x]);
+      lo.ent[x] = (int32_t)used_ent[x];
+      lo.grp[x] = (int32_t)used_grp[x];
+    }
+    const int64_t nseg2 = tot.v[1], npair2 = tot.v[0];
+    if (used_ent[3] + tot.v[5] > INT32_MAX / 2 || npair2 > INT32_MAX / 2)
+      DT_FAIL(GS_EOVERFLOW, "frontier exceeds 2^30 entries");
+    s = level_bufs(1 - which, nseg2, npair2, nxt);
+    if (s != GS_OK) return s;
+    DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
+    for (int x = 0; x < 4; ++x) {
+      used_ent[x] += tot.v[2 + x];
+      used_grp[x] += tot.v[6 + x];
+    }
+    std::swap(cur, nxt);
+    which = 1 - which;
+    nseg = nseg2;
+    npair = npair2;
+    ++level;
+  }
+  DT_HIP(hipStreamSynchronize(st));
+  double t3 = now_ms();
+  S.t_traverse_ms = t3 - t2;
+  S.levels = level;
+  S.frontier_peak = peak;
+
+  dh_level_begin.push_back(used_grp[0]);
+
+  // 4. Work lists: DL, H2L and base groups sorted by (h, Q) key; DH per level.
+  SortedGroups sg[4];
+  for (int x = 1; x < 4; ++x) {
+    const int n = (int)used_grp[x];
+    sg[x].n = n;
+    sg[x].grp = wl.grp[x];
+    if (n == 0) continue;
+    unsigned long long* key = BUF(unsigned long long, std::string("g_key_") + tname[x], n);
+    unsigned long long* skey = BUF(unsigned long long, std::string("g_skey_") + tname[x], n);
+    int32_t* idx = BUF(int32_t, std::string("g_idx_") + tname[x], n);
+    int32_t* sidx = BUF(int32_t, std::string("g_sidx_") + tname[x], n);
+    hipLaunchKernelGGL(group_keys_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n,
+                       wl.grp[x], nQ, key, idx);
+    size_t bytes = 0;
+    DT_HIP(rocprim::radix_sort_pairs((void*)nullptr, bytes, key, skey, idx, sidx, (unsigned)n, 0, 64, st));
+    void* temp = BUF(char, "g_sort_temp", bytes);
+    DT_HIP(rocprim::radix_sort_pairs(temp, bytes, key, skey, idx, sidx, (unsigned)n, 0, 64, st));
+    sg[x].order = sidx;
+    sg[x].key = skey;
+  }
+  if (use_fmm) {
+    DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+    DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
+    for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
+      const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
+      DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), wl.ent[0], qv, rv, xq_perm, Mom,
+                             d_sc, (int)Mq, gdh, st));
+    }
+  }
+  if (sg[3].n) {
+    float* rec = BUF(float, "base_rec", N * base_record_stride(D));
+    DT_HIP(launch_base_records(xr_perm, wr_perm, rt.leaf_of_pos, rt.ctr, N, D, wmax_bits, rec, st));
+    DT_HIP(launch_base(sg[3], wl.ent[3], qv, rv, xq_perm, rec, D, d_s2, wmax_bits, (int)Mq, gx, st));
+  }
+  DT_HIP(hipStreamSynchronize(st));
+  double t4 = now_ms();
+  S.t_work_ms = t4 - t3;
+
+  // 5. Post-pass.
+  for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
+    DT_HIP(launch_l2l_level(T, qv, qt.level_begin[lv], qt.level_begin[lv + 1], n_h, nQ, d_sc,
+                            lco ? lco : Gest, pL, Gest, st));
+  std::vector<int32_t> qleft(nQ);
+  DT_HIP(hipMemcpyAsync(qleft.data(), qt.left, nQ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> leaves;
+  for (int i = 0; i < nQ; ++i)
+    if (qleft[i] < 0) leaves.push_back(i);
+  int32_t* d_leaves = BUF(int32_t, "q_leaves", leaves.size());
+  DT_HIP(upload(leaves, d_leaves, st));
+  DT_HIP(launch_leaf_eval(T, qv, d_leaves, (int)leaves.size(), n_h, nQ, (int)Mq, d_sc, xq_perm,
+                          qt.perm, gx, gdh, Gest, lco ? lco : Gest, pL, G_dev, st));
+  DT_HIP(hipStreamSynchronize(st));
+  double t5 = now_ms();
+  S.t_post_ms = t5 - t4;
+
+  // Statistics.
+  std::vector<unsigned long long> hc(n_h * 6 + 1);
+  DT_HIP(hipMemcpyAsync(hc.data(), hcount, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < n_h * 6; ++k) {
+    ctx->pair_counts[k] = (int64_t)hc[k];
+    S.pairs[k % 6] += (int64_t)hc[k];
+  }
+  S.base_pair_evals = (int64_t)hc[n_h * 6];
+  if (opt.keep_trace) {
+    s = keep_tree(ctx, rt, D, ctx->host_tree[0], st);
+    if (s != GS_OK) return s;
+    s = keep_tree(ctx, qt, D, ctx->host_tree[1], st);
+    if (s != GS_OK) return s;
+  }
+  return GS_OK;
+}
+
+}  // namespace gs

@@ -1,0 +1,67 @@
+// Level-synchronous dual-tree traversal: device-side data layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+// Per-call constants of the pruning test (sections 4-5).
+struct DecideConst {
+  int D = 0, P = 0;
+  int mono = 0, use_tokens = 1, use_fmm = 1;
+  int log_pairs = 0;
+  int fmm_mask = 7;  // allowed series methods: bit 0 DH, bit 1 DL, bit 2 H2L
+  double Wtot = 0.0, eps_alg = 0.0;
+  double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
+  double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
+};
+
+// Counters of one frontier segment (one (bandwidth, query node) pair list).
+struct SegCount {
+  int32_t v[10];  // [0] next-level pairs, [1] next-level segments,
+                  // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags
+};
+
+struct FrontierLevel {
+  int32_t *h = nullptr, *Q = nullptr, *off = nullptr, *len = nullptr;
+  double *T = nullptr, *Lp = nullptr;
+  int32_t* R = nullptr;  // pairs
+};
+
+// Node fields read by the decision kernel.
+struct TreeView {
+  const double *lo, *hi, *rinf, *W, *wmin;
+  const int32_t *count, *left;
+};
+
+// Work list entries: (R << 4) | p; groups: {h, Q, first entry, entries}.
+struct WorkLists {
+  int32_t* ent[4];
+  int4* grp[4];
+};
+
+struct LevelOffsets {
+  int32_t ent[4];
+  int32_t grp[4];
+};
+
+hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
+                         const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
+                         const DecideConst& c, double* scratch_kmax, double* scratch_dmin2,
+                         int8_t* code, int8_t* porder, double* Gest, SegCount* cnt,
+                         unsigned long long* hcount, unsigned long long* base_evals,
+                         float* policy_feat, hipStream_t s);
+
+hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, size_t temp_bytes,
+                       hipStream_t s);
+size_t scan_counts_temp_bytes(int S);
+
+hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt,
+                       const int32_t* qleft, const int32_t* rleft, const int8_t* code,
+                       const int8_t* porder, const SegCount* cnt, const SegCount* incl,
+                       const WorkLists& wl, LevelOffsets base, hipStream_t s);
+
+}  // namespace gs

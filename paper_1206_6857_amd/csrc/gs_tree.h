@@ -1,0 +1,45 @@
+// Device kd-tree layout and builder interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace gs {
+
+// Node arrays in breadth-first numbering; boxes and centres are [node][D].
+struct DevTree {
+  int64_t capacity = 0, n_nodes = 0, n_points = 0;
+  int D = 0;
+  int32_t *begin = nullptr, *count = nullptr, *left = nullptr, *depth = nullptr;
+  int32_t *perm = nullptr;         // [n_points] original index at each position
+  int32_t *leaf_of_pos = nullptr;  // [n_points] leaf containing each position
+  double *lo = nullptr, *hi = nullptr, *ctr = nullptr;
+  double *rinf = nullptr, *W = nullptr, *wmin = nullptr;
+  const int32_t* perm_list = nullptr;
+  std::vector<int> level_begin;    // host: first node of each level, then n_nodes
+};
+
+struct TreeBuildArgs {
+  int64_t n = 0;
+  int D = 0;
+  int leaf_size = 64;
+  const double* xs = nullptr;  // [D][n]
+  const double* w = nullptr;   // [n] or nullptr (unit weights)
+  int32_t *ids = nullptr, *lists = nullptr, *lists_alt = nullptr;  // ids [n], lists [(D+1) n]
+  int32_t *pos_node = nullptr, *pos_node_alt = nullptr, *isleft = nullptr;  // [n]
+  int32_t *flags = nullptr, *scan = nullptr;                             // [(D+1) n]
+  int32_t *splitdim = nullptr;                                           // [capacity]
+  int32_t *n_children = nullptr;                                         // [1]
+  double* sort_keys = nullptr;                                           // [n]
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+};
+
+int64_t tree_node_capacity(int64_t n, int leaf_size);
+size_t tree_sort_temp_bytes(int64_t n, int D);
+hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int>& level_begin,
+                             hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,100 @@
+// Input staging: validation and layout conversion of caller arrays.
+#include "gs_internal.h"
+
+namespace gs {
+
+// Copy row-major points into a structure-of-arrays copy x_soa[d][n] and a
+// row-major copy x_aos[n][D].  Adding +0.0 turns -0.0 into +0.0, so that
+// both zeros compare and sort as one value.  Any NaN or infinity raises
+// *bad_flag.
+__global__ void stage_points_kernel(const double* __restrict__ x, int64_t n, int D,
+                                    double* __restrict__ x_soa, double* __restrict__ x_aos,
+                                    int* __restrict__ bad_flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool bad = false;
+  for (int d = 0; d < D; ++d) {
+    double v = x[i * D + d] + 0.0;
+    if (!isfinite(v)) bad = true;
+    x_soa[(int64_t)d * n + i] = v;
+    x_aos[i * D + d] = v;
+  }
+  if (bad) atomicOr(bad_flag, 1);
+}
+
+__global__ void check_positive_kernel(const double* __restrict__ v, int64_t n,
+                                      int* __restrict__ bad_flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = v[i];
+  if (!(a > 0.0) || !isfinite(a)) atomicOr(bad_flag, 2);
+}
+
+hipError_t launch_stage_points(const double* x, int64_t n, int D, double* x_soa, double* x_aos,
+                               int* bad_flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_points_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, n,
+                     D, x_soa, x_aos, bad_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_positive(const double* v, int64_t n, int* bad_flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_positive_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, v,
+                     n, bad_flag);
+  return hipGetLastError();
+}
+
+}  // namespace gs
+
+namespace gs {
+
+namespace {
+
+__global__ void gather_rows_kernel(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                                   int64_t n, int D, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * D) return;
+  const int64_t i = t / D;
+  const int d = (int)(t - i * D);
+  dst[t] = src[(int64_t)perm[i] * D + d];
+}
+
+__global__ void gather_kernel(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                              int64_t n, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void max_bits_kernel(const double* __restrict__ w, int64_t n,
+                                unsigned long long* __restrict__ out_bits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicMax(out_bits, (unsigned long long)__double_as_longlong(w[i]));
+}
+
+}  // namespace
+
+hipError_t launch_gather_rows(const double* src, const int32_t* perm, int64_t n, int D, double* dst,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)ceil_div(n * D, 256)), dim3(256), 0, s, src,
+                     perm, n, D, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, double* dst,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, src, perm, n,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_positive(const double* w, int64_t n, unsigned long long* out_bits,
+                               hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out_bits, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(max_bits_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w, n,
+                     out_bits);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,300 @@
+// kd-tree construction on the GPU (section 6, Figure 5).
+//
+// Split rule (the paper leaves it open): a node with more than leaf_size
+// points is split on its dimension of widest bounding-box extent (ties to the
+// smallest dimension); its points ordered by (coordinate, original index)
+// go to the left child for the first floor(n/2) and to the right child for the
+// rest.  Nodes are numbered breadth first, left before right.
+//
+// Construction without per-level sorting: each dimension d keeps a list of
+// point ids sorted by (x_d, id) inside every node's position range
+// [begin, begin+count) (one stable radix sort per dimension at the start), plus
+// one extra list sorted by id.  A node's bounding box is then read off the
+// first and last entry of each list, and its split assigns the first
+// floor(n/2) entries of the split dimension's list to the left child.  Every
+// list is then stably partitioned by that assignment (one exclusive scan of
+// the per-entry flags over all lists at once), which keeps each list sorted
+// inside both children.  The extra list becomes the final permutation, whose
+// leaves hold their points in increasing original index.
+//
+// All values cached per node are exact or computed in a fixed order:
+// lo/hi are copies of coordinates, ctr = 0.5*(lo+hi), rinf = max|x-ctr| via an
+// order-independent max, leaf W is the sequential sum in permutation order,
+// internal W = W_left + W_right.
+#include <cstring>  // rocprim uses memset without including it
+#include <rocprim/rocprim.hpp>
+
+#include "gs_internal.h"
+#include "gs_tree.h"
+
+namespace gs {
+
+namespace {
+
+__global__ void iota_kernel(int32_t* __restrict__ v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int32_t)i;
+}
+
+__global__ void node_stats_kernel(int lb, int le, int D, int64_t n, const int32_t* __restrict__ lists,
+                                  const double* __restrict__ xs, const int32_t* __restrict__ begin,
+                                  const int32_t* __restrict__ count, double* __restrict__ lo,
+                                  double* __restrict__ hi, double* __restrict__ ctr,
+                                  int32_t* __restrict__ splitdim,
+                                  unsigned long long* __restrict__ rinf_bits) {
+  const int i = lb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= le) return;
+  const int64_t b = begin[i];
+  const int64_t c = count[i];
+  int best = 0;
+  double bestext = -1.0;
+  for (int d = 0; d < D; ++d) {
+    const double l = xs[(int64_t)d * n + lists[(int64_t)d * n + b]];
+    const double h = xs[(int64_t)d * n + lists[(int64_t)d * n + b + c - 1]];
+    lo[(int64_t)i * D + d] = l;
+    hi[(int64_t)i * D + d] = h;
+    ctr[(int64_t)i * D + d] = 0.5 * (l + h);
+    const double ext = h - l;
+    if (ext > bestext) {
+      bestext = ext;
+      best = d;
+    }
+  }
+  splitdim[i] = best;
+  rinf_bits[i] = 0ull;
+}
+
+// One workgroup: number the children of the level's split nodes.
+__global__ __launch_bounds__(1024) void children_kernel(int lb, int le, int leaf_size,
+                                                       int32_t* __restrict__ begin,
+                                                       int32_t* __restrict__ count,
+                                                       int32_t* __restrict__ left,
+                                                       int32_t* __restrict__ depth,
+                                                       int32_t* __restrict__ n_children_out) {
+  __shared__ int sc[1024];
+  int carry = 0;
+  for (int base = lb; base < le; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int f = (i < le && count[i] > leaf_size) ? 1 : 0;
+    sc[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+      __syncthreads();
+      sc[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int incl = sc[threadIdx.x];
+    const int total = sc[1023];
+    if (i < le) {
+      if (f) {
+        const int l = le + 2 * (carry + incl - 1);
+        const int b = begin[i], c = count[i];
+        left[i] = l;
+        begin[l] = b;
+        count[l] = c / 2;
+        begin[l + 1] = b + c / 2;
+        count[l + 1] = c - c / 2;
+        depth[l] = depth[l + 1] = depth[i] + 1;
+      } else {
+        left[i] = -1;
+      }
+    }
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_children_out = 2 * carry;
+}
+
+// Per position of the level: radius, left/right assignment, next-level node.
+__global__ void mark_kernel(int64_t n, int D, const int32_t* __restrict__ lists,
+                            const double* __restrict__ xs, const int32_t* __restrict__ pos_node,
+                            int32_t* __restrict__ pos_node_next, int32_t* __restrict__ leaf_of_pos,
+                            const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+                            const int32_t* __restrict__ left, const int32_t* __restrict__ splitdim,
+                            const double* __restrict__ ctr, unsigned long long* __restrict__ rinf_bits,
+                            int32_t* __restrict__ isleft) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int node = pos_node[i];
+  if (node < 0) {
+    pos_node_next[i] = -1;
+    return;
+  }
+  const int32_t p = lists[(int64_t)D * n + i];
+  double r = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const double a = fabs(xs[(int64_t)d * n + p] - ctr[(int64_t)node * D + d]);
+    r = a > r ? a : r;
+  }
+  atomicMax(&rinf_bits[node], (unsigned long long)__double_as_longlong(r));
+  const int l = left[node];
+  if (l >= 0) {
+    const int64_t mid = (int64_t)begin[node] + count[node] / 2;
+    const int sd = splitdim[node];
+    isleft[lists[(int64_t)sd * n + i]] = i < mid ? 1 : 0;
+    pos_node_next[i] = i < mid ? l : l + 1;
+  } else {
+    leaf_of_pos[i] = node;
+    pos_node_next[i] = -1;
+  }
+}
+
+__global__ void flags_kernel(int64_t n, int nl, const int32_t* __restrict__ lists,
+                             const int32_t* __restrict__ pos_node, const int32_t* __restrict__ left,
+                             const int32_t* __restrict__ isleft, int32_t* __restrict__ flags) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nl) return;
+  const int64_t i = t % n;
+  const int node = pos_node[i];
+  flags[t] = (node >= 0 && left[node] >= 0) ? isleft[lists[t]] : 0;
+}
+
+__global__ void scatter_kernel(int64_t n, int nl, const int32_t* __restrict__ lists,
+                               const int32_t* __restrict__ pos_node, const int32_t* __restrict__ left,
+                               const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
+                               const int32_t* __restrict__ flags, const int32_t* __restrict__ scan,
+                               int32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nl) return;
+  const int64_t k = t / n;
+  const int64_t i = t - k * n;
+  const int node = pos_node[i];
+  int64_t dst = i;
+  if (node >= 0 && left[node] >= 0) {
+    const int64_t b = begin[node];
+    const int64_t half = count[node] / 2;
+    const int64_t rank = (int64_t)scan[t] - (int64_t)scan[k * n + b];
+    dst = flags[t] ? b + rank : b + half + (i - b - rank);
+  }
+  out[k * n + dst] = lists[t];
+}
+
+__global__ void leaf_weights_kernel(int n_nodes, const int32_t* __restrict__ left,
+                                    const int32_t* __restrict__ begin,
+                                    const int32_t* __restrict__ count,
+                                    const int32_t* __restrict__ perm, const double* __restrict__ w,
+                                    double* __restrict__ W, double* __restrict__ wmin) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes || left[i] >= 0) return;
+  double s = 0.0, m = INFINITY;
+  const int b = begin[i], e = begin[i] + count[i];
+  for (int j = b; j < e; ++j) {
+    const double v = w ? w[perm[j]] : 1.0;
+    s = s + v;
+    m = v < m ? v : m;
+  }
+  W[i] = s;
+  wmin[i] = m;
+}
+
+__global__ void internal_weights_kernel(int lb, int le, const int32_t* __restrict__ left,
+                                        double* __restrict__ W, double* __restrict__ wmin) {
+  const int i = lb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= le) return;
+  const int l = left[i];
+  if (l < 0) return;
+  W[i] = W[l] + W[l + 1];
+  wmin[i] = wmin[l] < wmin[l + 1] ? wmin[l] : wmin[l + 1];
+}
+
+}  // namespace
+
+int64_t tree_node_capacity(int64_t n, int leaf_size) {
+  int64_t min_leaf = (leaf_size + 1) / 2;
+  if (min_leaf < 1) min_leaf = 1;
+  return 2 * (n / min_leaf + 1) + 1;
+}
+
+size_t tree_sort_temp_bytes(int64_t n, int D) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs((void*)nullptr, bytes, (const double*)nullptr, (double*)nullptr,
+                            (const int32_t*)nullptr, (int32_t*)nullptr, (unsigned)n);
+  size_t b2 = 0;
+  (void)rocprim::exclusive_scan((void*)nullptr, b2, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
+                          (size_t)n * (D + 1), rocprim::plus<int32_t>());
+  return bytes > b2 ? bytes : b2;
+}
+
+hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int>& level_begin,
+                             hipStream_t s) {
+  const int64_t n = a.n;
+  const int D = a.D;
+  const int nl = D + 1;
+  hipError_t e;
+  const unsigned g1 = (unsigned)ceil_div(n, 256);
+  const unsigned gl = (unsigned)ceil_div(n * nl, 256);
+
+  // Per-dimension lists sorted by (x_d, id), plus the id list.
+  hipLaunchKernelGGL(iota_kernel, dim3(g1), dim3(256), 0, s, a.ids, n);
+  for (int d = 0; d < D; ++d) {
+    size_t bytes = a.temp_bytes;
+    e = rocprim::radix_sort_pairs(a.temp, bytes, a.xs + (int64_t)d * n, a.sort_keys, a.ids,
+                                  a.lists + (int64_t)d * n, (unsigned)n, 0, 64, s);
+    if (e != hipSuccess) return e;
+  }
+  e = hipMemcpyAsync(a.lists + (int64_t)D * n, a.ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+
+  // Root.
+  int32_t root[3] = {0, (int32_t)n, 0};
+  e = hipMemcpyAsync(t.begin, &root[0], sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.count, &root[1], sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.depth, &root[2], sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.pos_node, 0, n * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+
+  int32_t* lists = a.lists;
+  int32_t* lists_alt = a.lists_alt;
+  int32_t* pos = a.pos_node;
+  int32_t* pos_alt = a.pos_node_alt;
+  level_begin.clear();
+  int lb = 0, le = 1;
+  while (true) {
+    level_begin.push_back(lb);
+    const int width = le - lb;
+    hipLaunchKernelGGL(node_stats_kernel, dim3((unsigned)ceil_div(width, 256)), dim3(256), 0, s, lb,
+                       le, D, n, lists, a.xs, t.begin, t.count, t.lo, t.hi, t.ctr, a.splitdim,
+                       (unsigned long long*)t.rinf);
+    hipLaunchKernelGGL(children_kernel, dim3(1), dim3(1024), 0, s, lb, le, a.leaf_size, t.begin,
+                       t.count, t.left, t.depth, a.n_children);
+    hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, D, lists, a.xs, pos, pos_alt,
+                       t.leaf_of_pos, t.begin, t.count, t.left, a.splitdim, t.ctr,
+                       (unsigned long long*)t.rinf, a.isleft);
+    int32_t nchild = 0;
+    e = hipMemcpyAsync(&nchild, a.n_children, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (nchild == 0) break;
+    hipLaunchKernelGGL(flags_kernel, dim3(gl), dim3(256), 0, s, n, nl, lists, pos, t.left, a.isleft,
+                       a.flags);
+    size_t bytes = a.temp_bytes;
+    e = rocprim::exclusive_scan(a.temp, bytes, a.flags, a.scan, 0, (size_t)n * nl,
+                                rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scatter_kernel, dim3(gl), dim3(256), 0, s, n, nl, lists, pos, t.left, t.begin,
+                       t.count, a.flags, a.scan, lists_alt);
+    std::swap(lists, lists_alt);
+    std::swap(pos, pos_alt);
+    lb = le;
+    le = le + nchild;
+    if (le > t.capacity) return hipErrorInvalidValue;
+  }
+  level_begin.push_back(le);
+  t.n_nodes = le;
+  t.n_points = n;
+  t.D = D;
+  t.perm_list = lists + (int64_t)D * n;
+  e = hipMemcpyAsync(t.perm, t.perm_list, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(leaf_weights_kernel, dim3((unsigned)ceil_div(le, 256)), dim3(256), 0, s, le,
+                     t.left, t.begin, t.count, t.perm, a.w, t.W, t.wmin);
+  for (int lv = (int)level_begin.size() - 2; lv >= 0; --lv) {
+    const int b = level_begin[lv], en = level_begin[lv + 1];
+    hipLaunchKernelGGL(internal_weights_kernel, dim3((unsigned)ceil_div(en - b, 256)), dim3(256), 0,
+                       s, b, en, t.left, t.W, t.wmin);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gs
