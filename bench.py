@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-bandwidth Gaussian summation on one MI355X.
+
+Workload (default): D=3, N=M=100,000 monochromatic points from an 8-component
+Gaussian mixture (sigma uniform 0.01-0.1), weights 1/N, 10 bandwidths
+log-spaced 1e-3..1, eps=0.01.  One step is one full gauss_sum call (tree
+build, moments, traversal, base cases, expansions, post-pass) over the whole
+bandwidth sweep with inputs already resident in device memory.
+
+Metric: pair-evals/s equivalent = M * N * n_h / (time per step), for the
+dual-tree path; the plain GPU exhaustive path is timed beside it.  The JSON
+line also carries the roofline of the dominant kernel (HIP-event timing of
+that kernel over the timed steps) and the CPU oracle's rate on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published figures (one GPU).
+CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+HBM_BYTES_PER_S = 8.0e12
+# Issue cost of one v_exp_f32 in VALU slots (transcendental rate), relative to
+# an FMA; measured on gfx950 by the rate probe recorded in the design notes.
+EXP_SLOTS = 2.0
+
+
+def base_tile_model(D):
+    """Algorithmic FP32 work of one point-pair kernel evaluation in the base-case
+    and exhaustive tiles: D subtractions + D FMAs (squared distance), one FMA
+    (scaled exponent), one exp2, one FMA (weighted accumulation).
+    Returns (flops per pair-eval, VALU issue slots per pair-eval)."""
+    flops = D + 2 * D + 2 + 1 + 2
+    slots = D + D + 1 + EXP_SLOTS + 1
+    return flops, slots
+
+
+def alu_peak_pairs_per_s(D):
+    lane_slots = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ
+    return lane_slots / base_tile_model(D)[1]
+
+
+def cpu_baseline(wl, n_queries, seed=0):
+    """The FP64 exhaustive oracle on a bounded sample of the workload's queries
+    (all references, all bandwidths), single-threaded."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.exhaustive import gauss_sum_exhaustive
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(wl.queries.shape[0], size=n_queries, replace=False)
+    q = wl.queries[idx]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        gauss_sum_exhaustive(q, wl.refs, wl.weights, wl.bandwidths)
+        t = time.perf_counter() - t0
+    evals = n_queries * wl.refs.shape[0] * len(wl.bandwidths)
+    return {"value": evals / t, "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 exhaustive oracle, %d of %d queries x all %d references x %d "
+                      "bandwidths (%.3g pair-evals in %.1f s)"
+                      % (n_queries, wl.queries.shape[0], wl.refs.shape[0], len(wl.bandwidths),
+                         evals, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=1, help="workload index (see datagen.workload)")
+    ap.add_argument("--cpu-queries", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exhaustive", action="store_true")
+    ap.add_argument("--leaf-size", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1206_6857_amd as g
+    from paper_1206_6857_amd import _lib
+    from paper_1206_6857_amd.datagen import workload
+
+    wl = workload(args.workload)
+    M, N, D, n_h = wl.queries.shape[0], wl.refs.shape[0], wl.D, len(wl.bandwidths)
+    dev = torch.device("cuda:0")
+    rd = torch.from_numpy(wl.refs).to(dev)
+    qd = rd if wl.monochromatic else torch.from_numpy(wl.queries).to(dev)
+    wd = torch.from_numpy(wl.weights).to(dev)
+    hd = torch.from_numpy(wl.bandwidths).to(dev)
+    out = torch.empty((n_h, M), dtype=torch.float64, device=dev)
+    ctx = g.Context(0)
+    pair_evals = float(M) * N * n_h
+
+    def run(method, steps, warmup):
+        for _ in range(warmup):
+            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, leaf_size=args.leaf_size)
+        torch.cuda.synchronize()
+        kms = np.zeros(8)
+        kl = np.zeros(8, dtype=np.int64)
+        base_evals = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, kernel_timing=1,
+                          leaf_size=args.leaf_size)
+            st = ctx.stats()
+            kms += np.array(st.k_ms[:])
+            kl += np.array(st.k_launches[:])
+            base_evals += st.base_pair_evals
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        return t, kms, kl, base_evals, ctx.stats()
+
+    t_dt, kms, kl, base_evals, st_dt = run("dualtree", args.steps, args.warmup)
+    pc = ctx.pair_counts(n_h)
+    result = {
+        "metric": "pair-evals/sec equiv. at eps=0.01, dual-tree vs GPU exhaustive; % of roofline",
+        "value": pair_evals / t_dt,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "D": D, "N": N, "M": M, "n_bandwidths": n_h,
+                   "eps": wl.eps, "method": "dualtree", "leaf_size": args.leaf_size,
+                   "parallelism": "single-gpu"},
+    }
+
+    # Dominant kernel of the dual-tree step: the base-case tiles (HIP events on
+    # the library's stream over the timed steps).
+    flops_pe, slots_pe = base_tile_model(D)
+    if kl[_lib.K_BASE] > 0:
+        avg_ms = kms[_lib.K_BASE] / kl[_lib.K_BASE]
+        evals_per_launch = base_evals / kl[_lib.K_BASE]
+        achieved = evals_per_launch * flops_pe / (avg_ms * 1e-3) / 1e12
+        peak = alu_peak_pairs_per_s(D) * flops_pe / 1e12
+        result["roofline"] = {"bound": "alu", "kernel": "base_kernel", "achieved": achieved,
+                              "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                              "traffic": None, "avg_launch_ms": avg_ms,
+                              "pair_evals_per_launch": evals_per_launch}
+    result["breakdown_ms"] = {
+        "stage": st_dt.t_stage_ms, "tree": st_dt.t_tree_ms, "moments": st_dt.t_moments_ms,
+        "traverse": st_dt.t_traverse_ms, "work": st_dt.t_work_ms, "post": st_dt.t_post_ms,
+        "base_kernel": float(kms[_lib.K_BASE] / args.steps),
+        "series_kernels": float(kms[_lib.K_SERIES] / args.steps)}
+    result["pairs"] = {k: int(pc[:, i].sum()) for i, k in enumerate(["FD", "DH", "DL", "H2L", "BASE", "SPLIT"])}
+    result["base_pair_evals_frac"] = base_evals / args.steps / pair_evals
+
+    if not args.no_exhaustive:
+        t_ex, kms_e, kl_e, _, _ = run("exhaustive", max(1, args.steps), 1)
+        ex = {"value": pair_evals / t_ex, "ms_per_step": t_ex * 1e3}
+        if kl_e[_lib.K_EXHAUSTIVE] > 0:
+            avg_ms = kms_e[_lib.K_EXHAUSTIVE] / kl_e[_lib.K_EXHAUSTIVE]
+            ach = pair_evals / (avg_ms * 1e-3)
+            ex["roofline"] = {"bound": "alu", "achieved_pair_evals_per_s": ach,
+                              "peak_pair_evals_per_s": alu_peak_pairs_per_s(D),
+                              "frac": ach / alu_peak_pairs_per_s(D)}
+        result["exhaustive"] = ex
+        result["dualtree_over_exhaustive"] = t_ex / t_dt
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_queries)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -73,6 +73,9 @@ typedef struct gs_options {
   int32_t log_pairs;        /* 1: record policy-training features and costs */
   int32_t fmm_mask;         /* series methods bestMethod may choose (Figure 6): bit 0
                                DH, bit 1 DL, bit 2 H2L; 0 or 7 allows all (ablations) */
+  int32_t kernel_timing;    /* 1: time kernel classes with HIP events on the context's
+                               stream (gs_stats.k_ms / k_launches) */
+  int32_t reserved0;
   double eps_round_share;   /* share of eps reserved for floating-point rounding
                                (default 0.1); the pruning test uses (1-share)*eps */
 } gs_options;
@@ -90,7 +93,22 @@ typedef struct gs_stats {
   int64_t policy_fallbacks; /* of those, choices the bound rejected (rule used) */
   double t_stage_ms, t_tree_ms, t_moments_ms, t_traverse_ms, t_work_ms, t_post_ms;
   double t_total_ms;        /* wall time of the last gauss_sum call */
+  /* With kernel_timing = 1: device milliseconds and launch counts per kernel class,
+   * indexed by GS_K_*. */
+  double k_ms[8];
+  int64_t k_launches[8];
 } gs_stats;
+
+/* Kernel classes of gs_stats.k_ms. */
+enum {
+  GS_K_BASE = 0,        /* base-case tiles */
+  GS_K_EXHAUSTIVE = 1,  /* plain exhaustive tiles */
+  GS_K_DECIDE = 2,      /* frontier decisions and emission */
+  GS_K_SERIES = 3,      /* DH, DL and H2L work */
+  GS_K_POST = 4,        /* L2L and leaf evaluation */
+  GS_K_TREE = 5,        /* tree construction */
+  GS_K_MOMENTS = 6      /* leaf moments and H2H */
+};
 
 /* Fill *opt with the defaults listed above. */
 void gs_default_options(gs_options* opt);

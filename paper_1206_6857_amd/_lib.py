@@ -31,6 +31,7 @@ class GsOptions(ctypes.Structure):
                 ("policy", ctypes.c_int32), ("monochromatic", ctypes.c_int32),
                 ("blocking", ctypes.c_int32), ("keep_trace", ctypes.c_int32),
                 ("log_pairs", ctypes.c_int32), ("fmm_mask", ctypes.c_int32),
+                ("kernel_timing", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("eps_round_share", ctypes.c_double)]
 
 
@@ -43,7 +44,9 @@ class GsStats(ctypes.Structure):
                 ("t_stage_ms", ctypes.c_double), ("t_tree_ms", ctypes.c_double),
                 ("t_moments_ms", ctypes.c_double), ("t_traverse_ms", ctypes.c_double),
                 ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 8),
+                ("k_launches", ctypes.c_int64 * 8)]
+K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS = range(7)
 
 
 _lib = None

@@ -31,6 +31,7 @@ SOURCES = [
     ("k_tree.hip", NO_CONTRACT),
     ("k_decide.hip", NO_CONTRACT),
     ("k_series.hip", []),
+    ("k_series_fast.hip", []),
     ("k_base.hip", []),
     ("dualtree.hip", NO_CONTRACT),
     ("capi.cpp", NO_CONTRACT),

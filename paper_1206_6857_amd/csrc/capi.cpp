@@ -58,6 +58,36 @@ bool is_device_pointer(const void* p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+KernelTimer::KernelTimer(gs_ctx_base* c, bool enabled, int k, hipStream_t s) : ctx(c), cls(k) {
+  if (!enabled) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  on = hipEventRecord(a, s) == hipSuccess;
+}
+
+void KernelTimer::stop(hipStream_t s, int n_launches) {
+  if (!on) return;
+  launches = n_launches;
+  if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+    (void)hipGetLastError();
+    on = false;
+    return;
+  }
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+    ctx->stats.k_ms[cls] += ms;
+    ctx->stats.k_launches[cls] += launches;
+  }
+  on = false;
+}
+
+KernelTimer::~KernelTimer() {
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+}
+
 }  // namespace gs
 
 struct gs_ctx : gs::gs_ctx_base {};
@@ -319,13 +349,16 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   ctx->pair_counts.assign((size_t)n_h * 6, 0);
   ctx->trace.clear();
   ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
+  ctx->kernel_timing = opt.kernel_timing != 0;
 
   if (opt.method == GS_EXHAUSTIVE) {
     float* rec = WS(float, "ex_rec", N * exhaustive_record_stride(D));
     unsigned long long* wb = WS(unsigned long long, "wmax_bits", 1);
     GS_HIP(ctx, launch_exhaustive_records(in.r_aos, in.w, N, D, rec, wb, st));
     double* partial = WS(double, "ex_partial", exhaustive_partial_elems(M, N, n_h));
+    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_EXHAUSTIVE, st);
     GS_HIP(ctx, launch_exhaustive(in.q_aos, M, rec, N, D, hs.data(), n_h, wb, partial, Gd, st));
+    kt.stop(st, 1);
   } else {
     s = run_dualtree(ctx, in, hs, eps, opt, Gd);
     if (s != GS_OK) return s;

@@ -242,6 +242,7 @@ __global__ void init_level0_kernel(int n_h, FrontierLevel f) {
   f.T[k] = 0.0;
   f.Lp[k] = 0.0;
   f.R[k] = 0;
+  f.seg[k] = k;
 }
 
 __global__ void group_keys_kernel(int n, const int4* __restrict__ grp, int nQ,
@@ -470,6 +471,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     dc.bconst[p] = bound_const(D, p);
     dc.binomD[p] = (double)binom(D + p - 1, D);
   }
+  {
+    int64_t v = 1;
+    for (int k = 0; k < 2 * kMaxPlimit + 2; ++k) {
+      dc.powD[k] = v;
+      int64_t nv;
+      v = __builtin_mul_overflow(v, (int64_t)D, &nv) ? INT64_MAX : nv;
+    }
+  }
 
   // Per (h, query node) and per (h, query point) state.
   double* Gest = BUF(double, "Gest", (int64_t)n_h * nQ);
@@ -497,6 +506,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     f.T = BUF(double, p + "T", nseg);
     f.Lp = BUF(double, p + "Lp", nseg);
     f.R = BUF(int32_t, p + "R", npair);
+    f.seg = BUF(int32_t, p + "seg", npair);
     return GS_OK;
   };
   FrontierLevel cur, nxt;
@@ -520,16 +530,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   std::vector<int8_t> tr_code, tr_p;
   while (nseg > 0) {
     peak = std::max(peak, npair);
-    double* s_kmax = BUF(double, "s_kmax", npair);
-    double* s_dmin2 = BUF(double, "s_dmin2", npair);
     int8_t* code = BUF(int8_t, "p_code", npair);
     int8_t* pord = BUF(int8_t, "p_ord", npair);
     SegCount* cnt = BUF(SegCount, "seg_cnt", nseg);
     SegCount* incl = BUF(SegCount, "seg_incl", nseg);
     const size_t tb = scan_counts_temp_bytes((int)nseg);
     void* temp = BUF(char, "scan_temp", tb);
-    DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, s_kmax,
-                         s_dmin2, code, pord, Gest, cnt, hcount, hcount + n_h * 6, nullptr, st));
+    DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
+                         Gest, cnt, hcount, hcount + n_h * 6, st));
     DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
     SegCount tot;
     DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
@@ -610,18 +618,34 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     sg[x].key = skey;
   }
   if (use_fmm) {
-    DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
+    const bool fast = series_fast_available(D, P);
+    if (fast)
+      DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+    else
+      DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
     DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
     for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
       const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
-      DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), wl.ent[0], qv, rv, xq_perm, Mom,
-                             d_sc, (int)Mq, gdh, st));
+      // query nodes of traversal level lv: depth lv (at most ceil(M / 2^lv) points)
+      // or leaves of earlier levels (at most leaf_size points)
+      const int64_t depth_max = lv < 62 ? ((Mq + ((int64_t)1 << lv) - 1) >> lv) : 1;
+      const int max_q = (int)std::max<int64_t>(depth_max, opt.leaf_size);
+      if (fast)
+        DT_HIP(launch_dh_fast(D, P, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
+                              Mom, d_sc, (int)Mq, gdh, st));
+      else
+        DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
+                               Mom, d_sc, (int)Mq, gdh, st));
     }
+    kt.stop(st, 2 + (int)dh_level_begin.size() - 1);
   }
   if (sg[3].n) {
     float* rec = BUF(float, "base_rec", N * base_record_stride(D));
     DT_HIP(launch_base_records(xr_perm, wr_perm, rt.leaf_of_pos, rt.ctr, N, D, wmax_bits, rec, st));
+    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_BASE, st);
     DT_HIP(launch_base(sg[3], wl.ent[3], qv, rv, xq_perm, rec, D, d_s2, wmax_bits, (int)Mq, gx, st));
+    kt.stop(st, 1);
   }
   DT_HIP(hipStreamSynchronize(st));
   double t4 = now_ms();

@@ -43,6 +43,7 @@ struct gs_ctx_base {
   std::vector<int64_t> pair_counts;   // [n_h][6]
   std::vector<int32_t> trace;         // [n][6]
   HostTree host_tree[2];
+  bool kernel_timing = false;
 };
 
 // Staged, validated inputs in device memory.
@@ -58,6 +59,20 @@ struct DeviceInputs {
 };
 
 bool is_device_pointer(const void* p);
+
+// Optional HIP-event timing of one kernel class on the context's stream:
+// construct before the launches, call stop() after them; the elapsed device
+// time is added to stats.k_ms[cls] once the stream is synchronised (flush()).
+struct KernelTimer {
+  gs_ctx_base* ctx = nullptr;
+  int cls = 0;
+  int launches = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  KernelTimer(gs_ctx_base* c, bool enabled, int k, hipStream_t s);
+  void stop(hipStream_t s, int n_launches);
+  ~KernelTimer();
+};
 
 // Graded multi-index set with |alpha| < p (section 2), library order.
 std::vector<std::vector<int>> multi_indices(int D, int p);

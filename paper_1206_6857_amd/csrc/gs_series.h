@@ -44,7 +44,7 @@ hipError_t launch_p2m(const SeriesTables& T, const NodeView& t, int n_nodes, con
 hipError_t launch_h2h_level(const SeriesTables& T, const NodeView& t, int lb, int le, double* M,
                             hipStream_t s);
 // DH groups of one traversal level (their query nodes are disjoint per h).
-hipError_t launch_dh_level(const SeriesTables& T, const int4* grp, int ng, const int32_t* ent,
+hipError_t launch_dh_level(const SeriesTables& T, const int4* grp, int ng, int max_q, const int32_t* ent,
                            const NodeView& qt, const NodeView& rt, const double* xq_perm,
                            const double* M, const double* sc, int M_q, double* gdh, hipStream_t s);
 hipError_t launch_dl(const SeriesTables& T, const SortedGroups& g, const int32_t* ent,
@@ -62,6 +62,18 @@ hipError_t launch_leaf_eval(const SeriesTables& T, const NodeView& qt, const int
                             const double* xq_perm, const int32_t* qperm, const double* gx,
                             const double* gdh, const double* Gest, const double* lco,
                             const int32_t* pL, double* G_out, hipStream_t s);
+
+// Compile-time specialisations of DH and DL for the order-limit table's
+// (D, P) pairs; launch_*_fast return hipErrorInvalidValue for other pairs.
+bool series_fast_available(int D, int P);
+// max_q: an upper bound on the point count of the groups' query nodes.
+hipError_t launch_dh_fast(int D, int P, const int4* grp, int ng, int max_q, const int32_t* ent,
+                          const NodeView& qt, const NodeView& rt, const double* xq_perm,
+                          const double* M, const double* sc, int Mq, double* gdh, hipStream_t s);
+hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+                          const NodeView& qt, const NodeView& rt, const double* xr_perm,
+                          const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
+                          hipStream_t s);
 
 // Base cases (DITOBase): gx[h][q] for the runs of BASE groups.
 int base_record_stride(int D);

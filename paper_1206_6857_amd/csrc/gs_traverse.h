@@ -17,6 +17,7 @@ struct DecideConst {
   double Wtot = 0.0, eps_alg = 0.0;
   double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
   double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
+  int64_t powD[2 * kMaxPlimit + 2];  // D^k, saturated at INT64_MAX (cost model)
 };
 
 // Counters of one frontier segment (one (bandwidth, query node) pair list).
@@ -28,7 +29,8 @@ struct SegCount {
 struct FrontierLevel {
   int32_t *h = nullptr, *Q = nullptr, *off = nullptr, *len = nullptr;
   double *T = nullptr, *Lp = nullptr;
-  int32_t* R = nullptr;  // pairs
+  int32_t* R = nullptr;    // pairs
+  int32_t* seg = nullptr;  // segment of each pair
 };
 
 // Node fields read by the decision kernel.
@@ -50,10 +52,9 @@ struct LevelOffsets {
 
 hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
-                         const DecideConst& c, double* scratch_kmax, double* scratch_dmin2,
-                         int8_t* code, int8_t* porder, double* Gest, SegCount* cnt,
-                         unsigned long long* hcount, unsigned long long* base_evals,
-                         float* policy_feat, hipStream_t s);
+                         const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
+                         SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
+                         hipStream_t s);
 
 hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, size_t temp_bytes,
                        hipStream_t s);

@@ -4,7 +4,8 @@
 //
 // One wave handles one run of base groups of a (h, Q) key, so it owns gx[h][q]
 // for the points of Q and writes them once, deterministically.  Lanes hold the
-// query points; the reference leaf's records are read as wave-uniform loads.
+// query points; each reference leaf is staged into LDS with coalesced loads and
+// swept with broadcast reads.
 //
 // Precision: reference coordinates are stored relative to their leaf centre
 // in float (u_r = x_r - c_R), and each lane forms u_q = x_q - c_R in double
@@ -45,6 +46,7 @@ __global__ __launch_bounds__(kW) void base_kernel(SortedGroups g, const int32_t*
                                                   const float* __restrict__ s2,
                                                   const unsigned long long* __restrict__ wmax_bits,
                                                   int Mq, double* __restrict__ gx) {
+  extern __shared__ float srec[];  // [kW][rs]: the reference chunk being swept
   constexpr int DC = DT > 0 ? DT : kMaxD;
   const int D = DT > 0 ? DT : Drt;
   const int i = blockIdx.x;
@@ -55,6 +57,7 @@ __global__ __launch_bounds__(kW) void base_kernel(SortedGroups g, const int32_t*
   const double wscale = __longlong_as_double((long long)*wmax_bits);
   const int qb = qt.begin[Q], qn = qt.count[Q];
   const int lane = threadIdx.x;
+  const int rs4 = rs / 4;
   for (int base = 0; base < qn; base += kW) {
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
@@ -84,20 +87,30 @@ __global__ __launch_bounds__(kW) void base_kernel(SortedGroups g, const int32_t*
           }
         }
         const float shift = (float)box2 * sh;
-        const float* rr = rec + (int64_t)rt.begin[R] * rs;
-        const int rn = rt.count[R];
+        const int rb = rt.begin[R], rn = rt.count[R];
         float part = 0.0f;
-        for (int r = 0; r < rn; ++r) {
-          const float* x = rr + r * rs;
-          float d2 = 0.0f;
-#pragma unroll
-          for (int d = 0; d < DC; ++d) {
-            if (d < D) {
-              const float dd = uq[d] - x[d];
-              d2 = fmaf(dd, dd, d2);
-            }
+        for (int c0 = 0; c0 < rn; c0 += kW) {
+          const int cn = rn - c0 < kW ? rn - c0 : kW;
+          __syncthreads();
+          {
+            const float4* src = reinterpret_cast<const float4*>(rec + (int64_t)(rb + c0) * rs);
+            float4* dst = reinterpret_cast<float4*>(srec);
+            for (int t = lane; t < cn * rs4; t += kW) dst[t] = src[t];
           }
-          part = fmaf(x[D], __builtin_amdgcn_exp2f(fmaf(-d2, sh, shift)), part);
+          __syncthreads();
+#pragma unroll 4
+          for (int r = 0; r < cn; ++r) {
+            const float* x = srec + r * rs;
+            float d2 = 0.0f;
+#pragma unroll
+            for (int d = 0; d < DC; ++d) {
+              if (d < D) {
+                const float dd = uq[d] - x[d];
+                d2 = fmaf(dd, dd, d2);
+              }
+            }
+            part = fmaf(x[D], __builtin_amdgcn_exp2f(fmaf(-d2, sh, shift)), part);
+          }
         }
         const float fi = floorf(shift);
         acc += ldexp((double)(part * __builtin_amdgcn_exp2f(fi - shift)), -(int)fi);
@@ -111,8 +124,9 @@ template <int DT>
 void launch_base_t(const SortedGroups& g, const int32_t* ent, const NodeView& qt, const NodeView& rt,
                    const double* xq_perm, const float* rec, int D, const float* s2,
                    const unsigned long long* wb, int Mq, double* gx, hipStream_t s) {
-  hipLaunchKernelGGL((base_kernel<DT>), dim3(g.n), dim3(kW), 0, s, g, ent, qt, rt, xq_perm, rec, D,
-                     base_record_stride(D), s2, wb, Mq, gx);
+  const int rs = base_record_stride(D);
+  hipLaunchKernelGGL((base_kernel<DT>), dim3(g.n), dim3(kW), (size_t)kW * rs * sizeof(float), s, g,
+                     ent, qt, rt, xq_perm, rec, D, rs, s2, wb, Mq, gx);
 }
 
 }  // namespace

@@ -78,70 +78,10 @@ __device__ __forceinline__ int64_t sat_mul(int64_t a, int64_t b) {
   return v < kInfCost ? v : kInfCost;
 }
 
-__device__ __forceinline__ int64_t pow_int(int64_t D, int e) {
-  int64_t v = 1;
-  for (int i = 0; i < e; ++i) v = sat_mul(v, D);
-  return v;
-}
-
 __device__ __forceinline__ double need_fn(double E, double WR, double L, double W, double eps) {
   if (E == 0.0) return -WR;
   if (L == 0.0) return INFINITY;
   return (W * E) / (eps * L) - WR;
-}
-
-// Figure 6: smallest feasible order per method, then the cheapest by the
-// cost model, first minimum in the order DH, DL, H2L, DIRECT.
-__device__ void best_method(const DecideConst& c, double maxerr, double WR, double g, double rQ,
-                            double rR, int64_t NQ, int64_t NR, int* code, int* p_out, double* E_out) {
-  constexpr double kSqrt2 = 1.4142135623730951;
-  int pf[3] = {0, 0, 0};
-  double Ef[3] = {0.0, 0.0, 0.0};
-  for (int p = 1; p <= c.P && (c.fmm_mask & 1); ++p) {
-    const double E = ((WR * g) * c.bconst[p]) * powi(rR, p);
-    if (E <= maxerr) {
-      pf[0] = p;
-      Ef[0] = E;
-      break;
-    }
-  }
-  for (int p = 1; p <= c.P && (c.fmm_mask & 2); ++p) {
-    const double E = ((WR * g) * c.bconst[p]) * powi(rQ, p);
-    if (E <= maxerr) {
-      pf[1] = p;
-      Ef[1] = E;
-      break;
-    }
-  }
-  for (int p = 1; p <= c.P && (c.fmm_mask & 4); ++p) {
-    const double sq = kSqrt2 * rQ;
-    const double itail = sq <= 1.0 ? 1.0 : powi(sq, p - 1);
-    const double second = (powi(kSqrt2 * rR, p) * c.binomD[p]) * itail;
-    const double E = ((WR * g) * c.bconst[p]) * (powi(rQ, p) + second);
-    if (E <= maxerr) {
-      pf[2] = p;
-      Ef[2] = E;
-      break;
-    }
-  }
-  int64_t cost[4];
-  cost[0] = pf[0] ? sat_mul(NQ, pow_int(c.D, pf[0] + 1)) : kInfCost;
-  cost[1] = pf[1] ? sat_mul(NR, pow_int(c.D, pf[1] + 1)) : kInfCost;
-  cost[2] = pf[2] ? pow_int(c.D, 2 * pf[2] + 1) : kInfCost;
-  cost[3] = sat_mul(c.D, sat_mul(NQ, NR));
-  int64_t best = cost[0];
-  for (int i = 1; i < 4; ++i) best = cost[i] < best ? cost[i] : best;
-  for (int i = 0; i < 3; ++i) {
-    if (cost[i] == best && pf[i]) {
-      *code = DH + i;
-      *p_out = pf[i];
-      *E_out = Ef[i];
-      return;
-    }
-  }
-  *code = -1;
-  *p_out = 0;
-  *E_out = INFINITY;
 }
 
 __device__ __forceinline__ void box_dist2(const double* loQ, const double* hiQ, const double* loR,
@@ -162,109 +102,303 @@ __device__ __forceinline__ void box_dist2(const double* loQ, const double* hiQ, 
   *dmax2 = smax;
 }
 
-__global__ void decide_kernel(int S, FrontierLevel cur, TreeView qt, TreeView rt,
-                              const double* __restrict__ inv2h2, const double* __restrict__ inv4h2,
-                              const double* __restrict__ invh, int nQ, DecideConst c,
-                              double* __restrict__ s_kmax, double* __restrict__ s_dmin2,
-                              int8_t* __restrict__ code_out, int8_t* __restrict__ p_out,
-                              double* __restrict__ Gest, SegCount* __restrict__ cnt,
-                              unsigned long long* __restrict__ hcount,
-                              unsigned long long* __restrict__ base_evals) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Broadcast of lane j's value to the whole wave (v_readlane: register to
+// register, no memory round trip).  j must be wave-uniform.
+__device__ __forceinline__ int rl(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ double rl(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Smallest double a with fl(a / W) >= m (W > 0): correctly rounded division is
+// monotone, so fl(a / W) >= m exactly when a >= astar.  -INFINITY if the search
+// does not settle within a few units in the last place (the caller then
+// divides), +INFINITY for m = +INFINITY.
+__device__ double division_threshold(double m, double W) {
+  if (!(m < INFINITY)) return INFINITY;
+  double a = m * W;
+  if (a / W >= m) {
+    for (int it = 0; it < 64; ++it) {
+      const double b = nextafter(a, -INFINITY);
+      if (b / W >= m)
+        a = b;
+      else
+        return a;
+    }
+  } else {
+    for (int it = 0; it < 64; ++it) {
+      a = nextafter(a, INFINITY);
+      if (a / W >= m) return a;
+    }
+  }
+  return -INFINITY;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wave per segment, 64 pairs at a time, one pair per lane.
+//
+// Every quantity of a pair that does not depend on the token is computed by
+// its lane, in parallel, and stays in that lane's registers: K(dmax), the
+// finite-difference value and its token need, the bounds E_DH, E_DL, E_H2L of
+// every order as prefix minima PM_X[p] = min(E_X(1..p)) (the first order whose
+// bound meets maxerr is the first p with PM_X[p] <= maxerr, and there
+// E_X(p) = PM_X[p]), and mstar, the smallest maxerr at which some series
+// method beats DIRECT: the cost model of Figure 6 grows with the order, so
+// method X can win only at an order p with c_X(p) <= c_Direct, and it reaches
+// one exactly when PM_X[pmax_X] <= maxerr.  Below mstar the choice is DIRECT
+// whatever the token, and "maxerr >= mstar" is tested without a division as
+// "(eps (W_R + t)) L >= astar" (see division_threshold).
+//
+// The token rule (Figures 6-7) then walks the pairs in order with the whole
+// wave in lockstep, reading pair j's values from lane j by register broadcast;
+// the per-method order search runs on lane j itself.  The lower bound L, the
+// finite-difference sum Gest_Q and Lpush_Q are summed in pair order the same
+// way; counters are wave reductions.  Every expression and its operation
+// order is that of the single-threaded formulation, so the decisions and sums
+// are identical to it.
+template <int P>
+__global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, TreeView qt,
+                                                    TreeView rt, const double* __restrict__ inv2h2,
+                                                    const double* __restrict__ inv4h2,
+                                                    const double* __restrict__ invh, int nQ,
+                                                    DecideConst c, int8_t* __restrict__ code_out,
+                                                    int8_t* __restrict__ p_out,
+                                                    double* __restrict__ Gest,
+                                                    SegCount* __restrict__ cnt,
+                                                    unsigned long long* __restrict__ hcount,
+                                                    unsigned long long* __restrict__ base_evals) {
+  constexpr double kSqrt2 = 1.4142135623730951;
+  const int s = blockIdx.x;
   if (s >= S) return;
+  const int lane = threadIdx.x;
   const int h = cur.h[s];
   const int Q = cur.Q[s];
   const int off = cur.off[s];
   const int len = cur.len[s];
-  double t = cur.T[s];
-  double Lp = cur.Lp[s];
   const int D = c.D;
   const double* loQ = qt.lo + (int64_t)Q * D;
   const double* hiQ = qt.hi + (int64_t)Q * D;
   const double i2 = inv2h2[h], i4 = inv4h2[h], ih = invh[h];
   const bool qleaf = qt.left[Q] < 0;
   const int64_t NQ = qt.count[Q];
+  const double rQ = qt.rinf[Q] * ih;
 
-  // Lower bound on G over Q.
-  double L = Lp;
-  for (int j = 0; j < len; ++j) {
-    const int R = cur.R[off + j];
-    double dmin2, dmax2;
-    box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
-    const double km = own_exp(-dmax2 * i2);
-    s_kmax[off + j] = km;
-    s_dmin2[off + j] = dmin2;
-    L = L + rt.W[R] * km;
+  // Lower bound L over Q, summed in pair order.
+  double L = cur.Lp[s];
+  for (int b0 = 0; b0 < len; b0 += 64) {
+    const int n = len - b0 < 64 ? len - b0 : 64;
+    double lterm = 0.0;
+    if (lane < n) {
+      const int R = cur.R[off + b0 + lane];
+      double dmin2, dmax2;
+      box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
+      lterm = rt.W[R] * own_exp(-dmax2 * i2);
+    }
+    for (int j = 0; j < n; ++j) L = L + rl(lterm, j);
   }
   if (c.mono && qt.wmin[Q] > L) L = qt.wmin[Q];
 
-  SegCount sc;
-  for (int k = 0; k < 10; ++k) sc.v[k] = 0;
-  int nchild = 0;
+  double t = cur.T[s];
+  double Lp = cur.Lp[s];
   double gest = 0.0;
   bool any_fd = false;
-  int counts[6] = {0, 0, 0, 0, 0, 0};
-  int64_t bevals = 0;
-  for (int j = 0; j < len; ++j) {
-    const int R = cur.R[off + j];
-    const double WR = rt.W[R];
-    const double km = s_kmax[off + j];
-    const double dmin2 = s_dmin2[off + j];
-    const double kmin = own_exp(-dmin2 * i2);
-    const double efd = 0.5 * (WR * (kmin - km));
-    const double nd = need_fn(efd, WR, L, c.Wtot, c.eps_alg);
-    int cd = -1, p = 0;
-    if (nd <= (c.use_tokens ? t : 0.0)) {
-      if (c.use_tokens) t = t - nd;
-      if (!any_fd) {
-        gest = Gest[(int64_t)h * nQ + Q];
-        any_fd = true;
+  int nFD = 0, nDH = 0, nDL = 0, nH2L = 0, nBASE = 0, nSPLIT = 0, nchild = 0;
+  long long bevals = 0;
+  for (int b0 = 0; b0 < len; b0 += 64) {
+    const int n = len - b0 < 64 ? len - b0 : 64;
+    double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY;
+    int NR = 0, rleaf = 0;
+    double pm0[P], pm1[P], pm2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) pm0[p] = pm1[p] = pm2[p] = INFINITY;
+    if (lane < n) {
+      const int R = cur.R[off + b0 + lane];
+      double dmin2, dmax2;
+      box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
+      const double kmax = own_exp(-dmax2 * i2);
+      const double kmin = own_exp(-dmin2 * i2);
+      WR = rt.W[R];
+      NR = rt.count[R];
+      rleaf = rt.left[R] < 0 ? 1 : 0;
+      lterm = WR * kmax;
+      fdval = 0.5 * (WR * (kmin + kmax));
+      nd = need_fn(0.5 * (WR * (kmin - kmax)), WR, L, c.Wtot, c.eps_alg);
+      if (c.use_fmm) {
+        const double g = own_exp(-dmin2 * i4);
+        const double rR = rt.rinf[R] * ih;
+        const double base_e = WR * g;
+        double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY;
+#pragma unroll
+        for (int p = 1; p <= P; ++p) {
+          const double bc = base_e * c.bconst[p];
+          const double e0 = (c.fmm_mask & 1) ? bc * powi(rR, p) : INFINITY;
+          const double e1 = (c.fmm_mask & 2) ? bc * powi(rQ, p) : INFINITY;
+          double e2 = INFINITY;
+          if (c.fmm_mask & 4) {
+            const double sq = kSqrt2 * rQ;
+            const double itail = sq <= 1.0 ? 1.0 : powi(sq, p - 1);
+            const double second = (powi(kSqrt2 * rR, p) * c.binomD[p]) * itail;
+            e2 = bc * (powi(rQ, p) + second);
+          }
+          m0 = e0 < m0 ? e0 : m0;
+          m1 = e1 < m1 ? e1 : m1;
+          m2 = e2 < m2 ? e2 : m2;
+          pm0[p - 1] = m0;
+          pm1[p - 1] = m1;
+          pm2[p - 1] = m2;
+        }
+        const int64_t cdir = sat_mul(c.D, sat_mul(NQ, (int64_t)NR));
+        double mstar = INFINITY;
+#pragma unroll
+        for (int p = 1; p <= P; ++p) {
+          if (sat_mul(NQ, c.powD[p + 1]) <= cdir) mstar = pm0[p - 1] < mstar ? pm0[p - 1] : mstar;
+          if (sat_mul((int64_t)NR, c.powD[p + 1]) <= cdir)
+            mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
+          if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
+        }
+        astar = division_threshold(mstar, c.Wtot);
       }
-      gest = gest + 0.5 * (WR * (kmin + km));
-      cd = FD;
-    } else if (c.use_fmm) {
-      const double tt = c.use_tokens ? t : 0.0;
-      const double maxerr = ((c.eps_alg * (WR + tt)) * L) / c.Wtot;
-      const double g = own_exp(-dmin2 * i4);
-      double E;
-      best_method(c, maxerr, WR, g, qt.rinf[Q] * ih, rt.rinf[R] * ih, NQ, rt.count[R], &cd, &p, &E);
-      if (cd >= 0) {
-        if (c.use_tokens) t = t - need_fn(E, WR, L, c.Wtot, c.eps_alg);
+    }
+    // The token rule, pair by pair, the wave in lockstep.
+    int my_code = -1, my_p = 0;
+    for (int j = 0; j < n; ++j) {
+      const double ndj = rl(nd, j);
+      int cd;
+      int p = 0;
+      if (ndj <= (c.use_tokens ? t : 0.0)) {
+        if (c.use_tokens) t = t - ndj;
+        cd = FD;
       } else {
-        p = 0;
+        cd = -1;
+        const double WRj = rl(WR, j);
+        const double tt = c.use_tokens ? t : 0.0;
+        const double a = (c.eps_alg * (WRj + tt)) * L;
+        if (c.use_fmm && a >= rl(astar, j)) {
+          const double maxerr = a / c.Wtot;
+          int q0 = 0, q1 = 0, q2 = 0;
+          double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+          if (lane == j) {
+            int a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+              a0 += pm0[pp] > maxerr ? 1 : 0;
+              a1 += pm1[pp] > maxerr ? 1 : 0;
+              a2 += pm2[pp] > maxerr ? 1 : 0;
+            }
+            q0 = a0 < P ? a0 + 1 : 0;
+            q1 = a1 < P ? a1 + 1 : 0;
+            q2 = a2 < P ? a2 + 1 : 0;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+              if (pp + 1 == q0) e0 = pm0[pp];
+              if (pp + 1 == q1) e1 = pm1[pp];
+              if (pp + 1 == q2) e2 = pm2[pp];
+            }
+          }
+          q0 = rl(q0, j);
+          q1 = rl(q1, j);
+          q2 = rl(q2, j);
+          const int64_t NRj = rl(NR, j);
+          const int64_t c0 = q0 ? sat_mul(NQ, c.powD[q0 + 1]) : kInfCost;
+          const int64_t c1 = q1 ? sat_mul(NRj, c.powD[q1 + 1]) : kInfCost;
+          const int64_t c2 = q2 ? c.powD[2 * q2 + 1] : kInfCost;
+          const int64_t c3 = sat_mul(c.D, sat_mul(NQ, NRj));
+          int64_t best = c0 < c1 ? c0 : c1;
+          best = c2 < best ? c2 : best;
+          best = c3 < best ? c3 : best;
+          double Esel = 0.0;
+          if (q0 && c0 == best) {
+            cd = DH;
+            p = q0;
+            Esel = rl(e0, j);
+          } else if (q1 && c1 == best) {
+            cd = DL;
+            p = q1;
+            Esel = rl(e1, j);
+          } else if (q2 && c2 == best) {
+            cd = H2L;
+            p = q2;
+            Esel = rl(e2, j);
+          }
+          if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, c.Wtot, c.eps_alg);
+        }
+        if (cd < 0) {
+          if (qleaf && rl(rleaf, j)) {
+            if (c.use_tokens) t = t + WRj;
+            cd = BASE;
+          } else {
+            cd = SPLIT;
+          }
+        }
+      }
+      if (lane == j) {
+        my_code = cd;
+        my_p = p;
       }
     }
-    const bool rleaf = rt.left[R] < 0;
-    if (cd < 0) {
-      if (qleaf && rleaf) {
-        if (c.use_tokens) t = t + WR;
-        cd = BASE;
-        bevals += NQ * (int64_t)rt.count[R];
-      } else {
-        cd = SPLIT;
+    // Order-dependent sums of the chunk, in pair order.
+    for (int j = 0; j < n; ++j) {
+      const int cj = rl(my_code, j);
+      if (cj == FD) {
+        if (!any_fd) {
+          gest = Gest[(int64_t)h * nQ + Q];
+          any_fd = true;
+        }
+        gest = gest + rl(fdval, j);
       }
+      if (cj != SPLIT) Lp = Lp + rl(lterm, j);
     }
-    if (cd == SPLIT) {
-      nchild += rleaf ? 1 : 2;
-    } else {
-      Lp = Lp + WR * km;
-      if (cd != FD) sc.v[2 + (cd - DH)] += 1;
+    // Counters.
+    const bool act = lane < n;
+    nFD += wave_sum_int(act && my_code == FD);
+    nDH += wave_sum_int(act && my_code == DH);
+    nDL += wave_sum_int(act && my_code == DL);
+    nH2L += wave_sum_int(act && my_code == H2L);
+    nBASE += wave_sum_int(act && my_code == BASE);
+    nSPLIT += wave_sum_int(act && my_code == SPLIT);
+    nchild += wave_sum_int(act && my_code == SPLIT ? (rleaf ? 1 : 2) : 0);
+    bevals += wave_sum_ll(act && my_code == BASE ? (long long)NQ * NR : 0ll);
+    if (act) {
+      code_out[off + b0 + lane] = (int8_t)my_code;
+      p_out[off + b0 + lane] = (int8_t)my_p;
     }
-    counts[cd] += 1;
-    code_out[off + j] = (int8_t)cd;
-    p_out[off + j] = (int8_t)p;
   }
+  if (lane != 0) return;
   if (any_fd) Gest[(int64_t)h * nQ + Q] = gest;
   cur.T[s] = t;
   cur.Lp[s] = Lp;
-  if (nchild > 0) {
-    sc.v[1] = qleaf ? 1 : 2;
-    sc.v[0] = nchild * sc.v[1];
-  }
-  for (int k = 0; k < 4; ++k) sc.v[6 + k] = sc.v[2 + k] > 0 ? 1 : 0;
+  SegCount sc;
+  sc.v[1] = nchild > 0 ? (qleaf ? 1 : 2) : 0;
+  sc.v[0] = nchild * sc.v[1];
+  sc.v[2] = nDH;
+  sc.v[3] = nDL;
+  sc.v[4] = nH2L;
+  sc.v[5] = nBASE;
+  sc.v[6] = nDH > 0;
+  sc.v[7] = nDL > 0;
+  sc.v[8] = nH2L > 0;
+  sc.v[9] = nBASE > 0;
   cnt[s] = sc;
-  for (int k = 0; k < 6; ++k)
-    if (counts[k]) atomicAdd(&hcount[h * 6 + k], (unsigned long long)counts[k]);
+  unsigned long long* hc = hcount + h * 6;
+  if (nFD) atomicAdd(&hc[FD], (unsigned long long)nFD);
+  if (nDH) atomicAdd(&hc[DH], (unsigned long long)nDH);
+  if (nDL) atomicAdd(&hc[DL], (unsigned long long)nDL);
+  if (nH2L) atomicAdd(&hc[H2L], (unsigned long long)nH2L);
+  if (nBASE) atomicAdd(&hc[BASE], (unsigned long long)nBASE);
+  if (nSPLIT) atomicAdd(&hc[SPLIT], (unsigned long long)nSPLIT);
   if (bevals) atomicAdd(base_evals, (unsigned long long)bevals);
 }
 
@@ -276,13 +410,32 @@ struct SegCountPlus {
   }
 };
 
-__global__ void emit_kernel(int S, FrontierLevel cur, FrontierLevel nxt,
-                            const int32_t* __restrict__ qleft, const int32_t* __restrict__ rleft,
-                            const int8_t* __restrict__ code, const int8_t* __restrict__ porder,
-                            const SegCount* __restrict__ cnt, const SegCount* __restrict__ incl,
-                            WorkLists wl, LevelOffsets base) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Exclusive prefix sum over the 64 lanes of a wave; *total receives the sum.
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+  const int lane = threadIdx.x & 63;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// One wave per segment: next-level segments and pairs (children in the same
+// left-to-right order) and typed work entries, positions by wave prefix sums.
+__global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, FrontierLevel nxt,
+                                                  const int32_t* __restrict__ qleft,
+                                                  const int32_t* __restrict__ rleft,
+                                                  const int8_t* __restrict__ code,
+                                                  const int8_t* __restrict__ porder,
+                                                  const SegCount* __restrict__ cnt,
+                                                  const SegCount* __restrict__ incl, WorkLists wl,
+                                                  LevelOffsets base) {
+  const int s = blockIdx.x;
   if (s >= S) return;
+  const int lane = threadIdx.x;
   const SegCount own = cnt[s];
   const SegCount in = incl[s];
   int ex[10];
@@ -295,38 +448,45 @@ __global__ void emit_kernel(int S, FrontierLevel cur, FrontierLevel nxt,
   const int nsegs = own.v[1];
   const int nch = nsegs ? own.v[0] / nsegs : 0;
   const int pb = ex[0];
-  if (nsegs) {
-    const int sb = ex[1];
-    const double T = cur.T[s], Lp = cur.Lp[s];
-    for (int k = 0; k < nsegs; ++k) {
-      nxt.h[sb + k] = h;
-      nxt.Q[sb + k] = qleaf ? Q : qleft[Q] + k;
-      nxt.off[sb + k] = pb + k * nch;
-      nxt.len[sb + k] = nch;
-      nxt.T[sb + k] = T;
-      nxt.Lp[sb + k] = Lp;
-    }
+  const int sb = ex[1];
+  if (lane < nsegs) {
+    nxt.h[sb + lane] = h;
+    nxt.Q[sb + lane] = qleaf ? Q : qleft[Q] + lane;
+    nxt.off[sb + lane] = pb + lane * nch;
+    nxt.len[sb + lane] = nch;
+    nxt.T[sb + lane] = cur.T[s];
+    nxt.Lp[sb + lane] = cur.Lp[s];
   }
   int eb[4];
   for (int x = 0; x < 4; ++x) {
     eb[x] = base.ent[x] + ex[2 + x];
-    if (own.v[2 + x] > 0) wl.grp[x][base.grp[x] + ex[6 + x]] = make_int4(h, Q, eb[x], own.v[2 + x]);
+    if (lane == 0 && own.v[2 + x] > 0)
+      wl.grp[x][base.grp[x] + ex[6 + x]] = make_int4(h, Q, eb[x], own.v[2 + x]);
   }
   int kc = 0;
-  for (int j = 0; j < len; ++j) {
-    const int cd = code[off + j];
-    const int R = cur.R[off + j];
-    if (cd == SPLIT) {
-      const int rl = rleft[R];
-      const int nk = rl < 0 ? 1 : 2;
-      for (int u = 0; u < nk; ++u) {
-        const int kid = rl < 0 ? R : rl + u;
-        for (int k = 0; k < nsegs; ++k) nxt.R[pb + k * nch + kc] = kid;
-        ++kc;
+  for (int b0 = 0; b0 < len; b0 += 64) {
+    const bool act = b0 + lane < len;
+    const int cd = act ? code[off + b0 + lane] : -1;
+    const int R = act ? cur.R[off + b0 + lane] : 0;
+    const int rl = act ? rleft[R] : -1;
+    const int nk = cd == SPLIT ? (rl < 0 ? 1 : 2) : 0;
+    int tot;
+    const int kp = wave_excl_scan(nk, &tot);
+    for (int u = 0; u < nk; ++u) {
+      const int kid = rl < 0 ? R : rl + u;
+      for (int k = 0; k < nsegs; ++k) {
+        const int o = pb + k * nch + kc + kp + u;
+        nxt.R[o] = kid;
+        nxt.seg[o] = sb + k;
       }
-    } else if (cd != FD) {
-      const int x = cd - DH;
-      wl.ent[x][eb[x]++] = (R << 4) | porder[off + j];
+    }
+    kc += tot;
+    for (int x = 0; x < 4; ++x) {
+      const int f = cd == DH + x ? 1 : 0;
+      int tx;
+      const int ep = wave_excl_scan(f, &tx);
+      if (f) wl.ent[x][eb[x] + ep] = (R << 4) | porder[off + b0 + lane];
+      eb[x] += tx;
     }
   }
 }
@@ -335,14 +495,22 @@ __global__ void emit_kernel(int S, FrontierLevel cur, FrontierLevel nxt,
 
 hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
-                         const DecideConst& c, double* scratch_kmax, double* scratch_dmin2,
-                         int8_t* code, int8_t* porder, double* Gest, SegCount* cnt,
-                         unsigned long long* hcount, unsigned long long* base_evals,
-                         float* policy_feat, hipStream_t s) {
-  (void)policy_feat;
-  hipLaunchKernelGGL(decide_kernel, dim3((unsigned)ceil_div(S, 64)), dim3(64), 0, s, S, cur, qt, rt,
-                     inv2h2, inv4h2, invh, nQ, c, scratch_kmax, scratch_dmin2, code, porder, Gest,
-                     cnt, hcount, base_evals);
+                         const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
+                         SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
+                         hipStream_t s) {
+#define GS_DECIDE(PP)                                                                           \
+  case PP:                                                                                     \
+    hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)S), dim3(64), 0, s, S, cur, qt, rt,   \
+                       inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, hcount,           \
+                       base_evals);                                                            \
+    break;
+  switch (c.P) {
+    GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)
+    GS_DECIDE(6) GS_DECIDE(7) GS_DECIDE(8) GS_DECIDE(9) GS_DECIDE(10)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GS_DECIDE
   return hipGetLastError();
 }
 
@@ -366,8 +534,8 @@ hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt
                        const int32_t* qleft, const int32_t* rleft, const int8_t* code,
                        const int8_t* porder, const SegCount* cnt, const SegCount* incl,
                        const WorkLists& wl, LevelOffsets base, hipStream_t s) {
-  hipLaunchKernelGGL(emit_kernel, dim3((unsigned)ceil_div(S, 64)), dim3(64), 0, s, S, cur, nxt,
-                     qleft, rleft, code, porder, cnt, incl, wl, base);
+  hipLaunchKernelGGL(emit_kernel, dim3((unsigned)S), dim3(64), 0, s, S, cur, nxt, qleft, rleft,
+                     code, porder, cnt, incl, wl, base);
   return hipGetLastError();
 }
 

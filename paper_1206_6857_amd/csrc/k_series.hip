@@ -153,7 +153,9 @@ __global__ __launch_bounds__(kW) void dh_kernel(SeriesTables T, const int4* __re
   const double s = sc[h];
   const int qb = qt.begin[Q], qn = qt.count[Q];
   const int lane = threadIdx.x;
-  for (int base = 0; base < qn; base += kW) {
+  {
+    const int base = blockIdx.y * kW;
+    if (base >= qn) return;
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
     double acc = 0.0;
@@ -423,13 +425,14 @@ hipError_t launch_h2h_level(const SeriesTables& T, const NodeView& t, int lb, in
   return hipGetLastError();
 }
 
-hipError_t launch_dh_level(const SeriesTables& T, const int4* grp, int ng, const int32_t* ent,
-                           const NodeView& qt, const NodeView& rt, const double* xq_perm,
-                           const double* M, const double* sc, int Mq, double* gdh, hipStream_t s) {
+hipError_t launch_dh_level(const SeriesTables& T, const int4* grp, int ng, int max_q,
+                           const int32_t* ent, const NodeView& qt, const NodeView& rt,
+                           const double* xq_perm, const double* M, const double* sc, int Mq,
+                           double* gdh, hipStream_t s) {
   if (ng == 0) return hipSuccess;
   const size_t lds = (size_t)(kW * T.D * T.P + T.C) * sizeof(double);
-  hipLaunchKernelGGL(dh_kernel, dim3(ng), dim3(kW), lds, s, T, grp, ng, ent, qt, rt, xq_perm, M, sc,
-                     Mq, gdh);
+  hipLaunchKernelGGL(dh_kernel, dim3(ng, (unsigned)ceil_div(max_q, kW)), dim3(kW), lds, s, T, grp, ng,
+                     ent, qt, rt, xq_perm, M, sc, Mq, gdh);
   return hipGetLastError();
 }
 

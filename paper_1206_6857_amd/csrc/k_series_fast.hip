@@ -1,0 +1,278 @@
+// Direct Hermite evaluation (DH) and direct local accumulation (DL) kernels
+// specialised at compile time for the (dimension, order limit) pairs of the
+// order-limit table (section 6), in double precision.
+//
+// With the multi-index set fixed at compile time (graded order, decreasing
+// lexicographic inside a degree, built by a constexpr enumerator), the sums
+// over multi-indices unroll completely: Hermite polynomial values stay in
+// registers and every index into them is a constant.  Both kernels use
+// h_a(t) = exp(-|t|^2) prod_d H_{a_d}(t_d), so one exponential serves all
+// dimensions of a point.
+//
+//   DH:  gdh[h][q] += sum_{|a|<p} M_a s^{|a|} h_a((x_q - x_R) s)   (one wave per
+//        group of a traversal level, lanes over the points of Q)
+//   DL:  lco[h][Q][b] += sum_{r in R} w_r/b! h_b((x_r - x_Q) s)    (one wave per
+//        run of a (h, Q) key, lanes over the points of R, per-lane partial
+//        coefficients reduced across the wave once per run)
+#include "gs_series.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kW = 64;
+constexpr int kWavesPerBlock = 4;
+
+constexpr int cbinom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long long c = 1;
+  for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
+  return (int)c;
+}
+
+constexpr double cfact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= (double)i;
+  return f;
+}
+
+// Graded multi-index set |a| < P in the library's order.
+template <int D, int P>
+struct MultiIndex {
+  static constexpr int C = cbinom(D + P - 1, D);
+  int a[C][D];
+  int deg[C];
+  double invf[C];
+  int nterms[P + 1];
+  constexpr MultiIndex() : a(), deg(), invf(), nterms() {
+    int idx = 0;
+    for (int g = 0; g < P; ++g) {
+      int cur[D] = {};
+      cur[0] = g;
+      while (true) {
+        double f = 1.0;
+        for (int d = 0; d < D; ++d) {
+          a[idx][d] = cur[d];
+          f *= cfact(cur[d]);
+        }
+        deg[idx] = g;
+        invf[idx] = 1.0 / f;
+        ++idx;
+        int i = D - 2;
+        while (i >= 0 && cur[i] == 0) --i;
+        if (i < 0) break;
+        cur[i] -= 1;
+        int rest = 1;
+        for (int k = i + 1; k < D; ++k) {
+          rest += cur[k];
+          cur[k] = 0;
+        }
+        cur[i + 1] = rest;
+      }
+    }
+    for (int p = 0; p <= P; ++p) nterms[p] = cbinom(D + p - 1, D);
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kW);
+  return v;
+}
+
+// Physicists' Hermite polynomials H_0..H_{P-1}(t).
+template <int P>
+__device__ __forceinline__ void hermite_polys(double t, double* H) {
+  H[0] = 1.0;
+  if (P > 1) H[1] = 2.0 * t;
+#pragma unroll
+  for (int k = 1; k + 1 < P; ++k) H[k + 1] = 2.0 * t * H[k] - 2.0 * k * H[k - 1];
+}
+
+// grid.x: groups (kWavesPerBlock per block), grid.y: 64-point chunks of Q.
+template <int D, int P>
+__global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
+    const int4* __restrict__ grp, int ng, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
+    const double* __restrict__ xq_perm, const double* __restrict__ M, const double* __restrict__ sc,
+    int Mq, double* __restrict__ gdh) {
+  constexpr MultiIndex<D, P> mi{};
+  constexpr int C = MultiIndex<D, P>::C;
+  const int lane = threadIdx.x % kW;
+  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  if (i >= ng) return;
+  const int4 gr = grp[i];
+  const int h = gr.x, Q = gr.y;
+  const int qb = qt.begin[Q], qn = qt.count[Q];
+  const int base = blockIdx.y * kW;
+  if (base >= qn) return;
+  const double s = sc[h];
+  double spow[P];
+  spow[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k < P; ++k) spow[k] = spow[k - 1] * s;
+  const bool active = base + lane < qn;
+  const int qpos = qb + base + (active ? lane : 0);
+  double x[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = xq_perm[(int64_t)qpos * D + d];
+  double acc = 0.0;
+  for (int e = gr.z; e < gr.z + gr.w; ++e) {
+    const int R = ent[e] >> 4, p = ent[e] & 15;
+    int nt = 0;
+#pragma unroll
+    for (int k = 0; k <= P; ++k)
+      if (k == p) nt = mi.nterms[k];
+    const double* cR = rt.ctr + (int64_t)R * D;
+    double H[D][P];
+    double tt = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double t = (x[d] - cR[d]) * s;
+      tt += t * t;
+      hermite_polys<P>(t, H[d]);
+    }
+    const double* m = M + (int64_t)R * C;
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      if (a < nt) {
+        double term = m[a] * spow[mi.deg[a]];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if (mi.a[a][d]) term *= H[d][mi.a[a][d]];
+        v += term;
+      }
+    }
+    acc += v * exp(-tt);
+  }
+  if (active) gdh[(int64_t)h * Mq + qpos] += acc;
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
+    SortedGroups g, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
+    const double* __restrict__ xr_perm, const double* __restrict__ wr_perm,
+    const double* __restrict__ sc, int nQ, double* __restrict__ lco, int32_t* __restrict__ pL) {
+  constexpr MultiIndex<D, P> mi{};
+  constexpr int C = MultiIndex<D, P>::C;
+  const int lane = threadIdx.x % kW;
+  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  if (i >= g.n || (i > 0 && g.key[i] == g.key[i - 1])) return;
+  const int4 g0 = g.grp[g.order[i]];
+  const int h = g0.x, Q = g0.y;
+  const double s = sc[h];
+  double cQ[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) cQ[d] = qt.ctr[(int64_t)Q * D + d];
+  double B[C];
+#pragma unroll
+  for (int a = 0; a < C; ++a) B[a] = 0.0;
+  int pmax = 0;
+  for (int j = i; j < g.n && (j == i || g.key[j] == g.key[j - 1]); ++j) {
+    const int4 gr = g.grp[g.order[j]];
+    for (int e = gr.z; e < gr.z + gr.w; ++e) {
+      const int R = ent[e] >> 4, p = ent[e] & 15;
+      pmax = p > pmax ? p : pmax;
+      int nt = 0;
+#pragma unroll
+      for (int k = 0; k <= P; ++k)
+        if (k == p) nt = mi.nterms[k];
+      const int rb = rt.begin[R], rn = rt.count[R];
+      for (int base = 0; base < rn; base += kW) {
+        if (base + lane >= rn) continue;
+        const int pos = rb + base + lane;
+        double H[D][P];
+        double tt = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double t = (xr_perm[(int64_t)pos * D + d] - cQ[d]) * s;
+          tt += t * t;
+          hermite_polys<P>(t, H[d]);
+        }
+        const double ew = wr_perm[pos] * exp(-tt);
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          if (a < nt) {
+            double term = ew;
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+              if (mi.a[a][d]) term *= H[d][mi.a[a][d]];
+            B[a] += term;
+          }
+        }
+      }
+    }
+  }
+  double* out = lco + ((int64_t)h * nQ + Q) * C;
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    const double v = wave_sum(B[a]);
+    if (lane == 0) out[a] += v * mi.invf[a];
+  }
+  if (lane == 0) {
+    int32_t* pl = pL + (int64_t)h * nQ + Q;
+    *pl = pmax > *pl ? pmax : *pl;
+  }
+}
+
+template <int D, int P>
+void dh_launch(const int4* grp, int ng, int max_q, const int32_t* ent, const NodeView& qt,
+               const NodeView& rt, const double* xq, const double* M, const double* sc, int Mq,
+               double* gdh, hipStream_t s) {
+  hipLaunchKernelGGL((dh_fast_kernel<D, P>),
+                     dim3((unsigned)ceil_div(ng, kWavesPerBlock), (unsigned)ceil_div(max_q, kW)),
+                     dim3(kW * kWavesPerBlock), 0, s, grp, ng, ent, qt, rt, xq, M, sc, Mq, gdh);
+}
+
+template <int D, int P>
+void dl_launch(const SortedGroups& g, const int32_t* ent, const NodeView& qt, const NodeView& rt,
+               const double* xr, const double* wr, const double* sc, int nQ, double* lco, int32_t* pL,
+               hipStream_t s) {
+  hipLaunchKernelGGL((dl_fast_kernel<D, P>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),
+                     dim3(kW * kWavesPerBlock), 0, s, g, ent, qt, rt, xr, wr, sc, nQ, lco, pL);
+}
+
+// (D, P) pairs with a compiled specialisation.
+#define GS_FAST_CASES(X) \
+  X(1, 10) X(2, 8) X(3, 6) X(4, 5) X(5, 4) X(6, 2) X(7, 1) X(8, 1) X(16, 1)
+
+}  // namespace
+
+bool series_fast_available(int D, int P) {
+#define X(d, p) \
+  if (D == d && P == p) return true;
+  GS_FAST_CASES(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_dh_fast(int D, int P, const int4* grp, int ng, int max_q, const int32_t* ent,
+                          const NodeView& qt, const NodeView& rt, const double* xq_perm,
+                          const double* M, const double* sc, int Mq, double* gdh, hipStream_t s) {
+  if (ng == 0) return hipSuccess;
+#define X(d, p)                                                                   \
+  if (D == d && P == p) {                                                         \
+    dh_launch<d, p>(grp, ng, max_q, ent, qt, rt, xq_perm, M, sc, Mq, gdh, s);     \
+    return hipGetLastError();                                               \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+                          const NodeView& qt, const NodeView& rt, const double* xr_perm,
+                          const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
+                          hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+#define X(d, p)                                                                \
+  if (D == d && P == p) {                                                      \
+    dl_launch<d, p>(g, ent, qt, rt, xr_perm, wr_perm, sc, nQ, lco, pL, s);     \
+    return hipGetLastError();                                                  \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gs

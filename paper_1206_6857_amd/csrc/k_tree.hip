@@ -18,8 +18,9 @@
 // leaves hold their points in increasing original index.
 //
 // All values cached per node are exact or computed in a fixed order:
-// lo/hi are copies of coordinates, ctr = 0.5*(lo+hi), rinf = max|x-ctr| via an
-// order-independent max, leaf W is the sequential sum in permutation order,
+// lo/hi are copies of coordinates, ctr = 0.5*(lo+hi), rinf = max over points of
+// |x - ctr|_inf, which equals max_d max(|lo_d - ctr_d|, |hi_d - ctr_d|) and is
+// read off the box; leaf W is the sequential sum in permutation order,
 // internal W = W_left + W_right.
 #include <cstring>  // rocprim uses memset without including it
 #include <rocprim/rocprim.hpp>
@@ -40,28 +41,33 @@ __global__ void node_stats_kernel(int lb, int le, int D, int64_t n, const int32_
                                   const double* __restrict__ xs, const int32_t* __restrict__ begin,
                                   const int32_t* __restrict__ count, double* __restrict__ lo,
                                   double* __restrict__ hi, double* __restrict__ ctr,
-                                  int32_t* __restrict__ splitdim,
-                                  unsigned long long* __restrict__ rinf_bits) {
+                                  int32_t* __restrict__ splitdim, double* __restrict__ rinf) {
   const int i = lb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= le) return;
   const int64_t b = begin[i];
   const int64_t c = count[i];
   int best = 0;
   double bestext = -1.0;
+  double r = 0.0;
   for (int d = 0; d < D; ++d) {
     const double l = xs[(int64_t)d * n + lists[(int64_t)d * n + b]];
     const double h = xs[(int64_t)d * n + lists[(int64_t)d * n + b + c - 1]];
+    const double m = 0.5 * (l + h);
     lo[(int64_t)i * D + d] = l;
     hi[(int64_t)i * D + d] = h;
-    ctr[(int64_t)i * D + d] = 0.5 * (l + h);
+    ctr[(int64_t)i * D + d] = m;
     const double ext = h - l;
     if (ext > bestext) {
       bestext = ext;
       best = d;
     }
+    // max over the node's points of |x_d - m| is attained at x_d = lo or hi
+    const double a = fabs(l - m), e = fabs(h - m);
+    r = a > r ? a : r;
+    r = e > r ? e : r;
   }
   splitdim[i] = best;
-  rinf_bits[i] = 0ull;
+  rinf[i] = r;
 }
 
 // One workgroup: number the children of the level's split nodes.
@@ -106,13 +112,12 @@ __global__ __launch_bounds__(1024) void children_kernel(int lb, int le, int leaf
   if (threadIdx.x == 0) *n_children_out = 2 * carry;
 }
 
-// Per position of the level: radius, left/right assignment, next-level node.
-__global__ void mark_kernel(int64_t n, int D, const int32_t* __restrict__ lists,
-                            const double* __restrict__ xs, const int32_t* __restrict__ pos_node,
+// Per position of the level: left/right assignment and next-level node.
+__global__ void mark_kernel(int64_t n, const int32_t* __restrict__ lists,
+                            const int32_t* __restrict__ pos_node,
                             int32_t* __restrict__ pos_node_next, int32_t* __restrict__ leaf_of_pos,
                             const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
                             const int32_t* __restrict__ left, const int32_t* __restrict__ splitdim,
-                            const double* __restrict__ ctr, unsigned long long* __restrict__ rinf_bits,
                             int32_t* __restrict__ isleft) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -121,13 +126,6 @@ __global__ void mark_kernel(int64_t n, int D, const int32_t* __restrict__ lists,
     pos_node_next[i] = -1;
     return;
   }
-  const int32_t p = lists[(int64_t)D * n + i];
-  double r = 0.0;
-  for (int d = 0; d < D; ++d) {
-    const double a = fabs(xs[(int64_t)d * n + p] - ctr[(int64_t)node * D + d]);
-    r = a > r ? a : r;
-  }
-  atomicMax(&rinf_bits[node], (unsigned long long)__double_as_longlong(r));
   const int l = left[node];
   if (l >= 0) {
     const int64_t mid = (int64_t)begin[node] + count[node] / 2;
@@ -255,12 +253,11 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
     const int width = le - lb;
     hipLaunchKernelGGL(node_stats_kernel, dim3((unsigned)ceil_div(width, 256)), dim3(256), 0, s, lb,
                        le, D, n, lists, a.xs, t.begin, t.count, t.lo, t.hi, t.ctr, a.splitdim,
-                       (unsigned long long*)t.rinf);
+                       t.rinf);
     hipLaunchKernelGGL(children_kernel, dim3(1), dim3(1024), 0, s, lb, le, a.leaf_size, t.begin,
                        t.count, t.left, t.depth, a.n_children);
-    hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, D, lists, a.xs, pos, pos_alt,
-                       t.leaf_of_pos, t.begin, t.count, t.left, a.splitdim, t.ctr,
-                       (unsigned long long*)t.rinf, a.isleft);
+    hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, lists, pos, pos_alt,
+                       t.leaf_of_pos, t.begin, t.count, t.left, a.splitdim, a.isleft);
     int32_t nchild = 0;
     e = hipMemcpyAsync(&nchild, a.n_children, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 TOL_ROUND = 1e-4
 
 CASES = [
-    # (name, D, N, M (None: monochromatic), hs, leaf, method)
+    # (name, D, N, M (None: monochromatic), hs, leaf, method[, plimit])
     ("d1", 1, 900, None, [1e-3, 1e-2, 0.05, 0.3, 2.0], 16, "dito"),
     ("d2", 2, 1500, None, [1e-3, 1e-2, 0.03, 0.1, 0.3, 1.0, 10.0], 32, "dito"),
     ("d3", 3, 1500, None, [1e-3, 1e-2, 0.05, 0.2, 1.0], 32, "dito"),
@@ -35,6 +35,8 @@ CASES = [
     ("d3_bi", 3, 1100, 500, [0.02, 0.1, 0.5], 16, "dito"),
     ("d16_bi", 16, 900, 300, [0.05, 0.3, 2.0], 64, "dito"),
     ("d2_leaf64_ragged", 2, 1001, None, [0.02, 0.2], 64, "dito"),
+    ("d2_plimit5_generic", 2, 1200, None, [0.03, 0.1, 0.3], 32, "dito", 5),
+    ("d4_table", 4, 1000, None, [0.05, 0.2, 1.0], 32, "dito"),
 ]
 
 
@@ -45,13 +47,15 @@ def _inputs(D, N, M, seed):
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_dualtree_parity(case):
-    name, D, N, M, hs, leaf, method = case
+    name, D, N, M, hs, leaf, method = case[:7]
+    plimit = case[7] if len(case) > 7 else 0
     banner("dualtree", name)
     r, w, q = _inputs(D, N, M, 70 + D)
     hs = np.array(hs)
     c = ctx()
-    G = c.gauss_sum(q, r, w, hs, 0.01, method=method, leaf_size=leaf, keep_trace=1)
-    ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, method=method, trace=True)
+    G = c.gauss_sum(q, r, w, hs, 0.01, method=method, leaf_size=leaf, keep_trace=1, plimit=plimit)
+    ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, method=method, trace=True,
+                      plimit=plimit or None)
 
     # tree, bit-exact
     for which, t in ((0, ref.rtree), (1, ref.qtree)):
