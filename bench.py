@@ -35,8 +35,8 @@ EXP_SLOTS = 2.0
 
 
 def base_tile_model(D):
-    """Algorithmic FP32 work of one point-pair kernel evaluation in the base-case
-    and exhaustive tiles: D subtractions + D FMAs (squared distance), one FMA
+    """Algorithmic FP32 work of one point-pair kernel evaluation in the
+    exhaustive tiles: D subtractions + D FMAs (squared distance), one FMA
     (scaled exponent), one exp2, one FMA (weighted accumulation).
     Returns (flops per pair-eval, VALU issue slots per pair-eval)."""
     flops = D + 2 * D + 2 + 1 + 2
@@ -44,9 +44,21 @@ def base_tile_model(D):
     return flops, slots
 
 
+def fused_base_model(D, dist_evals, exp_evals):
+    """Algorithmic FP32 work of the bandwidth-fused base tiles: every point pair
+    of a regrouped entry forms its squared distance once (D subtractions, D
+    FMAs), and each bandwidth of the entry's mask costs one FMA (exponent), one
+    exp2 and one FMA (accumulation).  Returns (flops, VALU issue slots)."""
+    flops = dist_evals * 3 * D + exp_evals * 5
+    slots = dist_evals * 2 * D + exp_evals * (2 + EXP_SLOTS)
+    return flops, slots
+
+
+LANE_SLOTS_PER_S = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ
+
+
 def alu_peak_pairs_per_s(D):
-    lane_slots = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ
-    return lane_slots / base_tile_model(D)[1]
+    return LANE_SLOTS_PER_S / base_tile_model(D)[1]
 
 
 def cpu_baseline(wl, n_queries, seed=0):
@@ -109,7 +121,7 @@ def main():
         torch.cuda.synchronize()
         kms = np.zeros(8)
         kl = np.zeros(8, dtype=np.int64)
-        base_evals = 0
+        evals = np.zeros(2, dtype=np.int64)
         t0 = time.perf_counter()
         for _ in range(steps):
             ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, kernel_timing=1,
@@ -117,12 +129,13 @@ def main():
             st = ctx.stats()
             kms += np.array(st.k_ms[:])
             kl += np.array(st.k_launches[:])
-            base_evals += st.base_pair_evals
+            evals += (st.base_pair_evals, st.base_dist_evals)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / steps
-        return t, kms, kl, base_evals, ctx.stats()
+        return t, kms, kl, evals, ctx.stats()
 
-    t_dt, kms, kl, base_evals, st_dt = run("dualtree", args.steps, args.warmup)
+    t_dt, kms, kl, evals, st_dt = run("dualtree", args.steps, args.warmup)
+    base_evals, dist_evals = int(evals[0]), int(evals[1])
     pc = ctx.pair_counts(n_h)
     result = {
         "metric": "pair-evals/sec equiv. at eps=0.01, dual-tree vs GPU exhaustive; % of roofline",
@@ -142,18 +155,19 @@ def main():
                    "parallelism": "single-gpu"},
     }
 
-    # Dominant kernel of the dual-tree step: the base-case tiles (HIP events on
-    # the library's stream over the timed steps).
-    flops_pe, slots_pe = base_tile_model(D)
+    # Dominant kernel of the dual-tree step: the bandwidth-fused base tiles
+    # (HIP events on the library's stream around each launch, timed steps only).
     if kl[_lib.K_BASE] > 0:
-        avg_ms = kms[_lib.K_BASE] / kl[_lib.K_BASE]
-        evals_per_launch = base_evals / kl[_lib.K_BASE]
-        achieved = evals_per_launch * flops_pe / (avg_ms * 1e-3) / 1e12
-        peak = alu_peak_pairs_per_s(D) * flops_pe / 1e12
-        result["roofline"] = {"bound": "alu", "kernel": "base_kernel", "achieved": achieved,
+        n = kl[_lib.K_BASE]
+        avg_ms = kms[_lib.K_BASE] / n
+        flops, slots = fused_base_model(D, dist_evals / n, base_evals / n)
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        peak = LANE_SLOTS_PER_S * flops / slots / 1e12
+        result["roofline"] = {"bound": "alu", "kernel": "base_fused_kernel", "achieved": achieved,
                               "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                               "traffic": None, "avg_launch_ms": avg_ms,
-                              "pair_evals_per_launch": evals_per_launch}
+                              "pair_evals_per_launch": base_evals / n,
+                              "dist_evals_per_launch": dist_evals / n}
     result["breakdown_ms"] = {
         "stage": st_dt.t_stage_ms, "tree": st_dt.t_tree_ms, "moments": st_dt.t_moments_ms,
         "traverse": st_dt.t_traverse_ms, "work": st_dt.t_work_ms, "post": st_dt.t_post_ms,

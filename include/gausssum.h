@@ -75,9 +75,16 @@ typedef struct gs_options {
                                DH, bit 1 DL, bit 2 H2L; 0 or 7 allows all (ablations) */
   int32_t kernel_timing;    /* 1: time kernel classes with HIP events on the context's
                                stream (gs_stats.k_ms / k_launches) */
-  int32_t reserved0;
+  int32_t h_chunk;          /* most bandwidths traversed together (0: all); the
+                               library halves it by itself when a frontier outgrows
+                               2^30 pairs or device memory.  Results do not depend
+                               on it beyond floating-point summation order. */
   double eps_round_share;   /* share of eps reserved for floating-point rounding
                                (default 0.1); the pruning test uses (1-share)*eps */
+  int64_t max_frontier;     /* cap on the node pairs of one frontier level (bounds the
+                               traversal's memory; 0: 2^30).  A chunk of bandwidths whose
+                               frontier exceeds it is retried with half the bandwidths;
+                               GS_EOVERFLOW when one bandwidth alone exceeds it. */
 } gs_options;
 
 typedef struct gs_stats {
@@ -97,6 +104,10 @@ typedef struct gs_stats {
    * indexed by GS_K_*. */
   double k_ms[8];
   int64_t k_launches[8];
+  int64_t base_dist_evals;  /* point pairs whose squared distance the base tiles
+                               formed (one per pair for all bandwidths of a block) */
+  int32_t h_chunks;         /* bandwidth chunks the traversal was split into */
+  int32_t reserved1;
 } gs_stats;
 
 /* Kernel classes of gs_stats.k_ms. */

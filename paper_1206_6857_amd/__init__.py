@@ -89,7 +89,7 @@ class Context:
         queries may be the same object as refs (monochromatic).  Options:
         method ('dualtree', 'exhaustive', 'dfd', 'dfdo'), policy ('rule',
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
-        keep_trace, log_pairs, blocking."""
+        keep_trace, log_pairs, blocking, fmm_mask, kernel_timing, h_chunk."""
         lib = _lib.load()
         same = queries is refs
         r = _Arr(refs)

@@ -31,8 +31,8 @@ class GsOptions(ctypes.Structure):
                 ("policy", ctypes.c_int32), ("monochromatic", ctypes.c_int32),
                 ("blocking", ctypes.c_int32), ("keep_trace", ctypes.c_int32),
                 ("log_pairs", ctypes.c_int32), ("fmm_mask", ctypes.c_int32),
-                ("kernel_timing", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("eps_round_share", ctypes.c_double)]
+                ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
+                ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64)]
 
 
 class GsStats(ctypes.Structure):
@@ -45,7 +45,8 @@ class GsStats(ctypes.Structure):
                 ("t_moments_ms", ctypes.c_double), ("t_traverse_ms", ctypes.c_double),
                 ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 8),
-                ("k_launches", ctypes.c_int64 * 8)]
+                ("k_launches", ctypes.c_int64 * 8), ("base_dist_evals", ctypes.c_int64),
+                ("h_chunks", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS = range(7)
 
 

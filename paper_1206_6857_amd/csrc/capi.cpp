@@ -274,6 +274,8 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   if (opt.method != GS_EXHAUSTIVE && !(eps > 0.0 && eps < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps must be in (0, 1)");
   if (opt.leaf_size < 1 || opt.leaf_size > 1024) GS_FAIL(ctx, GS_EINVAL, "leaf_size must be in [1, 1024]");
+  if (opt.h_chunk < 0) GS_FAIL(ctx, GS_EINVAL, "h_chunk must be >= 0");
+  if (opt.max_frontier < 0) GS_FAIL(ctx, GS_EINVAL, "max_frontier must be >= 0");
   if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");
   if (opt.policy != GS_RULE && opt.policy != GS_LEARNED) GS_FAIL(ctx, GS_EINVAL, "unknown policy");

@@ -232,10 +232,11 @@ HostSeries make_series_tables(int D, int P) {
   return T;
 }
 
-__global__ void init_level0_kernel(int n_h, FrontierLevel f) {
+// Root pairs (h, root, root) of the bandwidths [h0, h0 + nh).
+__global__ void init_level0_kernel(int h0, int nh, FrontierLevel f) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_h) return;
-  f.h[k] = k;
+  if (k >= nh) return;
+  f.h[k] = h0 + k;
   f.Q[k] = 0;
   f.off[k] = k;
   f.len[k] = 1;
@@ -486,15 +487,19 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* lco = use_fmm ? BUF(double, "lco", (int64_t)n_h * nQ * C) : nullptr;
   double* gx = BUF(double, "gx", (int64_t)n_h * Mq);
   double* gdh = BUF(double, "gdh", (int64_t)n_h * Mq);
-  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 1);
+  // [n_h][6] decisions per type, then two per-chunk event counters: base
+  // point-pair evaluations and base distance evaluations.
+  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 2);
+  unsigned long long* chunk_ev = hcount + n_h * 6;
   DT_HIP(hipMemsetAsync(Gest, 0, sizeof(double) * n_h * nQ, st));
   DT_HIP(hipMemsetAsync(pL, 0, sizeof(int32_t) * n_h * nQ, st));
   if (lco) DT_HIP(hipMemsetAsync(lco, 0, sizeof(double) * n_h * nQ * C, st));
   DT_HIP(hipMemsetAsync(gx, 0, sizeof(double) * n_h * Mq, st));
   DT_HIP(hipMemsetAsync(gdh, 0, sizeof(double) * n_h * Mq, st));
-  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 1), st));
+  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 2), st));
+  float* rec = nullptr;  // base-case reference records, built on first use
+  bool rec_ready = false;
 
-  // 3. Traversal.
   TreeView qtv{qt.lo, qt.hi, qt.rinf, qt.W, qt.wmin, qt.count, qt.left};
   TreeView rtv{rt.lo, rt.hi, rt.rinf, rt.W, rt.wmin, rt.count, rt.left};
   auto level_bufs = [&](int which, int64_t nseg, int64_t npair, FrontierLevel& f) -> gs_status {
@@ -509,147 +514,284 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     f.seg = BUF(int32_t, p + "seg", npair);
     return GS_OK;
   };
-  FrontierLevel cur, nxt;
-  int64_t nseg = n_h, npair = n_h;
-  s = level_bufs(0, nseg, npair, cur);
-  if (s != GS_OK) return s;
-  hipLaunchKernelGGL(init_level0_kernel, dim3((unsigned)ceil_div(n_h, 64)), dim3(64), 0, st, n_h, cur);
-  DT_HIP(hipGetLastError());
-  WorkLists wl;
-  int64_t used_ent[4] = {0, 0, 0, 0}, used_grp[4] = {0, 0, 0, 0};
   const char* tname[4] = {"dh", "dl", "h2l", "base"};
-  for (int x = 0; x < 4; ++x) {
-    wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], 0, 1024);
-    wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], 0, 256);
-  }
-  int level = 0;
-  int which = 0;
-  std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
+  const int64_t max_frontier =
+      opt.max_frontier > 0 ? std::min<int64_t>(opt.max_frontier, kMaxFrontier) : kMaxFrontier;
+  double t_trav = 0.0, t_work = 0.0;
   int64_t peak = 0;
-  std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
-  std::vector<int8_t> tr_code, tr_p;
-  while (nseg > 0) {
-    peak = std::max(peak, npair);
-    int8_t* code = BUF(int8_t, "p_code", npair);
-    int8_t* pord = BUF(int8_t, "p_ord", npair);
-    SegCount* cnt = BUF(SegCount, "seg_cnt", nseg);
-    SegCount* incl = BUF(SegCount, "seg_incl", nseg);
-    const size_t tb = scan_counts_temp_bytes((int)nseg);
-    void* temp = BUF(char, "scan_temp", tb);
-    DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
-                         Gest, cnt, hcount, hcount + n_h * 6, st));
-    DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
-    SegCount tot;
-    DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
-    DT_HIP(hipStreamSynchronize(st));
-    if (opt.keep_trace) {
-      tr_h.resize(nseg);
-      tr_Q.resize(nseg);
-      tr_off.resize(nseg);
-      tr_len.resize(nseg);
-      tr_R.resize(npair);
-      tr_code.resize(npair);
-      tr_p.resize(npair);
-      DT_HIP(hipMemcpyAsync(tr_h.data(), cur.h, nseg * 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_Q.data(), cur.Q, nseg * 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_off.data(), cur.off, nseg * 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_len.data(), cur.len, nseg * 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_R.data(), cur.R, npair * 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_code.data(), code, npair, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipMemcpyAsync(tr_p.data(), pord, npair, hipMemcpyDeviceToHost, st));
+  int max_level = 0;
+  int64_t base_evals = 0, dist_evals = 0;
+
+  // Steps 3 and 4 for the bandwidths [hc0, hc1).  Bandwidths never interact
+  // in the traversal, so any split of the sweep makes the same decisions.
+  // Sets *retry (and changes nothing the final result depends on) when the
+  // frontier or a work list outgrows 32-bit indexing or device memory before
+  // any work kernel ran; the caller then halves the chunk.
+  auto run_chunk = [&](int hc0, int hc1, bool* retry) -> gs_status {
+    const int nh = hc1 - hc0;
+    *retry = false;
+    const size_t trace0 = ctx->trace.size();
+    auto overflow = [&]() -> gs_status {
+      if (nh == 1)
+        DT_FAIL(GS_EOVERFLOW, "the frontier of a single bandwidth exceeds max_frontier (or 2^30) "
+                              "pairs, or a work list exceeds 2^30 entries");
+      *retry = true;
+      // Undo the chunk's decisions: lower-bound sums, counters and trace.
+      DT_HIP(hipMemsetAsync(Gest + (int64_t)hc0 * nQ, 0, sizeof(double) * nh * nQ, st));
+      DT_HIP(hipMemsetAsync(hcount + hc0 * 6, 0, sizeof(unsigned long long) * nh * 6, st));
       DT_HIP(hipStreamSynchronize(st));
-      for (int64_t k = 0; k < nseg; ++k)
-        for (int j = 0; j < tr_len[k]; ++j) {
-          const int64_t o = tr_off[k] + j;
-          const int32_t rec[6] = {tr_h[k], level, tr_Q[k], tr_R[o], tr_code[o], tr_p[o]};
-          ctx->trace.insert(ctx->trace.end(), rec, rec + 6);
-        }
+      ctx->trace.resize(trace0);
+      return GS_OK;
+    };
+    // A failed allocation during the traversal is retried with fewer bandwidths.
+#define CHUNK_ALLOC(expr)                                  \
+  do {                                                     \
+    gs_status _s = (expr);                                 \
+    if (_s == GS_ENOMEM && nh > 1) return overflow();      \
+    if (_s != GS_OK) return _s;                            \
+  } while (0)
+    const double ta = now_ms();
+    DT_HIP(hipMemsetAsync(chunk_ev, 0, 2 * sizeof(unsigned long long), st));
+    FrontierLevel cur, nxt;
+    int64_t nseg = nh, npair = nh;
+    CHUNK_ALLOC(level_bufs(0, nseg, npair, cur));
+    hipLaunchKernelGGL(init_level0_kernel, dim3((unsigned)ceil_div(nh, 64)), dim3(64), 0, st, hc0, nh, cur);
+    DT_HIP(hipGetLastError());
+    WorkLists wl;
+    int64_t used_ent[4] = {0, 0, 0, 0}, used_grp[4] = {0, 0, 0, 0};
+    auto grow_lists = [&](const int64_t* add_ent, const int64_t* add_grp) -> gs_status {
+      for (int x = 0; x < 4; ++x) {
+        wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], used_ent[x], used_ent[x] + add_ent[x]);
+        wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], used_grp[x], used_grp[x] + add_grp[x]);
+      }
+      return GS_OK;
+    };
+    {
+      const int64_t e0[4] = {1024, 1024, 1024, 1024}, g0[4] = {256, 256, 256, 256};
+      CHUNK_ALLOC(grow_lists(e0, g0));
     }
+    int level = 0, which = 0;
+    std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
+    std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
+    std::vector<int8_t> tr_code, tr_p;
+    while (nseg > 0) {
+      peak = std::max(peak, npair);
+      int8_t* code;
+      int8_t* pord;
+      SegCount *cnt, *incl;
+      void* temp;
+      const size_t tb = scan_counts_temp_bytes((int)nseg);
+      CHUNK_ALLOC(([&]() -> gs_status {
+        code = BUF(int8_t, "p_code", npair);
+        pord = BUF(int8_t, "p_ord", npair);
+        cnt = BUF(SegCount, "seg_cnt", nseg);
+        incl = BUF(SegCount, "seg_incl", nseg);
+        temp = BUF(char, "scan_temp", tb);
+        return GS_OK;
+      })());
+      DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
+                           Gest, cnt, hcount, chunk_ev, st));
+      DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
+      SegCount tot;
+      DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
+      DT_HIP(hipStreamSynchronize(st));
+      if (opt.keep_trace) {
+        tr_h.resize(nseg);
+        tr_Q.resize(nseg);
+        tr_off.resize(nseg);
+        tr_len.resize(nseg);
+        tr_R.resize(npair);
+        tr_code.resize(npair);
+        tr_p.resize(npair);
+        DT_HIP(hipMemcpyAsync(tr_h.data(), cur.h, nseg * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_Q.data(), cur.Q, nseg * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_off.data(), cur.off, nseg * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_len.data(), cur.len, nseg * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_R.data(), cur.R, npair * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_code.data(), code, npair, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipMemcpyAsync(tr_p.data(), pord, npair, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipStreamSynchronize(st));
+        for (int64_t k = 0; k < nseg; ++k)
+          for (int j = 0; j < tr_len[k]; ++j) {
+            const int64_t o = tr_off[k] + j;
+            const int32_t r6[6] = {tr_h[k], level, tr_Q[k], tr_R[o], tr_code[o], tr_p[o]};
+            ctx->trace.insert(ctx->trace.end(), r6, r6 + 6);
+          }
+      }
+      const int64_t nseg2 = tot.v[1], npair2 = tot.v[0];
+      bool too_big = npair2 > max_frontier || nseg2 > max_frontier;
+      for (int x = 0; x < 4; ++x)
+        too_big = too_big || used_ent[x] + tot.v[2 + x] > kMaxFrontier ||
+                  used_grp[x] + tot.v[6 + x] > kMaxFrontier;
+      if (too_big) return overflow();
+      dh_level_begin.push_back(used_grp[0]);
+      CHUNK_ALLOC(grow_lists(tot.v + 2, tot.v + 6));
+      LevelOffsets lo;
+      for (int x = 0; x < 4; ++x) {
+        lo.ent[x] = (int32_t)used_ent[x];
+        lo.grp[x] = (int32_t)used_grp[x];
+      }
+      CHUNK_ALLOC(level_bufs(1 - which, nseg2, npair2, nxt));
+      DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
+      for (int x = 0; x < 4; ++x) {
+        used_ent[x] += tot.v[2 + x];
+        used_grp[x] += tot.v[6 + x];
+      }
+      std::swap(cur, nxt);
+      which = 1 - which;
+      nseg = nseg2;
+      npair = npair2;
+      ++level;
+    }
+    DT_HIP(hipStreamSynchronize(st));
+    const double tb0 = now_ms();
+    t_trav += tb0 - ta;
+    max_level = std::max(max_level, level);
     dh_level_begin.push_back(used_grp[0]);
-    LevelOffsets lo;
-    for (int x = 0; x < 4; ++x) {
-      wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], used_ent[x], used_ent[x] + tot.v[2 + x]);
-      wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], used_grp[x], used_grp[x] + tot.v[6 + x]);
-      lo.ent[x] = (int32_t)used_ent[x];
-      lo.grp[x] = (int32_t)used_grp[x];
-    }
-    const int64_t nseg2 = tot.v[1], npair2 = tot.v[0];
-    if (used_ent[3] + tot.v[5] > INT32_MAX / 2 || npair2 > INT32_MAX / 2)
-      DT_FAIL(GS_EOVERFLOW, "frontier exceeds 2^30 entries");
-    s = level_bufs(1 - which, nseg2, npair2, nxt);
-    if (s != GS_OK) return s;
-    DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
-    for (int x = 0; x < 4; ++x) {
-      used_ent[x] += tot.v[2 + x];
-      used_grp[x] += tot.v[6 + x];
-    }
-    std::swap(cur, nxt);
-    which = 1 - which;
-    nseg = nseg2;
-    npair = npair2;
-    ++level;
-  }
-  DT_HIP(hipStreamSynchronize(st));
-  double t3 = now_ms();
-  S.t_traverse_ms = t3 - t2;
-  S.levels = level;
-  S.frontier_peak = peak;
 
-  dh_level_begin.push_back(used_grp[0]);
-
-  // 4. Work lists: DL, H2L and base groups sorted by (h, Q) key; DH per level.
-  SortedGroups sg[4];
-  for (int x = 1; x < 4; ++x) {
-    const int n = (int)used_grp[x];
-    sg[x].n = n;
-    sg[x].grp = wl.grp[x];
-    if (n == 0) continue;
-    unsigned long long* key = BUF(unsigned long long, std::string("g_key_") + tname[x], n);
-    unsigned long long* skey = BUF(unsigned long long, std::string("g_skey_") + tname[x], n);
-    int32_t* idx = BUF(int32_t, std::string("g_idx_") + tname[x], n);
-    int32_t* sidx = BUF(int32_t, std::string("g_sidx_") + tname[x], n);
-    hipLaunchKernelGGL(group_keys_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n,
-                       wl.grp[x], nQ, key, idx);
-    size_t bytes = 0;
-    DT_HIP(rocprim::radix_sort_pairs((void*)nullptr, bytes, key, skey, idx, sidx, (unsigned)n, 0, 64, st));
-    void* temp = BUF(char, "g_sort_temp", bytes);
-    DT_HIP(rocprim::radix_sort_pairs(temp, bytes, key, skey, idx, sidx, (unsigned)n, 0, 64, st));
-    sg[x].order = sidx;
-    sg[x].key = skey;
-  }
-  if (use_fmm) {
-    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
-    const bool fast = series_fast_available(D, P);
-    if (fast)
-      DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-    else
-      DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-    DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
-    for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
-      const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
-      // query nodes of traversal level lv: depth lv (at most ceil(M / 2^lv) points)
-      // or leaves of earlier levels (at most leaf_size points)
-      const int64_t depth_max = lv < 62 ? ((Mq + ((int64_t)1 << lv) - 1) >> lv) : 1;
-      const int max_q = (int)std::max<int64_t>(depth_max, opt.leaf_size);
+    // 4. Work.  Every scratch buffer is taken before the first work kernel,
+    // so a failed allocation can still be retried.
+    SortedGroups sg[3];
+    unsigned long long* gkey[3] = {};
+    int32_t* gidx[3] = {};
+    size_t gsort_bytes = 0;
+    BaseFusedArgs ba;
+    const bool any_base = used_grp[3] > 0;
+    CHUNK_ALLOC(([&]() -> gs_status {
+      for (int x = 1; x < 3; ++x) {
+        const int n = (int)used_grp[x];
+        sg[x].n = n;
+        sg[x].grp = wl.grp[x];
+        if (n == 0 || !use_fmm) continue;
+        gkey[x] = BUF(unsigned long long, std::string("g_key_") + tname[x], n);
+        sg[x].key = BUF(unsigned long long, std::string("g_skey_") + tname[x], n);
+        gidx[x] = BUF(int32_t, std::string("g_idx_") + tname[x], n);
+        sg[x].order = BUF(int32_t, std::string("g_sidx_") + tname[x], n);
+        size_t bytes = 0;
+        DT_HIP(rocprim::radix_sort_pairs((void*)nullptr, bytes, gkey[x], (unsigned long long*)nullptr,
+                                         gidx[x], (int32_t*)nullptr, (unsigned)n, 0, 64, st));
+        gsort_bytes = std::max(gsort_bytes, bytes);
+      }
+      if (!any_base) return GS_OK;
+      const int64_t ne = used_ent[3];
+      if (!rec) rec = BUF(float, "base_rec", N * base_record_stride(D));
+      ba.grp = wl.grp[3];
+      ba.n_groups = (int)used_grp[3];
+      ba.ent = wl.ent[3];
+      ba.n_entries = ne;
+      ba.n_qnodes = nQ;
+      ba.n_rnodes = nR;
+      ba.n_hblocks = (n_h + 7) / 8;
+      ba.hc0 = hc0;
+      ba.hc1 = hc1;
+      ba.qt = qv;
+      ba.rt = rv;
+      ba.xq_perm = xq_perm;
+      ba.rec = rec;
+      ba.D = D;
+      ba.Mq = (int)Mq;
+      ba.s2 = d_s2;
+      ba.wmax_bits = wmax_bits;
+      ba.gx = gx;
+      ba.dist_evals = chunk_ev + 1;
+      ba.key = BUF(unsigned long long, "bf_key", ne);
+      ba.key_sorted = BUF(unsigned long long, "bf_skey", ne);
+      ba.ukey = BUF(unsigned long long, "bf_ukey", ne);
+      ba.bit = BUF(uint8_t, "bf_bit", ne);
+      ba.bit_sorted = BUF(uint8_t, "bf_sbit", ne);
+      ba.umask = BUF(uint8_t, "bf_umask", ne);
+      ba.flag = BUF(int32_t, "bf_flag", ne);
+      ba.pos = BUF(int32_t, "bf_pos", ne);
+      ba.run_start = BUF(int32_t, "bf_runs", ne + 1);
+      ba.n_unique = BUF(int32_t, "bf_nu", 1);
+      ba.temp_bytes = std::max(base_fused_temp_bytes(ne), gsort_bytes);
+      ba.temp = BUF(char, "g_sort_temp", ba.temp_bytes);
+      return GS_OK;
+    })());
+    if (!any_base && gsort_bytes) {
+      gs_status s2 = GS_OK;
+      CHUNK_ALLOC(([&]() -> gs_status {
+        ba.temp = buf<char>(ctx, "g_sort_temp", gsort_bytes, &s2);
+        return ba.temp ? GS_OK : s2;
+      })());
+      ba.temp_bytes = gsort_bytes;
+    }
+#undef CHUNK_ALLOC
+    for (int x = 1; x < 3 && use_fmm; ++x) {
+      const int n = sg[x].n;
+      if (n == 0) continue;
+      hipLaunchKernelGGL(group_keys_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n,
+                         wl.grp[x], nQ, gkey[x], gidx[x]);
+      size_t bytes = ba.temp_bytes;
+      DT_HIP(rocprim::radix_sort_pairs(ba.temp, bytes, gkey[x], const_cast<unsigned long long*>(sg[x].key),
+                                       gidx[x], const_cast<int32_t*>(sg[x].order), (unsigned)n, 0, 64, st));
+    }
+    if (use_fmm) {
+      KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
+      const bool fast = series_fast_available(D, P);
       if (fast)
-        DT_HIP(launch_dh_fast(D, P, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
-                              Mom, d_sc, (int)Mq, gdh, st));
+        DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
       else
-        DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
-                               Mom, d_sc, (int)Mq, gdh, st));
+        DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+      DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
+      for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
+        const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
+        // query nodes of traversal level lv: depth lv (at most ceil(M / 2^lv)
+        // points) or leaves of earlier levels (at most leaf_size points)
+        const int64_t depth_max = lv < 62 ? ((Mq + ((int64_t)1 << lv) - 1) >> lv) : 1;
+        const int max_q = (int)std::max<int64_t>(depth_max, opt.leaf_size);
+        if (fast)
+          DT_HIP(launch_dh_fast(D, P, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
+                                Mom, d_sc, (int)Mq, gdh, st));
+        else
+          DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
+                                 Mom, d_sc, (int)Mq, gdh, st));
+      }
+      kt.stop(st, 2 + (int)dh_level_begin.size() - 1);
     }
-    kt.stop(st, 2 + (int)dh_level_begin.size() - 1);
+    if (any_base) {
+      if (!rec_ready) {
+        DT_HIP(launch_base_records(xr_perm, wr_perm, rt.leaf_of_pos, rt.ctr, N, D, wmax_bits, rec, st));
+        rec_ready = true;
+      }
+      BaseFusedPlan plan;
+      DT_HIP(plan_base_fused(ba, &plan, st));
+      KernelTimer kt(ctx, ctx->kernel_timing, GS_K_BASE, st);
+      DT_HIP(launch_base_fused(ba, plan, st));
+      kt.stop(st, 1);
+    }
+    unsigned long long ev[2] = {0, 0};
+    DT_HIP(hipMemcpyAsync(ev, chunk_ev, sizeof(ev), hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    base_evals += (int64_t)ev[0];
+    dist_evals += (int64_t)ev[1];
+    t_work += now_ms() - tb0;
+    return GS_OK;
+  };
+
+  // 3-4. Traversal and work, over chunks of the bandwidth sweep.
+  int chunk = opt.h_chunk > 0 ? std::min(opt.h_chunk, n_h) : n_h, h_chunks = 0;
+  for (int hc0 = 0; hc0 < n_h;) {
+    const int hc1 = std::min(n_h, hc0 + chunk);
+    bool retry = false;
+    s = run_chunk(hc0, hc1, &retry);
+    if (s != GS_OK) return s;
+    if (retry) {
+      chunk = std::max(1, (hc1 - hc0) / 2);
+      ctx->err.clear();
+      continue;
+    }
+    ++h_chunks;
+    hc0 = hc1;
   }
-  if (sg[3].n) {
-    float* rec = BUF(float, "base_rec", N * base_record_stride(D));
-    DT_HIP(launch_base_records(xr_perm, wr_perm, rt.leaf_of_pos, rt.ctr, N, D, wmax_bits, rec, st));
-    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_BASE, st);
-    DT_HIP(launch_base(sg[3], wl.ent[3], qv, rv, xq_perm, rec, D, d_s2, wmax_bits, (int)Mq, gx, st));
-    kt.stop(st, 1);
-  }
-  DT_HIP(hipStreamSynchronize(st));
   double t4 = now_ms();
-  S.t_work_ms = t4 - t3;
+  S.t_traverse_ms = t_trav;
+  S.t_work_ms = t_work;
+  S.levels = max_level;
+  S.frontier_peak = peak;
+  S.h_chunks = h_chunks;
+  S.base_pair_evals = base_evals;
+  S.base_dist_evals = dist_evals;
 
   // 5. Post-pass.
   for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
@@ -670,14 +812,13 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   S.t_post_ms = t5 - t4;
 
   // Statistics.
-  std::vector<unsigned long long> hc(n_h * 6 + 1);
+  std::vector<unsigned long long> hc(n_h * 6);
   DT_HIP(hipMemcpyAsync(hc.data(), hcount, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < n_h * 6; ++k) {
     ctx->pair_counts[k] = (int64_t)hc[k];
     S.pairs[k % 6] += (int64_t)hc[k];
   }
-  S.base_pair_evals = (int64_t)hc[n_h * 6];
   if (opt.keep_trace) {
     s = keep_tree(ctx, rt, D, ctx->host_tree[0], st);
     if (s != GS_OK) return s;

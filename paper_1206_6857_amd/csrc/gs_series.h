@@ -75,14 +75,45 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* en
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
                           hipStream_t s);
 
-// Base cases (DITOBase): gx[h][q] for the runs of BASE groups.
+// Base cases (DITOBase), fused over blocks of 8 bandwidths.
 int base_record_stride(int D);
 hipError_t launch_base_records(const double* xr_perm, const double* wr_perm, const int32_t* leaf_of_pos,
                                const double* rctr, int64_t n, int D, const unsigned long long* wmax_bits,
                                float* rec, hipStream_t s);
-hipError_t launch_base(const SortedGroups& g, const int32_t* ent, const NodeView& qt,
-                       const NodeView& rt, const double* xq_perm, const float* rec, int D,
-                       const float* s2, const unsigned long long* wmax_bits, int M_q, double* gx,
-                       hipStream_t s);
+
+struct BaseFusedArgs {
+  // base work list of the traversal: groups {h, Q, first entry, entries}
+  const int4* grp = nullptr;
+  int n_groups = 0;
+  const int32_t* ent = nullptr;  // (R << 4) | p
+  int64_t n_entries = 0;
+  int n_qnodes = 0, n_rnodes = 0, n_hblocks = 0;
+  // bandwidths [hc0, hc1) are written by this call; others are left alone
+  int hc0 = 0, hc1 = 0;
+  NodeView qt{}, rt{};
+  const double* xq_perm = nullptr;  // [M][D], query tree order
+  const float* rec = nullptr;       // reference records, base_record_stride(D) floats each
+  int D = 0, Mq = 0;
+  const float* s2 = nullptr;        // log2(e) / 2h^2 per bandwidth
+  const unsigned long long* wmax_bits = nullptr;
+  double* gx = nullptr;             // [n_h][M]
+  unsigned long long* dist_evals = nullptr;  // += point pairs of the regrouped entries
+  // scratch, n_entries elements each (n_entries + 1 for run_start)
+  unsigned long long *key = nullptr, *key_sorted = nullptr, *ukey = nullptr;
+  uint8_t *bit = nullptr, *bit_sorted = nullptr, *umask = nullptr;
+  int32_t *flag = nullptr, *pos = nullptr, *run_start = nullptr;
+  int32_t* n_unique = nullptr;  // one element
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+};
+
+struct BaseFusedPlan {
+  int nruns = 0, rbits = 0, hbits = 0;
+};
+
+size_t base_fused_temp_bytes(int64_t n_entries);
+// Regroups the entries into runs (synchronises the stream twice).
+hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t s);
+hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s);
 
 }  // namespace gs

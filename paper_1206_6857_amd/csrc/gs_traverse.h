@@ -8,6 +8,10 @@
 
 namespace gs {
 
+// Largest frontier (pairs or segments) and work list (entries or groups) of
+// one traversal: offsets are 32-bit.
+constexpr int64_t kMaxFrontier = (int64_t)1 << 30;
+
 // Per-call constants of the pruning test (sections 4-5).
 struct DecideConst {
   int D = 0, P = 0;
@@ -22,7 +26,7 @@ struct DecideConst {
 
 // Counters of one frontier segment (one (bandwidth, query node) pair list).
 struct SegCount {
-  int32_t v[10];  // [0] next-level pairs, [1] next-level segments,
+  int64_t v[10];  // [0] next-level pairs, [1] next-level segments,
                   // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags
 };
 

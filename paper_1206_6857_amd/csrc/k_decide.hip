@@ -438,15 +438,16 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
   const int lane = threadIdx.x;
   const SegCount own = cnt[s];
   const SegCount in = incl[s];
+  // totals were checked on the host to fit 32-bit offsets
   int ex[10];
-  for (int k = 0; k < 10; ++k) ex[k] = in.v[k] - own.v[k];
+  for (int k = 0; k < 10; ++k) ex[k] = (int)(in.v[k] - own.v[k]);
   const int h = cur.h[s];
   const int Q = cur.Q[s];
   const int off = cur.off[s];
   const int len = cur.len[s];
   const bool qleaf = qleft[Q] < 0;
-  const int nsegs = own.v[1];
-  const int nch = nsegs ? own.v[0] / nsegs : 0;
+  const int nsegs = (int)own.v[1];
+  const int nch = nsegs ? (int)(own.v[0] / nsegs) : 0;
   const int pb = ex[0];
   const int sb = ex[1];
   if (lane < nsegs) {
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
   for (int x = 0; x < 4; ++x) {
     eb[x] = base.ent[x] + ex[2 + x];
     if (lane == 0 && own.v[2 + x] > 0)
-      wl.grp[x][base.grp[x] + ex[6 + x]] = make_int4(h, Q, eb[x], own.v[2 + x]);
+      wl.grp[x][base.grp[x] + ex[6 + x]] = make_int4(h, Q, eb[x], (int)own.v[2 + x]);
   }
   int kc = 0;
   for (int b0 = 0; b0 < len; b0 += 64) {

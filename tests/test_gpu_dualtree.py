@@ -98,3 +98,64 @@ def test_dualtree_torch_device_and_repeat():
     assert np.array_equal(G1, G2)   # deterministic: no float atomics
     exact = gauss_sum_exhaustive(r, r, w, hs)
     assert (np.abs(G1 - exact) / exact).max() <= 0.01
+
+
+def _sorted_trace(c):
+    t = c.get_trace().astype(np.int64)
+    return t[np.lexsort(t.T[::-1])]
+
+
+def test_dualtree_bandwidth_chunks():
+    """Bandwidths never interact in the traversal: any split of the sweep
+    (h_chunk) makes the same decisions; values differ only by the summation
+    order of the base tiles.  10 bandwidths span two base-tile blocks of 8, and
+    chunks of 3 split both blocks across chunks."""
+    banner("dualtree chunks")
+    r, w, _ = mixture((91, 3), 3000, 3, 8, (0.01, 0.1))
+    hs = np.logspace(-3, 0, 10)
+    c = ctx()
+    G0 = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, keep_trace=1)
+    tr0 = _sorted_trace(c)
+    pc0 = c.pair_counts(len(hs))
+    st0 = c.stats()
+    assert st0.h_chunks == 1
+    assert 0 < st0.base_dist_evals <= st0.base_pair_evals
+    for chunk in (1, 3, 7):
+        G = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, keep_trace=1, h_chunk=chunk)
+        st = c.stats()
+        assert st.h_chunks == -(-len(hs) // chunk)
+        assert st.base_pair_evals == st0.base_pair_evals
+        assert np.array_equal(_sorted_trace(c), tr0)
+        assert np.array_equal(c.pair_counts(len(hs)), pc0)
+        assert (np.abs(G - G0) / G0).max() <= 1e-12, chunk
+    exact = gauss_sum_exhaustive(r, r, w, hs)
+    assert (np.abs(G0 - exact) / exact).max() <= 0.01
+
+
+def test_dualtree_frontier_cap_retry():
+    """A frontier cap below the full sweep's frontier makes the library halve
+    the bandwidth chunk and redo it; the decisions and values are those of the
+    uncapped call.  A cap no single bandwidth fits in is an overflow error."""
+    import paper_1206_6857_amd as g
+    from paper_1206_6857_amd import _lib
+    banner("dualtree frontier cap")
+    r, w, _ = mixture((92, 2), 2000, 2, 6, (0.01, 0.1))
+    hs = np.logspace(-2.5, 0, 6)
+    c = ctx()
+    G0 = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=16, keep_trace=1)
+    tr0 = _sorted_trace(c)
+    peak = c.stats().frontier_peak
+    # the largest frontier of one bandwidth: from single-bandwidth runs
+    one = 0
+    for k in range(len(hs)):
+        c.gauss_sum(r, r, w, hs[k:k + 1], 0.01, leaf_size=16)
+        one = max(one, c.stats().frontier_peak)
+    assert one < peak
+    G = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=16, keep_trace=1, max_frontier=one)
+    st = c.stats()
+    assert st.h_chunks > 1 and st.frontier_peak <= one
+    assert np.array_equal(_sorted_trace(c), tr0)
+    assert (np.abs(G - G0) / G0).max() <= 1e-12
+    with pytest.raises(g.GaussSumError) as ei:
+        c.gauss_sum(r, r, w, hs, 0.01, leaf_size=16, max_frontier=one - 1)
+    assert ei.value.status == _lib.GS_EOVERFLOW
