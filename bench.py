@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exhaustive", action="store_true")
     ap.add_argument("--leaf-size", type=int, default=64)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy (y = x * 1) of this many MiB, "
+                         "to calibrate HBM byte counters against a known size")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
@@ -133,6 +136,13 @@ def main():
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / steps
         return t, kms, kl, evals, ctx.stats()
+
+    if args.calib_copy_mib > 0:
+        xc = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        yc = torch.empty_like(xc)
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
 
     t_dt, kms, kl, evals, st_dt = run("dualtree", args.steps, args.warmup)
     base_evals, dist_evals = int(evals[0]), int(evals[1])

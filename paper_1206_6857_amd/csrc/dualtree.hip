@@ -499,6 +499,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 2), st));
   float* rec = nullptr;  // base-case reference records, built on first use
   bool rec_ready = false;
+  BaseRecordsArgs ra;
 
   TreeView qtv{qt.lo, qt.hi, qt.rinf, qt.W, qt.wmin, qt.count, qt.left};
   TreeView rtv{rt.lo, rt.hi, rt.rinf, rt.W, rt.wmin, rt.count, rt.left};
@@ -674,7 +675,26 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       }
       if (!any_base) return GS_OK;
       const int64_t ne = used_ent[3];
-      if (!rec) rec = BUF(float, "base_rec", N * base_record_stride(D));
+      if (!rec) {
+        ra.xr_perm = xr_perm;
+        ra.wr_perm = wr_perm;
+        ra.leaf_of_pos = rt.leaf_of_pos;
+        ra.begin = rt.begin;
+        ra.count = rt.count;
+        ra.left = rt.left;
+        ra.rctr = rt.ctr;
+        ra.n = N;
+        ra.D = D;
+        ra.n_nodes = nR;
+        ra.wmax_bits = wmax_bits;
+        ra.padded = BUF(int32_t, "rec_pad", nR);
+        ra.rec_off = BUF(int32_t, "rec_off", nR);
+        ra.rec_capacity = base_records_capacity(N, nR);
+        ra.temp_bytes = base_records_temp_bytes(nR);
+        ra.temp = BUF(char, "rec_temp", ra.temp_bytes);
+        rec = BUF(float, "base_rec", ra.rec_capacity * base_record_stride(D));
+        ra.rec = rec;
+      }
       ba.grp = wl.grp[3];
       ba.n_groups = (int)used_grp[3];
       ba.ent = wl.ent[3];
@@ -688,6 +708,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.rt = rv;
       ba.xq_perm = xq_perm;
       ba.rec = rec;
+      ba.rec_off = ra.rec_off;
+      ba.max_leaf = opt.leaf_size;
       ba.D = D;
       ba.Mq = (int)Mq;
       ba.s2 = d_s2;
@@ -702,8 +724,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.umask = BUF(uint8_t, "bf_umask", ne);
       ba.flag = BUF(int32_t, "bf_flag", ne);
       ba.pos = BUF(int32_t, "bf_pos", ne);
+      ba.mflag = BUF(int32_t, "bf_mflag", ne);
+      ba.mpos = BUF(int32_t, "bf_mpos", ne);
       ba.run_start = BUF(int32_t, "bf_runs", ne + 1);
-      ba.n_unique = BUF(int32_t, "bf_nu", 1);
+      ba.slices = BUF(int4, "bf_slices", base_max_slices(ne));
+      const int nslots = base_partial_slots(opt.leaf_size);
+      ba.slots = BUF(int4, "bf_slots", nslots);
+      ba.partial = BUF(double, "bf_partial", (int64_t)nslots * 8 * ceil_div(opt.leaf_size, 64) * 64);
+      ba.counters = BUF(int32_t, "bf_counters", 4);
       ba.temp_bytes = std::max(base_fused_temp_bytes(ne), gsort_bytes);
       ba.temp = BUF(char, "g_sort_temp", ba.temp_bytes);
       return GS_OK;
@@ -751,7 +779,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     }
     if (any_base) {
       if (!rec_ready) {
-        DT_HIP(launch_base_records(xr_perm, wr_perm, rt.leaf_of_pos, rt.ctr, N, D, wmax_bits, rec, st));
+        DT_HIP(launch_base_records(ra, st));
         rec_ready = true;
       }
       BaseFusedPlan plan;

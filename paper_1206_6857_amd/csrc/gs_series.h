@@ -77,9 +77,28 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* en
 
 // Base cases (DITOBase), fused over blocks of 8 bandwidths.
 int base_record_stride(int D);
-hipError_t launch_base_records(const double* xr_perm, const double* wr_perm, const int32_t* leaf_of_pos,
-                               const double* rctr, int64_t n, int D, const unsigned long long* wmax_bits,
-                               float* rec, hipStream_t s);
+
+// Reference records for the base tiles: per leaf, its points' float
+// coordinates relative to the leaf centre and weight / max weight, padded with
+// zero records to a multiple of 4; rec_off[leaf] = the leaf's first record.
+struct BaseRecordsArgs {
+  const double* xr_perm = nullptr;  // [N][D], reference tree order
+  const double* wr_perm = nullptr;
+  const int32_t *leaf_of_pos = nullptr, *begin = nullptr, *count = nullptr, *left = nullptr;
+  const double* rctr = nullptr;
+  int64_t n = 0;
+  int D = 0, n_nodes = 0;
+  const unsigned long long* wmax_bits = nullptr;
+  int32_t* padded = nullptr;   // [n_nodes] scratch
+  int32_t* rec_off = nullptr;  // [n_nodes] out
+  float* rec = nullptr;        // [rec_capacity][base_record_stride(D)] out
+  int64_t rec_capacity = 0;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+};
+int64_t base_records_capacity(int64_t n_points, int n_nodes);
+size_t base_records_temp_bytes(int n_nodes);
+hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s);
 
 struct BaseFusedArgs {
   // base work list of the traversal: groups {h, Q, first entry, entries}
@@ -88,31 +107,38 @@ struct BaseFusedArgs {
   const int32_t* ent = nullptr;  // (R << 4) | p
   int64_t n_entries = 0;
   int n_qnodes = 0, n_rnodes = 0, n_hblocks = 0;
+  int max_leaf = 0;  // most points in a query leaf
   // bandwidths [hc0, hc1) are written by this call; others are left alone
   int hc0 = 0, hc1 = 0;
   NodeView qt{}, rt{};
   const double* xq_perm = nullptr;  // [M][D], query tree order
-  const float* rec = nullptr;       // reference records, base_record_stride(D) floats each
+  const float* rec = nullptr;       // reference records (BaseRecordsArgs)
+  const int32_t* rec_off = nullptr;
   int D = 0, Mq = 0;
   const float* s2 = nullptr;        // log2(e) / 2h^2 per bandwidth
   const unsigned long long* wmax_bits = nullptr;
   double* gx = nullptr;             // [n_h][M]
   unsigned long long* dist_evals = nullptr;  // += point pairs of the regrouped entries
-  // scratch, n_entries elements each (n_entries + 1 for run_start)
+  // scratch: n_entries elements each (run_start n_entries + 1)
   unsigned long long *key = nullptr, *key_sorted = nullptr, *ukey = nullptr;
   uint8_t *bit = nullptr, *bit_sorted = nullptr, *umask = nullptr;
-  int32_t *flag = nullptr, *pos = nullptr, *run_start = nullptr;
-  int32_t* n_unique = nullptr;  // one element
+  int32_t *flag = nullptr, *pos = nullptr, *mflag = nullptr, *mpos = nullptr, *run_start = nullptr;
+  int4* slices = nullptr;    // base_max_slices(n_entries)
+  int4* slots = nullptr;     // base_partial_slots(max_leaf)
+  double* partial = nullptr; // base_partial_slots(max_leaf) * 8 * round_up(max_leaf, 64)
+  int32_t* counters = nullptr;  // 4: unique entries, runs, slices, partial slots used
   void* temp = nullptr;
   size_t temp_bytes = 0;
 };
 
 struct BaseFusedPlan {
-  int nruns = 0, rbits = 0, hbits = 0;
+  int n_slices = 0, n_slots = 0, max_slots = 0, slice_entries = 0, qmax = 0, rbits = 0, hbits = 0;
 };
 
 size_t base_fused_temp_bytes(int64_t n_entries);
-// Regroups the entries into runs (synchronises the stream twice).
+int64_t base_max_slices(int64_t n_entries);
+int base_partial_slots(int max_leaf);
+// Regroups the entries into runs and slices (synchronises the stream twice).
 hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t s);
 hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s);
 

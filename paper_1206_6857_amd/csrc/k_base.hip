@@ -8,13 +8,19 @@
 // depend on h, so the entries are regrouped by (Q, block of 8 bandwidths, R)
 // with an 8-bit mask of the block's bandwidths that need the pair: a radix sort
 // of (Q, block, R) keys, then an OR reduction by key.  A run is the set of
-// regrouped entries of one (Q, block).  One workgroup of kWaves waves handles
-// one run: lanes hold the points of Q, the run's entries are dealt round-robin
-// to the waves, and every point pair's squared distance feeds one exp2 per
-// bandwidth of the entry's mask.  Reference points are read with wave-uniform
-// addresses (scalar loads, no LDS staging).  The per-wave partials are summed in
-// wave order, so every gx[h][q] is written once and the result is
-// deterministic.
+// regrouped entries of one (Q, block); runs are cut into slices of at most S
+// entries, S chosen so that there are many more slices than SIMDs (the runs of
+// dense clusters hold hundreds of entries, the others a few).
+//
+// One wave handles one slice: lanes hold the points of Q, the wave sweeps the
+// reference leaves of its entries, and every point pair's squared distance
+// feeds one exp2 per bandwidth of the entry's mask.  Reference records are read
+// with wave-uniform addresses (scalar loads, several records per load, the
+// next batch requested before the current one is used); each leaf's records
+// are padded with zero-weight records to a multiple of 4.  A run of one slice
+// writes gx directly; otherwise every slice writes its partial sums and a
+// second kernel adds them in slice order.  Every gx[h][q] is written once and
+// the result is deterministic.
 //
 // Precision: reference coordinates are stored relative to their leaf centre
 // in float (u_r = x_r - c_R); each lane forms u_q = x_q - c_R in double before
@@ -36,18 +42,27 @@ namespace gs {
 namespace {
 
 constexpr int kW = 64;
-constexpr int kWaves = 4;  // waves per run
-constexpr int kHB = 8;     // bandwidths per block
+constexpr int kHB = 8;   // bandwidths per block
+constexpr int kPad = 4;  // records per leaf are padded to a multiple of this
+
+__global__ void pad_counts_kernel(const int32_t* __restrict__ left, const int32_t* __restrict__ count,
+                                  int n_nodes, int32_t* __restrict__ padded) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  padded[i] = left[i] < 0 ? (count[i] + kPad - 1) / kPad * kPad : 0;
+}
 
 __global__ void base_records_kernel(const double* __restrict__ xr, const double* __restrict__ wr,
                                     const int32_t* __restrict__ leaf_of_pos,
+                                    const int32_t* __restrict__ begin, const int32_t* __restrict__ rec_off,
                                     const double* __restrict__ rctr, int64_t n, int D, int rs,
                                     const unsigned long long* __restrict__ wmax_bits,
                                     float* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double* c = rctr + (int64_t)leaf_of_pos[i] * D;
-  float* o = rec + i * rs;
+  const int L = leaf_of_pos[i];
+  const double* c = rctr + (int64_t)L * D;
+  float* o = rec + ((int64_t)rec_off[L] + (i - begin[L])) * rs;
   for (int d = 0; d < D; ++d) o[d] = (float)(xr[i * D + d] - c[d]);
   o[D] = (float)(wr[i] / __longlong_as_double((long long)*wmax_bits));
   for (int k = D + 1; k < rs; ++k) o[k] = 0.0f;
@@ -74,10 +89,12 @@ struct BitOr {
 };
 
 // Run heads (first entry of each (Q, block)) and the number of point pairs
-// whose squared distance the fused kernel forms.
-__global__ void run_flags_kernel(const unsigned long long* __restrict__ ukey, int n, int rbits, int hbits,
-                                 const int32_t* __restrict__ qcount, const int32_t* __restrict__ rcount,
-                                 int32_t* __restrict__ flag, unsigned long long* __restrict__ dist_evals) {
+// whose squared distance the sweep forms (one atomic per workgroup).
+__global__ __launch_bounds__(1024) void run_flags_kernel(
+    const unsigned long long* __restrict__ ukey, int n, int rbits, int hbits,
+    const int32_t* __restrict__ qcount, const int32_t* __restrict__ rcount, int32_t* __restrict__ flag,
+    unsigned long long* __restrict__ dist_evals) {
+  __shared__ unsigned long long part[1024 / kW];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long pe = 0;
   if (i < n) {
@@ -89,9 +106,16 @@ __global__ void run_flags_kernel(const unsigned long long* __restrict__ ukey, in
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) pe += __shfl_xor(pe, off, kW);
-  if ((threadIdx.x % kW) == 0 && pe) atomicAdd(dist_evals, pe);
+  if (threadIdx.x % kW == 0) part[threadIdx.x / kW] = pe;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kW); ++w) t += part[w];
+    if (t) atomicAdd(dist_evals, t);
+  }
 }
 
+// run_start[r] = first entry of run r; run_start[nruns] = n; *nruns.
 __global__ void run_scatter_kernel(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
                                    int n, int32_t* __restrict__ run_start, int32_t* __restrict__ nruns) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,58 +127,130 @@ __global__ void run_scatter_kernel(const int32_t* __restrict__ flag, const int32
   }
 }
 
-// Sweep of one reference leaf for NA bandwidths: for every point r,
+// Slices per run, and the same count for runs of several slices (whose
+// slices get partial-sum slots); 0 past the last run.
+__global__ void slice_counts_kernel(const int32_t* __restrict__ run_start, const int32_t* __restrict__ nruns,
+                                    int n, int S, int32_t* __restrict__ nslice, int32_t* __restrict__ nmulti) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int ns = r < *nruns ? (run_start[r + 1] - run_start[r] + S - 1) / S : 0;
+  nslice[r] = ns;
+  nmulti[r] = ns > 1 ? ns : 0;
+}
+
+// Slices {run, first entry, end entry, partial slot (-1 when the run has a
+// single slice)} and, per slot, {run, the run's first slot, its slot count}.
+// counters[2] = slices, counters[3] = slots.
+__global__ void slices_kernel(const int32_t* __restrict__ run_start, const int32_t* __restrict__ nruns,
+                              const int32_t* __restrict__ nslice, const int32_t* __restrict__ sstart,
+                              const int32_t* __restrict__ nmulti, const int32_t* __restrict__ mstart, int S,
+                              int max_slots, int4* __restrict__ slices, int4* __restrict__ slots,
+                              int32_t* __restrict__ counters) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nr = *nruns;
+  if (r >= nr) return;
+  const int e0 = run_start[r], e1 = run_start[r + 1], ns = nslice[r], s0 = sstart[r];
+  const int m0 = mstart[r];
+  for (int j = 0; j < ns; ++j) {
+    const int a = e0 + j * S;
+    const int slot = ns > 1 && m0 + j < max_slots ? m0 + j : -1;
+    slices[s0 + j] = make_int4(r, a, min(e1, a + S), slot);
+    if (slot >= 0) slots[slot] = make_int4(r, m0, ns, 0);
+  }
+  if (r == nr - 1) {
+    counters[2] = s0 + ns;
+    counters[3] = m0 + nmulti[r];
+  }
+}
+
+// Sixteen floats read by one scalar load when the address is wave-uniform.
+typedef float f16v __attribute__((ext_vector_type(16), aligned(16)));
+
+// Sweep of one reference leaf for NA bandwidths: for every record r,
 //   part[j] += w_r exp2(shiftc[j] - |u_q - u_r|^2 shc[j]),  j < NA.
-// The record addresses are wave-uniform (scalar loads).
-template <int DC, int NA>
-__device__ __forceinline__ void sweep(const float* __restrict__ rp, int rn, int rs, int D,
-                                      const float* uq, const float* shc, const float* shiftc,
-                                      float* part) {
-#pragma unroll 2
-  for (int r = 0; r < rn; ++r) {
-    const float* x = rp + r * rs;
-    float d2 = 0.0f;
+// p: the leaf's padded records, nb batches of BR records of RS floats; a
+// batch is read as whole 16-float vectors (up to 15 floats past the batch,
+// inside the record array's tail).
+template <int D, int NA, int RS, int BR>
+__device__ __forceinline__ void sweep(const float* __restrict__ p, int nb, const float* uq,
+                                      const float* shc, const float* shiftc, float* part) {
+  constexpr int NF = RS * BR;
+  constexpr int NV = (NF + 15) / 16;
+  for (int b = 0; b < nb; ++b, p += NF) {
+    f16v v[NV];
 #pragma unroll
-    for (int d = 0; d < DC; ++d) {
-      if (d < D) {
-        const float dd = uq[d] - x[d];
+    for (int i = 0; i < NV; ++i) v[i] = *reinterpret_cast<const f16v*>(p + 16 * i);
+#pragma unroll
+    for (int j = 0; j < BR; ++j) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const float dd = uq[d] - v[(j * RS + d) / 16][(j * RS + d) % 16];
         d2 = fmaf(dd, dd, d2);
       }
-    }
-    const float wr = x[D];
+      const float wr = v[(j * RS + D) / 16][(j * RS + D) % 16];
 #pragma unroll
-    for (int j = 0; j < NA; ++j)
-      part[j] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[j], shiftc[j])), part[j]);
+      for (int a = 0; a < NA; ++a)
+        part[a] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[a], shiftc[a])), part[a]);
+    }
+  }
+}
+
+// Any D: one record at a time.
+template <int NA>
+__device__ __forceinline__ void sweep_any(const float* __restrict__ p, int n, int D, int rs,
+                                          const float* uq, const float* shc, const float* shiftc,
+                                          float* part) {
+  for (int r = 0; r < n; ++r, p += rs) {
+    float d2 = 0.0f;
+    for (int d = 0; d < D; ++d) {
+      const float dd = uq[d] - p[d];
+      d2 = fmaf(dd, dd, d2);
+    }
+    const float wr = p[D];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+      part[a] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[a], shiftc[a])), part[a]);
+  }
+}
+
+template <int DT, int NA>
+__device__ __forceinline__ void sweep_leaf(const float* __restrict__ rec, int rs, int D, int rn_padded,
+                                           const float* uq, const float* shc, const float* shiftc,
+                                           float* part) {
+  if constexpr (DT > 0) {
+    constexpr int RS = (DT + 4) / 4 * 4;
+    constexpr int BR = RS == 4 ? 4 : RS == 8 ? 2 : 1;
+    sweep<DT, NA, RS, BR>(rec, rn_padded / BR, uq, shc, shiftc, part);
+  } else {
+    sweep_any<NA>(rec, rn_padded, D, rs, uq, shc, shiftc, part);
   }
 }
 
 template <int DT>
-__global__ __launch_bounds__(kW* kWaves) void base_fused_kernel(
-    const int32_t* __restrict__ run_start, int nruns, const unsigned long long* __restrict__ ukey,
+__global__ __launch_bounds__(kW) void base_fused_kernel(
+    const int4* __restrict__ slices, int n_slices,
+    const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey,
     const uint8_t* __restrict__ umask, int rbits, int hbits, int hc0, int hc1, NodeView qt, NodeView rt,
-    const double* __restrict__ xq_perm, const float* __restrict__ rec, int Drt, int rs_rt,
-    const float* __restrict__ s2, const unsigned long long* __restrict__ wmax_bits, int Mq,
-    double* __restrict__ gx) {
-  __shared__ double red[kWaves - 1][kHB][kW];
+    const int32_t* __restrict__ rec_off, const double* __restrict__ xq_perm, const float* __restrict__ rec,
+    int Drt, int rs_rt, const float* __restrict__ s2, const unsigned long long* __restrict__ wmax_bits,
+    int Mq, int qmax, double* __restrict__ partial, double* __restrict__ gx) {
   constexpr int DC = DT > 0 ? DT : kMaxD;
   const int D = DT > 0 ? DT : Drt;
   const int rs = DT > 0 ? (DT + 4) / 4 * 4 : rs_rt;
-  // Consecutive runs (neighbouring query leaves, which share reference
+  // Consecutive slices (neighbouring query leaves, which share reference
   // leaves) go to the same XCD: workgroups are dealt to the 8 XCDs
-  // round-robin, so block b takes run (b % 8) * per + b / 8.
-  const int per = (nruns + 7) / 8;
-  const int run = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (run >= nruns) return;
-  const int e0 = run_start[run], e1 = run_start[run + 1];
-  const unsigned long long k0 = ukey[e0];
+  // round-robin, so block b takes slice (b % 8) * per + b / 8.
+  const int per = (n_slices + 7) / 8;
+  const int sl = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (sl >= n_slices) return;
+  const int4 sd = slices[sl];
+  const unsigned long long k0 = ukey[run_start[sd.x]];
   const int Q = (int)(k0 >> (hbits + rbits));
   const int h0 = (int)((k0 >> rbits) & ((1ull << hbits) - 1)) * kHB;
   const unsigned long long rmask = (1ull << rbits) - 1;
   const int qb = qt.begin[Q], qn = qt.count[Q];
-  const int lane = threadIdx.x % kW;
-  // wave index as a wave-uniform value, so the run's entries (and the
-  // reference points they name) are read with scalar loads
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
+  const int lane = threadIdx.x;
   for (int base = 0; base < qn; base += kW) {
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
@@ -165,7 +261,7 @@ __global__ __launch_bounds__(kW* kWaves) void base_fused_kernel(
     double acc[kHB];
 #pragma unroll
     for (int k = 0; k < kHB; ++k) acc[k] = 0.0;
-    for (int e = e0 + wave; e < e1; e += kWaves) {
+    for (int e = sd.y; e < sd.z; ++e) {
       const int R = (int)(ukey[e] & rmask);
       const unsigned m = umask[e];
       const double* cR = rt.ctr + (int64_t)R * D;
@@ -184,8 +280,8 @@ __global__ __launch_bounds__(kW* kWaves) void base_fused_kernel(
           box2 += gap * gap;
         }
       }
-      // Compact the entry's bandwidths: j-th set bit of m -> shc[j] (uniform),
-      // shiftc[j] = the lane's underflow shift for that bandwidth.
+      // Compact the entry's bandwidths: j-th set bit of m -> shc[j]
+      // (uniform), shiftc[j] = the lane's underflow shift for it.
       const int na = __builtin_popcount(m);
       float shc[kHB], shiftc[kHB], part[kHB];
       {
@@ -199,17 +295,17 @@ __global__ __launch_bounds__(kW* kWaves) void base_fused_kernel(
           part[j] = 0.0f;
         }
       }
-      const float* rp = rec + (int64_t)rt.begin[R] * rs;
-      const int rn = rt.count[R];
+      const float* rp = rec + (int64_t)rec_off[R] * rs;
+      const int rnp = (rt.count[R] + kPad - 1) / kPad * kPad;
       switch (na) {
-        case 1: sweep<DC, 1>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 2: sweep<DC, 2>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 3: sweep<DC, 3>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 4: sweep<DC, 4>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 5: sweep<DC, 5>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 6: sweep<DC, 6>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        case 7: sweep<DC, 7>(rp, rn, rs, D, uq, shc, shiftc, part); break;
-        default: sweep<DC, 8>(rp, rn, rs, D, uq, shc, shiftc, part); break;
+        case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
       }
       {
         unsigned mm = m;
@@ -226,22 +322,46 @@ __global__ __launch_bounds__(kW* kWaves) void base_fused_kernel(
         }
       }
     }
-    if (wave > 0) {
+    if (active) {
+      if (sd.w < 0) {
+        const double wscale = __longlong_as_double((long long)*wmax_bits);
 #pragma unroll
-      for (int k = 0; k < kHB; ++k) red[wave - 1][k][lane] = acc[k];
-    }
-    __syncthreads();
-    if (wave == 0 && active) {
-      const double wscale = __longlong_as_double((long long)*wmax_bits);
+        for (int k = 0; k < kHB; ++k)
+          if (h0 + k >= hc0 && h0 + k < hc1) gx[(int64_t)(h0 + k) * Mq + qpos] = acc[k] * wscale;
+      } else {
+        double* pp = partial + (int64_t)sd.w * kHB * qmax + base + lane;
 #pragma unroll
-      for (int k = 0; k < kHB; ++k) {
-        double v = acc[k];
-#pragma unroll
-        for (int w = 0; w < kWaves - 1; ++w) v += red[w][k][lane];
-        if (h0 + k >= hc0 && h0 + k < hc1) gx[(int64_t)(h0 + k) * Mq + qpos] = v * wscale;
+        for (int k = 0; k < kHB; ++k) pp[(int64_t)k * qmax] = acc[k];
       }
     }
-    __syncthreads();
+  }
+}
+
+// Runs of several slices: gx = sum of the slices' partials in slice order.
+// One workgroup per partial slot; only a run's first slot does the work.
+__global__ __launch_bounds__(kW) void base_reduce_kernel(
+    const int4* __restrict__ slots, int n_slots,
+    const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey, int rbits, int hbits,
+    int hc0, int hc1, NodeView qt, const unsigned long long* __restrict__ wmax_bits, int Mq, int qmax,
+    const double* __restrict__ partial, double* __restrict__ gx) {
+  const int sl = blockIdx.x;
+  if (sl >= n_slots) return;
+  const int4 info = slots[sl];
+  if (info.y != sl) return;
+  const int ns = info.z;
+  const unsigned long long k0 = ukey[run_start[info.x]];
+  const int Q = (int)(k0 >> (hbits + rbits));
+  const int h0 = (int)((k0 >> rbits) & ((1ull << hbits) - 1)) * kHB;
+  const int qb = qt.begin[Q], qn = qt.count[Q];
+  const double wscale = __longlong_as_double((long long)*wmax_bits);
+  for (int q = threadIdx.x; q < qn; q += kW) {
+#pragma unroll
+    for (int k = 0; k < kHB; ++k) {
+      if (h0 + k < hc0 || h0 + k >= hc1) continue;
+      double v = 0.0;
+      for (int j = 0; j < ns && sl + j < n_slots; ++j) v += partial[((int64_t)(sl + j) * kHB + k) * qmax + q];
+      gx[(int64_t)(h0 + k) * Mq + qb + q] = v * wscale;
+    }
   }
 }
 
@@ -253,21 +373,41 @@ int bits_for(int64_t n) {
 
 template <int DT>
 void launch_fused_t(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s) {
-  const int nb = (p.nruns + 7) / 8 * 8;
-  hipLaunchKernelGGL((base_fused_kernel<DT>), dim3((unsigned)nb), dim3(kW * kWaves), 0, s, a.run_start,
-                     p.nruns, a.ukey, a.umask, p.rbits, p.hbits, a.hc0, a.hc1, a.qt, a.rt, a.xq_perm,
-                     a.rec, a.D, base_record_stride(a.D), a.s2, a.wmax_bits, a.Mq, a.gx);
+  const int nb = (p.n_slices + 7) / 8 * 8;
+  hipLaunchKernelGGL((base_fused_kernel<DT>), dim3((unsigned)nb), dim3(kW), 0, s, a.slices, p.n_slices,
+                     a.run_start, a.ukey, a.umask, p.rbits, p.hbits, a.hc0, a.hc1, a.qt,
+                     a.rt, a.rec_off, a.xq_perm, a.rec, a.D, base_record_stride(a.D), a.s2, a.wmax_bits,
+                     a.Mq, p.qmax, a.partial, a.gx);
 }
 
 }  // namespace
 
 int base_record_stride(int D) { return (D + 1 + 3) / 4 * 4; }
 
-hipError_t launch_base_records(const double* xr_perm, const double* wr_perm, const int32_t* leaf_of_pos,
-                               const double* rctr, int64_t n, int D, const unsigned long long* wmax_bits,
-                               float* rec, hipStream_t s) {
-  hipLaunchKernelGGL(base_records_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, xr_perm,
-                     wr_perm, leaf_of_pos, rctr, n, D, base_record_stride(D), wmax_bits, rec);
+int64_t base_records_capacity(int64_t n_points, int n_nodes) {
+  // padding of at most kPad - 1 per leaf, plus a tail for the 16-float reads
+  return n_points + (int64_t)(kPad - 1) * n_nodes + 16;
+}
+
+size_t base_records_temp_bytes(int n_nodes) {
+  size_t b = 0;
+  (void)rocprim::exclusive_scan((void*)nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
+                                (size_t)n_nodes, rocprim::plus<int32_t>());
+  return b;
+}
+
+hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(a.rec, 0, sizeof(float) * a.rec_capacity * base_record_stride(a.D), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pad_counts_kernel, dim3((unsigned)ceil_div(a.n_nodes, 256)), dim3(256), 0, s, a.left,
+                     a.count, a.n_nodes, a.padded);
+  size_t bytes = a.temp_bytes;
+  e = rocprim::exclusive_scan(a.temp, bytes, a.padded, a.rec_off, 0, (size_t)a.n_nodes,
+                              rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(base_records_kernel, dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, s, a.xr_perm,
+                     a.wr_perm, a.leaf_of_pos, a.begin, a.rec_off, a.rctr, a.n, a.D, base_record_stride(a.D),
+                     a.wmax_bits, a.rec);
   return hipGetLastError();
 }
 
@@ -285,12 +425,34 @@ size_t base_fused_temp_bytes(int64_t n) {
   return std::max(b1, std::max(b2, b3));
 }
 
+// Partial-sum slots of one call: 2 * 16384 * 64 / qmax, so the partials take
+// 2 * 16384 * 64 * 8 doubles (128 MiB) whatever the leaf size.
+int base_partial_slots(int max_leaf) {
+  const int qmax = (int)ceil_div(std::max(1, max_leaf), kW) * kW;
+  return 2 * 16384 * kW / qmax;
+}
+
+// Entries per slice: about base_partial_slots / 2 slices in all (16 per SIMD
+// at leaf sizes <= 64), at least 8 entries each.  A run of len > S entries
+// has ceil(len / S) < 2 len / S slices, so the runs of several slices hold
+// fewer than 2 n_unique / S <= base_partial_slots slices.
+int base_slice_entries(int64_t n_unique, int max_leaf) {
+  const int64_t target = base_partial_slots(max_leaf) / 2;
+  return (int)std::max<int64_t>(8, (n_unique + target - 1) / target);
+}
+
+int64_t base_max_slices(int64_t n_entries) {
+  // runs <= entries, and slices <= runs + entries / S with S >= 8
+  return n_entries + n_entries / 8 + 1;
+}
+
 hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t s) {
-  p->nruns = 0;
+  p->n_slices = 0;
   const int64_t n = a.n_entries;
   if (n == 0 || a.n_groups == 0) return hipSuccess;
   p->rbits = bits_for(a.n_rnodes + 1);
   p->hbits = bits_for(a.n_hblocks + 1);
+  p->qmax = (int)ceil_div(a.max_leaf, kW) * kW;
   const int qbits = bits_for(a.n_qnodes + 1);
   if (p->rbits + p->hbits + qbits > 63 || n > INT32_MAX / 2) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fuse_keys_kernel, dim3((unsigned)a.n_groups), dim3(64), 0, s, a.grp, a.n_groups,
@@ -303,14 +465,14 @@ hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t
   if (e != hipSuccess) return e;
   bytes = a.temp_bytes;
   e = rocprim::reduce_by_key(a.temp, bytes, a.key_sorted, a.bit_sorted, (size_t)n, a.ukey, a.umask,
-                             a.n_unique, BitOr(), rocprim::equal_to<unsigned long long>(), s);
+                             a.counters, BitOr(), rocprim::equal_to<unsigned long long>(), s);
   if (e != hipSuccess) return e;
   int32_t nu = 0;
-  e = hipMemcpyAsync(&nu, a.n_unique, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(&nu, a.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   if (nu <= 0 || nu > n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(run_flags_kernel, dim3((unsigned)ceil_div(nu, 256)), dim3(256), 0, s, a.ukey, nu,
+  hipLaunchKernelGGL(run_flags_kernel, dim3((unsigned)ceil_div(nu, 1024)), dim3(1024), 0, s, a.ukey, nu,
                      p->rbits, p->hbits, a.qt.count, a.rt.count, a.flag, a.dist_evals);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -318,20 +480,43 @@ hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t
   e = rocprim::exclusive_scan(a.temp, bytes, a.flag, a.pos, 0, (size_t)nu, rocprim::plus<int32_t>(), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(run_scatter_kernel, dim3((unsigned)ceil_div(nu, 256)), dim3(256), 0, s, a.flag,
-                     a.pos, nu, a.run_start, a.n_unique);
+                     a.pos, nu, a.run_start, a.counters + 1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int32_t nr = 0;
-  e = hipMemcpyAsync(&nr, a.n_unique, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  // Slices: counts per run into flag and mflag, their exclusive scans into
+  // pos and mpos (runs <= nu, counts past the last run are 0).
+  const int S = base_slice_entries(nu, a.max_leaf);
+  hipLaunchKernelGGL(slice_counts_kernel, dim3((unsigned)ceil_div(nu, 256)), dim3(256), 0, s, a.run_start,
+                     a.counters + 1, nu, S, a.flag, a.mflag);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bytes = a.temp_bytes;
+  e = rocprim::exclusive_scan(a.temp, bytes, a.flag, a.pos, 0, (size_t)nu, rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  bytes = a.temp_bytes;
+  e = rocprim::exclusive_scan(a.temp, bytes, a.mflag, a.mpos, 0, (size_t)nu, rocprim::plus<int32_t>(), s);
+  if (e != hipSuccess) return e;
+  p->max_slots = base_partial_slots(a.max_leaf);
+  hipLaunchKernelGGL(slices_kernel, dim3((unsigned)ceil_div(nu, 256)), dim3(256), 0, s, a.run_start,
+                     a.counters + 1, a.flag, a.pos, a.mflag, a.mpos, S, p->max_slots, a.slices, a.slots,
+                     a.counters);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  p->slice_entries = S;
+  int32_t cnt[4] = {0, 0, 0, 0};
+  e = hipMemcpyAsync(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  if (nr <= 0 || nr > nu) return hipErrorInvalidValue;
-  p->nruns = nr;
+  // slices <= runs + nu / S; slots < 2 nu / S <= max_slots
+  if (cnt[2] <= 0 || (int64_t)cnt[2] > base_max_slices(n) || cnt[3] < 0 || cnt[3] > p->max_slots)
+    return hipErrorInvalidValue;
+  p->n_slices = cnt[2];
+  p->n_slots = cnt[3];
   return hipSuccess;
 }
 
 hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s) {
-  if (p.nruns == 0) return hipSuccess;
+  if (p.n_slices == 0) return hipSuccess;
   switch (a.D) {
     case 1: launch_fused_t<1>(a, p, s); break;
     case 2: launch_fused_t<2>(a, p, s); break;
@@ -342,6 +527,12 @@ hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hip
     case 16: launch_fused_t<16>(a, p, s); break;
     default: launch_fused_t<0>(a, p, s); break;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p.n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(base_reduce_kernel, dim3((unsigned)p.n_slots), dim3(kW), 0, s, a.slots, p.n_slots,
+                     a.run_start, a.ukey, p.rbits, p.hbits, a.hc0, a.hc1, a.qt, a.wmax_bits,
+                     a.Mq, p.qmax, a.partial, a.gx);
   return hipGetLastError();
 }
 
