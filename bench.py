@@ -61,6 +61,24 @@ def alu_peak_pairs_per_s(D):
     return LANE_SLOTS_PER_S / base_tile_model(D)[1]
 
 
+def measured_traffic(kernel_source, profile):
+    """HBM bytes per launch recorded by the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if the kernel source still hashes to the recorded
+    prefix (None otherwise: the counters describe an older kernel)."""
+    import hashlib
+    import re
+    try:
+        text = open(profile).read()
+        src = open(kernel_source, "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"sha256 prefix: (\w+)", text)
+    t = re.search(r"traffic_bytes_per_launch \S+ = (\d+)", text)
+    if not m or not t or hashlib.sha256(src).hexdigest()[:16] != m.group(1):
+        return None
+    return float(t.group(1))
+
+
 def cpu_baseline(wl, n_queries, seed=0):
     """The FP64 exhaustive oracle on a bounded sample of the workload's queries
     (all references, all bandwidths), single-threaded."""
@@ -173,9 +191,14 @@ def main():
         flops, slots = fused_base_model(D, dist_evals / n, base_evals / n)
         achieved = flops / (avg_ms * 1e-3) / 1e12
         peak = LANE_SLOTS_PER_S * flops / slots / 1e12
+        traffic = None
+        if args.leaf_size == 64:
+            traffic = measured_traffic(
+                os.path.join(ROOT, "paper_1206_6857_amd", "csrc", "k_base.hip"),
+                os.path.join(ROOT, "profiles", "base_fused_kernel_%s_hbm_bytes.txt" % wl.name))
         result["roofline"] = {"bound": "alu", "kernel": "base_fused_kernel", "achieved": achieved,
                               "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                              "traffic": None, "avg_launch_ms": avg_ms,
+                              "traffic": traffic, "avg_launch_ms": avg_ms,
                               "pair_evals_per_launch": base_evals / n,
                               "dist_evals_per_launch": dist_evals / n}
     result["breakdown_ms"] = {
