@@ -23,7 +23,12 @@ exhaustive   the plain definition G(x_q) = sum_r w_r exp(-|x_q-x_r|^2/2h^2)
 kdtree       kd-tree with cached statistics (section 6, Figure 5).
 dualtree     the dual-tree algorithm with token error control (section 5,
              Theorem 2; section 6, Figures 6-8) run level by level, plus the
-             depth-first form printed in the paper.
+             depth-first form printed in the paper; it can also replay
+             another run's choices after certifying each with its own bounds.
+mlp          the pair-policy network (two ReLU layers), its masked squared
+             loss, gradient and one Adam step, in FP64.
+policy       features, cost-to-go and training records of the pair policy,
+             computed from a decision trace.
 
 Every function that has no independent pin says "parity unpinned" in its
 docstring.  All functions here are pinned by tests under `tests/`.

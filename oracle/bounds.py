@@ -116,12 +116,11 @@ def _pow_int(D, e):
     return v
 
 
-def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7):
-    """Figure 6.  Smallest feasible order per method, cost model
-    c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1},
-    c_Direct = D N_Q N_R, first minimum in the order DH, DL, H2L, DIRECT.
-    `mask` restricts the candidate methods (bit 0 DH, 1 DL, 2 H2L) for
-    ablations.  Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
+def feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask=7):
+    """Figure 6, first half: for each series method, the smallest order
+    p <= plimit whose bound meets maxerr.  Returns {name: (p, E)} for the
+    methods that have one; `mask` restricts the candidates (bit 0 DH, 1 DL,
+    2 H2L)."""
     found = {}
     for bit, name, fn in ((1, "DH", lambda p: e_dh(W_R, g, D, p, r_R)),
                           (2, "DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
@@ -133,6 +132,16 @@ def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7):
             if E <= maxerr:
                 found[name] = (p, E)
                 break
+    return found
+
+
+def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7):
+    """Figure 6.  Smallest feasible order per method, cost model
+    c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1},
+    c_Direct = D N_Q N_R, first minimum in the order DH, DL, H2L, DIRECT.
+    `mask` restricts the candidate methods (bit 0 DH, 1 DL, 2 H2L) for
+    ablations.  Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
+    found = feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask)
     costs = []
     for name in ("DH", "DL", "H2L"):
         if name in found:

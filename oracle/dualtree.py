@@ -59,7 +59,7 @@ import math
 
 import numpy as np
 
-from .bounds import best_method, box_dist2, e_fd, need
+from .bounds import best_method, box_dist2, e_fd, feasible_orders, need
 from .exp64 import exp64
 from .kdtree import attach_moments, build_kdtree
 from .multiindex import num_terms, plimit_for
@@ -67,6 +67,7 @@ from .series import direct_local, eval_hermite, eval_local, h2l, l2l, scale_mome
 
 FD, DH, DL, H2L, BASE, SPLIT = 0, 1, 2, 3, 4, 5
 CODE = {"DH": DH, "DL": DL, "H2L": H2L}
+NAME = {DH: "DH", DL: "DL", H2L: "H2L"}
 METHODS = ("dito", "dfdo", "dfd")
 
 
@@ -74,10 +75,26 @@ class Result:
     pass
 
 
+class CertificationError(AssertionError):
+    """A replayed choice that the error bounds do not admit."""
+
+
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
-             method="dito", mono=None, trace=False, fmm_mask=7):
+             method="dito", mono=None, trace=False, fmm_mask=7, replay=None,
+             record_feasible=False):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
-    decision trace: a list of (h_index, level, Q, R, code, p) tuples."""
+    decision trace: a list of (h_index, level, Q, R, code, p) tuples.
+
+    replay: {(h_index, level, Q, R): (code, p)} of another run's decisions.
+    Where bestMethod is reached, the recorded choice replaces the cost rule of
+    Figure 6, after a check with this oracle's own bounds: a series method
+    must be admitted (its bound meets maxerr) at exactly the recorded order,
+    the smallest that does; otherwise CertificationError.  The token book is
+    kept as for any choice, so the run reproduces the other run's pair lists
+    when, and only when, its bookkeeping matches.
+    record_feasible: keep {(h_index, level, Q, R): {method: p}} of the
+    smallest admitted order of every series method wherever bestMethod is
+    reached (res.feasible)."""
     xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
     if mono is None:
         mono = xq is xr
@@ -99,6 +116,8 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.trace = [] if trace else None
     res.counts = np.zeros((len(hs), 6), dtype=np.int64)
     res.fmm_mask = fmm_mask
+    res.replay = replay
+    res.feasible = {} if record_feasible else None
     for k, h in enumerate(hs):
         res.G[k] = _one_bandwidth(k, float(h), qt, rt, xq, mono, P, eps_alg, method, res)
     return res
@@ -149,10 +168,29 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                     tt = t if use_tokens else 0.0
                     maxerr = ((eps_alg * (WR + tt)) * L) / Wtot
                     g = exp64(-dmin2 * inv_4h2)
-                    name, p, E = best_method(D, P, maxerr, WR, g, float(qt.rinf[Q]) * inv_h,
-                                             float(rt.rinf[R]) * inv_h,
-                                             int(qt.count[Q]), int(rt.count[R]),
-                                             mask=res.fmm_mask)
+                    rQ, rR = float(qt.rinf[Q]) * inv_h, float(rt.rinf[R]) * inv_h
+                    key = (hk, level, Q, R)
+                    if res.feasible is not None or res.replay is not None:
+                        found = feasible_orders(D, P, maxerr, WR, g, rQ, rR, res.fmm_mask)
+                        if res.feasible is not None:
+                            res.feasible[key] = {n: found[n][0] for n in found}
+                    if res.replay is not None:
+                        rc, rp = res.replay[key]
+                        if rc in (DH, DL, H2L):
+                            name = NAME[rc]
+                            if name not in found or found[name][0] != rp:
+                                raise CertificationError(
+                                    "pair %s: %s at order %d is not admitted (smallest "
+                                    "admitted: %s)" % (key, name, rp, found.get(name)))
+                            p, E = found[name]
+                        elif rc in (BASE, SPLIT):
+                            name, p, E = "DIRECT", 0, math.inf
+                        else:
+                            raise CertificationError("pair %s: code %d at bestMethod" % (key, rc))
+                    else:
+                        name, p, E = best_method(D, P, maxerr, WR, g, rQ, rR,
+                                                 int(qt.count[Q]), int(rt.count[R]),
+                                                 mask=res.fmm_mask)
                     if name != "DIRECT":
                         if use_tokens:
                             t = t - need(E, WR, L, Wtot, eps_alg)
