@@ -140,8 +140,8 @@ def main():
         for _ in range(warmup):
             ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, leaf_size=args.leaf_size)
         torch.cuda.synchronize()
-        kms = np.zeros(8)
-        kl = np.zeros(8, dtype=np.int64)
+        kms = np.zeros(12)
+        kl = np.zeros(12, dtype=np.int64)
         evals = np.zeros(2, dtype=np.int64)
         t0 = time.perf_counter()
         for _ in range(steps):

@@ -85,6 +85,12 @@ typedef struct gs_options {
                                traversal's memory; 0: 2^30).  A chunk of bandwidths whose
                                frontier exceeds it is retried with half the bandwidths;
                                GS_EOVERFLOW when one bandwidth alone exceeds it. */
+  double log_explore;       /* with log_pairs: share (0..1, default 0) of the pairs
+                               reaching bestMethod whose action is drawn uniformly
+                               from the admitted ones (each admitted series method
+                               at its order, or the direct path) instead of the
+                               rule's, so that the log also holds costs the rule
+                               never incurs.  log_pairs needs policy = GS_RULE. */
 } gs_options;
 
 typedef struct gs_stats {
@@ -102,8 +108,8 @@ typedef struct gs_stats {
   double t_total_ms;        /* wall time of the last gauss_sum call */
   /* With kernel_timing = 1: device milliseconds and launch counts per kernel class,
    * indexed by GS_K_*. */
-  double k_ms[8];
-  int64_t k_launches[8];
+  double k_ms[12];
+  int64_t k_launches[12];
   int64_t base_dist_evals;  /* point pairs whose squared distance the base tiles
                                formed (one per pair for all bandwidths of a block) */
   int32_t h_chunks;         /* bandwidth chunks the traversal was split into */
@@ -114,11 +120,14 @@ typedef struct gs_stats {
 enum {
   GS_K_BASE = 0,        /* base-case tiles */
   GS_K_EXHAUSTIVE = 1,  /* plain exhaustive tiles */
-  GS_K_DECIDE = 2,      /* frontier decisions and emission */
-  GS_K_SERIES = 3,      /* DH, DL and H2L work */
+  GS_K_DECIDE = 2,      /* frontier decisions, policy inference, scan and emission */
+  GS_K_SERIES = 3,      /* DH, DL and H2L work together */
   GS_K_POST = 4,        /* L2L and leaf evaluation */
   GS_K_TREE = 5,        /* tree construction */
-  GS_K_MOMENTS = 6      /* leaf moments and H2H */
+  GS_K_MOMENTS = 6,     /* leaf moments and H2H */
+  GS_K_DH = 7,          /* of GS_K_SERIES: direct Hermite evaluation */
+  GS_K_DL = 8,          /* of GS_K_SERIES: direct local accumulation */
+  GS_K_H2L = 9          /* of GS_K_SERIES: Hermite-to-local translation */
 };
 
 /* Fill *opt with the defaults listed above. */
@@ -178,6 +187,99 @@ gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_p
  * code, order p) with code 0 FD, 1 DH, 2 DL, 3 H2L, 4 base case, 5 split
  * (Figure 7).  records may be NULL to read *n_records first. */
 gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records);
+
+/* ---------------------------------------------------------------------------
+ * Learned pair policy.
+ *
+ * bestMethod (section 6, Figure 6) chooses among DH, DL, H2L and the direct
+ * path (base case or split) with an operation-count model whose cut-offs the
+ * paper calls rough.  With policy = GS_LEARNED a small network predicts, from
+ * the pair's geometry only, the log2 cost in nanoseconds of four actions: DH,
+ * DL and H2L at the smallest order their bound admits, and "recurse", the
+ * cost-to-go of the direct path.  The cheapest predicted action is taken; a
+ * series method only where its error bound admits an order (Lemmas 4-6, the
+ * test the rule uses), otherwise the rule decides.  Theorem 2 therefore holds
+ * whatever the network predicts.
+ *
+ * Network: 16 features -> 64 ReLU -> 64 ReLU -> 4 outputs.  Parameter vector
+ * (float, 5508): W1[64][16], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]; in
+ * gs_policy_get_params / gs_policy_set_params it is followed by the
+ * standardisation mu_x[16], sd_x[16], mu_y, sd_y (5542 floats in all): the
+ * network sees (x - mu_x) / sd_x and predicts (log2 cost - mu_y) / sd_y.
+ *
+ * Training record (float[24]): features[16], targets[4] (log2 ns), masks[4]
+ * (1 where the target is known).  Features of a pair (Q, R) at bandwidth h:
+ * log2 N_Q, log2 N_R, log2(1 + dmin/h), log2(1 + dmax/h), log2 h,
+ * log2(1 + rinf_Q/h), log2(1 + rinf_R/h), [Q is a leaf], [R is a leaf], D/16,
+ * then six zeros.  Costs follow gs_cost_model: every decided pair costs
+ * pair_ns, plus N_Q C(D+p-1,D) dh_ns (DH), N_R C dl_ns (DL), C^2 h2l_ns (H2L),
+ * N_Q N_R base_ns (base case), or its children's cost-to-go (split).
+ *
+ * Callers: gauss_sum with log_pairs = 1 (and keep_trace implied) records one
+ * training record per pair that reaches bestMethod; gs_policy_train* fits the
+ * network with the library's own gradient and Adam kernels; gauss_sum with
+ * policy = GS_LEARNED uses it.
+ * ------------------------------------------------------------------------- */
+
+typedef struct gs_cost_model {
+  double pair_ns;   /* deciding one node pair */
+  double dh_ns;     /* per query point and term of a direct Hermite evaluation */
+  double dl_ns;     /* per reference point and term of a direct local accumulation */
+  double h2l_ns;    /* per (term x term) of a Hermite-to-local translation */
+  double base_ns;   /* per point pair of a base case */
+} gs_cost_model;
+
+typedef struct gs_train_opts {
+  int32_t struct_size;  /* sizeof(gs_train_opts); set by gs_default_train_opts */
+  int32_t steps;        /* Adam steps (default 3000) */
+  int32_t batch;        /* records per step (default 4096; all if fewer) */
+  int32_t reinit;       /* 1 (default): new standardisation from the records and
+                           fresh parameters from seed; 0: continue from the
+                           current parameters */
+  uint64_t seed;        /* parameter initialisation and batch order (default 1) */
+  double lr;            /* Adam learning rate (default 2e-3; betas 0.9, 0.999) */
+} gs_train_opts;
+
+void gs_default_train_opts(gs_train_opts* opts);
+
+/* Cost model of the policy's training targets (defaults: measured on one
+ * MI355X).  All fields must be >= 0. */
+gs_status gs_policy_set_cost_model(gs_ctx* ctx, const gs_cost_model* cm);
+gs_status gs_policy_get_cost_model(gs_ctx* ctx, gs_cost_model* cm);
+
+/* Training records of the last gauss_sum call made with log_pairs = 1:
+ * records[n][24] and keys[n][4] = (bandwidth index, level, Q, R), host
+ * pointers, either may be NULL; call with both NULL to read *n_records. */
+gs_status gs_policy_get_log(gs_ctx* ctx, int64_t* n_records, float* records, int32_t* keys);
+
+/* Writes those records to a file (binary, this library's format). */
+gs_status gs_policy_write_log(gs_ctx* ctx, const char* path);
+
+/* Trains the policy on the records of a log file (gs_policy_write_log) or of
+ * an array records[n][24] (host or device).  *final_loss (may be NULL): the
+ * masked mean squared error over all records, in standardised units.
+ * GS_EINVAL for n < 1, steps < 0, batch < 1, lr <= 0. */
+gs_status gs_policy_train(gs_ctx* ctx, const char* log_path, const gs_train_opts* opts,
+                          float* final_loss);
+gs_status gs_policy_train_records(gs_ctx* ctx, const float* records, int64_t n,
+                                  const gs_train_opts* opts, float* final_loss);
+
+/* Gradient of the masked mean squared error at the current parameters over
+ * records[n][24] (host or device): grad[5508] (host or device), *loss. */
+gs_status gs_policy_gradient(gs_ctx* ctx, const float* records, int64_t n, float* grad,
+                             float* loss);
+
+/* Network outputs for raw features[n][16]: scores[n][4], standardised units
+ * (host or device pointers; the half-precision inference kernel). */
+gs_status gs_policy_predict(gs_ctx* ctx, const float* features, int64_t n, float* scores);
+
+/* Parameters and standardisation, 5542 floats (host pointers; n must be 5542). */
+gs_status gs_policy_get_params(gs_ctx* ctx, float* params, int64_t n);
+gs_status gs_policy_set_params(gs_ctx* ctx, const float* params, int64_t n);
+
+/* Parameter file with the cost model (binary, this library's format). */
+gs_status gs_policy_save(gs_ctx* ctx, const char* path);
+gs_status gs_policy_load(gs_ctx* ctx, const char* path);
 
 /* Multi-index set of the O(D^p) expansions (section 2): every alpha with
  * |alpha| < p, ordered by degree and, inside a degree, in decreasing

@@ -89,7 +89,8 @@ class Context:
         queries may be the same object as refs (monochromatic).  Options:
         method ('dualtree', 'exhaustive', 'dfd', 'dfdo'), policy ('rule',
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
-        keep_trace, log_pairs, blocking, fmm_mask, kernel_timing, h_chunk."""
+        keep_trace, log_pairs, log_explore, blocking, fmm_mask, kernel_timing,
+        h_chunk, max_frontier."""
         lib = _lib.load()
         same = queries is refs
         r = _Arr(refs)
@@ -153,6 +154,88 @@ class Context:
         self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt),
                                     *[t[k].ctypes.data for k in order]))
         return t
+
+    # ---- learned pair policy (gs_policy_*) ----
+
+    def policy_log(self):
+        """(records[n][24], keys[n][4]) of the last call made with log_pairs=1."""
+        lib = _lib.load()
+        n = ctypes.c_int64()
+        self._check(lib.gs_policy_get_log(self._h, ctypes.byref(n), None, None))
+        rec = np.zeros((n.value, _lib.POLICY_RECORD), dtype=np.float32)
+        keys = np.zeros((n.value, 4), dtype=np.int32)
+        self._check(lib.gs_policy_get_log(self._h, ctypes.byref(n), rec.ctypes.data, keys.ctypes.data))
+        return rec, keys
+
+    def policy_write_log(self, path):
+        self._check(_lib.load().gs_policy_write_log(self._h, str(path).encode()))
+
+    @staticmethod
+    def _train_opts(**kw):
+        o = _lib.GsTrainOpts()
+        _lib.load().gs_default_train_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise TypeError("unknown training option %r" % k)
+            setattr(o, k, v)
+        return o
+
+    def policy_train(self, records=None, log_path=None, **kw):
+        """Fit the policy network (library kernels); returns the final loss."""
+        lib = _lib.load()
+        o = self._train_opts(**kw)
+        loss = ctypes.c_float()
+        if log_path is not None:
+            self._check(lib.gs_policy_train(self._h, str(log_path).encode(), ctypes.byref(o),
+                                            ctypes.byref(loss)))
+        else:
+            rec = np.ascontiguousarray(records, dtype=np.float32)
+            self._check(lib.gs_policy_train_records(self._h, rec.ctypes.data, rec.shape[0],
+                                                    ctypes.byref(o), ctypes.byref(loss)))
+        return loss.value
+
+    def policy_gradient(self, records):
+        rec = np.ascontiguousarray(records, dtype=np.float32)
+        g = np.zeros(_lib.POLICY_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(_lib.load().gs_policy_gradient(self._h, rec.ctypes.data, rec.shape[0], g.ctypes.data,
+                                                   ctypes.byref(loss)))
+        return g, loss.value
+
+    def policy_predict(self, features):
+        f = np.ascontiguousarray(features, dtype=np.float32)
+        out = np.zeros((f.shape[0], 4), dtype=np.float32)
+        self._check(_lib.load().gs_policy_predict(self._h, f.ctypes.data, f.shape[0], out.ctypes.data))
+        return out
+
+    def policy_params(self):
+        out = np.zeros(_lib.POLICY_PARAM_FLOATS, dtype=np.float32)
+        self._check(_lib.load().gs_policy_get_params(self._h, out.ctypes.data, out.size))
+        return out
+
+    def policy_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(_lib.load().gs_policy_set_params(self._h, p.ctypes.data, p.size))
+
+    def policy_cost_model(self, **kw):
+        """Get (no arguments) or update the cost model: pair_ns, dh_ns, dl_ns,
+        h2l_ns, base_ns."""
+        lib = _lib.load()
+        cm = _lib.GsCostModel()
+        self._check(lib.gs_policy_get_cost_model(self._h, ctypes.byref(cm)))
+        if kw:
+            for k, v in kw.items():
+                if not hasattr(cm, k):
+                    raise TypeError("unknown cost %r" % k)
+                setattr(cm, k, float(v))
+            self._check(lib.gs_policy_set_cost_model(self._h, ctypes.byref(cm)))
+        return {k: getattr(cm, k) for k, _ in cm._fields_}
+
+    def policy_save(self, path):
+        self._check(_lib.load().gs_policy_save(self._h, str(path).encode()))
+
+    def policy_load(self, path):
+        self._check(_lib.load().gs_policy_load(self._h, str(path).encode()))
 
     def get_trace(self):
         """Decision records (h, level, Q, R, code, p) of the last keep_trace call."""

@@ -22,7 +22,15 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_EDEVICE",
 # Every function the header declares; tests check that the library exports them.
 EXPORTED = ["gs_default_options", "gs_create", "gs_destroy", "gauss_sum", "gs_get_stats",
             "gs_get_pair_counts", "gs_last_error", "gs_get_tree", "gs_get_trace",
-            "gs_multi_indices"]
+            "gs_multi_indices", "gs_default_train_opts", "gs_policy_set_cost_model",
+            "gs_policy_get_cost_model", "gs_policy_get_log", "gs_policy_write_log",
+            "gs_policy_train", "gs_policy_train_records", "gs_policy_gradient",
+            "gs_policy_predict", "gs_policy_get_params", "gs_policy_set_params",
+            "gs_policy_save", "gs_policy_load"]
+
+POLICY_PARAMS = 5508          # W1[64][16] b1[64] W2[64][64] b2[64] W3[4][64] b3[4]
+POLICY_PARAM_FLOATS = 5542    # + mu_x[16] sd_x[16] mu_y sd_y
+POLICY_RECORD = 24            # features[16] targets[4] masks[4]
 
 
 class GsOptions(ctypes.Structure):
@@ -32,7 +40,18 @@ class GsOptions(ctypes.Structure):
                 ("blocking", ctypes.c_int32), ("keep_trace", ctypes.c_int32),
                 ("log_pairs", ctypes.c_int32), ("fmm_mask", ctypes.c_int32),
                 ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
-                ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64)]
+                ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
+                ("log_explore", ctypes.c_double)]
+
+
+class GsCostModel(ctypes.Structure):
+    _fields_ = [("pair_ns", ctypes.c_double), ("dh_ns", ctypes.c_double), ("dl_ns", ctypes.c_double),
+                ("h2l_ns", ctypes.c_double), ("base_ns", ctypes.c_double)]
+
+
+class GsTrainOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("steps", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("reinit", ctypes.c_int32), ("seed", ctypes.c_uint64), ("lr", ctypes.c_double)]
 
 
 class GsStats(ctypes.Structure):
@@ -44,10 +63,10 @@ class GsStats(ctypes.Structure):
                 ("t_stage_ms", ctypes.c_double), ("t_tree_ms", ctypes.c_double),
                 ("t_moments_ms", ctypes.c_double), ("t_traverse_ms", ctypes.c_double),
                 ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 8),
-                ("k_launches", ctypes.c_int64 * 8), ("base_dist_evals", ctypes.c_int64),
+                ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 12),
+                ("k_launches", ctypes.c_int64 * 12), ("base_dist_evals", ctypes.c_int64),
                 ("h_chunks", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
-K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS = range(7)
+K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS, K_DH, K_DL, K_H2L = range(10)
 
 
 _lib = None
@@ -84,5 +103,25 @@ def load():
     lib.gs_get_trace.restype = i32
     lib.gs_multi_indices.argtypes = [i32, i32, ctypes.POINTER(i64), P]
     lib.gs_multi_indices.restype = i32
+    pf = ctypes.POINTER(ctypes.c_float)
+    lib.gs_default_train_opts.argtypes = [ctypes.POINTER(GsTrainOpts)]
+    lib.gs_default_train_opts.restype = None
+    lib.gs_policy_set_cost_model.argtypes = [P, ctypes.POINTER(GsCostModel)]
+    lib.gs_policy_get_cost_model.argtypes = [P, ctypes.POINTER(GsCostModel)]
+    lib.gs_policy_get_log.argtypes = [P, ctypes.POINTER(i64), P, P]
+    lib.gs_policy_write_log.argtypes = [P, ctypes.c_char_p]
+    lib.gs_policy_train.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(GsTrainOpts), pf]
+    lib.gs_policy_train_records.argtypes = [P, P, i64, ctypes.POINTER(GsTrainOpts), pf]
+    lib.gs_policy_gradient.argtypes = [P, P, i64, P, pf]
+    lib.gs_policy_predict.argtypes = [P, P, i64, P]
+    lib.gs_policy_get_params.argtypes = [P, P, i64]
+    lib.gs_policy_set_params.argtypes = [P, P, i64]
+    lib.gs_policy_save.argtypes = [P, ctypes.c_char_p]
+    lib.gs_policy_load.argtypes = [P, ctypes.c_char_p]
+    for name in ("gs_policy_set_cost_model", "gs_policy_get_cost_model", "gs_policy_get_log",
+                 "gs_policy_write_log", "gs_policy_train", "gs_policy_train_records",
+                 "gs_policy_gradient", "gs_policy_predict", "gs_policy_get_params",
+                 "gs_policy_set_params", "gs_policy_save", "gs_policy_load"):
+        getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -33,6 +33,8 @@ SOURCES = [
     ("k_series.hip", []),
     ("k_series_fast.hip", []),
     ("k_base.hip", []),
+    ("k_policy.hip", []),
+    ("policy.cpp", []),
     ("dualtree.hip", NO_CONTRACT),
     ("capi.cpp", NO_CONTRACT),
 ]

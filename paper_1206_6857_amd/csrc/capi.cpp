@@ -178,6 +178,7 @@ gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream) {
     ctx->own_stream = true;
   }
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  policy_default_costs(ctx->policy);
   *out = ctx;
   return GS_OK;
 }
@@ -245,6 +246,132 @@ gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alph
   return GS_OK;
 }
 
+void gs_default_train_opts(gs_train_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(gs_train_opts);
+  o->steps = 3000;
+  o->batch = 4096;
+  o->reinit = 1;
+  o->seed = 1;
+  o->lr = 2e-3;
+}
+
+gs_status gs_policy_set_cost_model(gs_ctx* ctx, const gs_cost_model* cm) {
+  if (!ctx || !cm) return GS_EINVAL;
+  const double v[5] = {cm->pair_ns, cm->dh_ns, cm->dl_ns, cm->h2l_ns, cm->base_ns};
+  for (double x : v)
+    if (!(x >= 0.0) || !std::isfinite(x)) GS_FAIL(ctx, GS_EINVAL, "cost model entries must be finite and >= 0");
+  PolicyState& ps = ctx->policy;
+  ps.c_pair = v[0];
+  ps.c_dh = v[1];
+  ps.c_dl = v[2];
+  ps.c_h2l = v[3];
+  ps.c_base = v[4];
+  return GS_OK;
+}
+
+gs_status gs_policy_get_cost_model(gs_ctx* ctx, gs_cost_model* cm) {
+  if (!ctx || !cm) return GS_EINVAL;
+  const PolicyState& ps = ctx->policy;
+  cm->pair_ns = ps.c_pair;
+  cm->dh_ns = ps.c_dh;
+  cm->dl_ns = ps.c_dl;
+  cm->h2l_ns = ps.c_h2l;
+  cm->base_ns = ps.c_base;
+  return GS_OK;
+}
+
+gs_status gs_policy_get_log(gs_ctx* ctx, int64_t* n_records, float* records, int32_t* keys) {
+  if (!ctx || !n_records) return GS_EINVAL;
+  const PolicyState& ps = ctx->policy;
+  *n_records = (int64_t)(ps.log.size() / kPolicyRecord);
+  if (records) std::copy(ps.log.begin(), ps.log.end(), records);
+  if (keys) std::copy(ps.log_keys.begin(), ps.log_keys.end(), keys);
+  return GS_OK;
+}
+
+gs_status gs_policy_write_log(gs_ctx* ctx, const char* path) {
+  if (!ctx || !path) return GS_EINVAL;
+  ctx->err.clear();
+  return policy_write_log(ctx, path);
+}
+
+static gs_status train_opts_of(gs_ctx* ctx, const gs_train_opts* in, gs_train_opts* o) {
+  gs_default_train_opts(o);
+  if (in) {
+    if (in->struct_size != (int32_t)sizeof(gs_train_opts))
+      GS_FAIL(ctx, GS_EINVAL, "gs_train_opts.struct_size does not match this library");
+    *o = *in;
+  }
+  return GS_OK;
+}
+
+gs_status gs_policy_train(gs_ctx* ctx, const char* log_path, const gs_train_opts* opts, float* final_loss) {
+  if (!ctx || !log_path) return GS_EINVAL;
+  ctx->err.clear();
+  gs_train_opts o;
+  gs_status s = train_opts_of(ctx, opts, &o);
+  if (s != GS_OK) return s;
+  std::vector<float> rec;
+  s = policy_read_log(ctx, log_path, &rec);
+  if (s != GS_OK) return s;
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  return policy_train(ctx, rec.data(), (int64_t)(rec.size() / kPolicyRecord), o, final_loss);
+}
+
+gs_status gs_policy_train_records(gs_ctx* ctx, const float* records, int64_t n, const gs_train_opts* opts,
+                                  float* final_loss) {
+  if (!ctx || !records) return GS_EINVAL;
+  ctx->err.clear();
+  gs_train_opts o;
+  gs_status s = train_opts_of(ctx, opts, &o);
+  if (s != GS_OK) return s;
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  return policy_train(ctx, records, n, o, final_loss);
+}
+
+gs_status gs_policy_gradient(gs_ctx* ctx, const float* records, int64_t n, float* grad, float* loss) {
+  if (!ctx || !records) return GS_EINVAL;
+  ctx->err.clear();
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  return policy_gradient(ctx, records, n, grad, loss);
+}
+
+gs_status gs_policy_predict(gs_ctx* ctx, const float* features, int64_t n, float* scores) {
+  if (!ctx || !features || !scores) return GS_EINVAL;
+  ctx->err.clear();
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  return policy_predict(ctx, features, n, scores);
+}
+
+gs_status gs_policy_get_params(gs_ctx* ctx, float* params, int64_t n) {
+  if (!ctx || !params) return GS_EINVAL;
+  if (n != policy_param_floats()) GS_FAIL(ctx, GS_EINVAL, "the parameter array holds 5542 floats");
+  if (!ctx->policy.ready) GS_FAIL(ctx, GS_EINVAL, "the learned policy has no parameters");
+  policy_get_params(ctx->policy, params);
+  return GS_OK;
+}
+
+gs_status gs_policy_set_params(gs_ctx* ctx, const float* params, int64_t n) {
+  if (!ctx || !params) return GS_EINVAL;
+  ctx->err.clear();
+  if (n != policy_param_floats()) GS_FAIL(ctx, GS_EINVAL, "the parameter array holds 5542 floats");
+  return policy_set_params(ctx, params);
+}
+
+gs_status gs_policy_save(gs_ctx* ctx, const char* path) {
+  if (!ctx || !path) return GS_EINVAL;
+  ctx->err.clear();
+  return policy_save(ctx, path);
+}
+
+gs_status gs_policy_load(gs_ctx* ctx, const char* path) {
+  if (!ctx || !path) return GS_EINVAL;
+  ctx->err.clear();
+  return policy_load(ctx, path);
+}
+
 gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records) {
   if (!ctx || !n_records) return GS_EINVAL;
   *n_records = (int64_t)(ctx->trace.size() / 6);
@@ -279,6 +406,16 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");
   if (opt.policy != GS_RULE && opt.policy != GS_LEARNED) GS_FAIL(ctx, GS_EINVAL, "unknown policy");
+  if (opt.policy == GS_LEARNED && !ctx->policy.ready)
+    GS_FAIL(ctx, GS_EINVAL, "policy = GS_LEARNED needs parameters: train or load the policy first");
+  if (!(opt.log_explore >= 0.0 && opt.log_explore <= 1.0))
+    GS_FAIL(ctx, GS_EINVAL, "log_explore must be in [0, 1]");
+  if (opt.log_pairs && opt.policy == GS_LEARNED)
+    GS_FAIL(ctx, GS_EINVAL, "log_pairs records the rule's decisions: use policy = GS_RULE");
+  if (opt.log_pairs) {
+    opt.keep_trace = 1;     // the records are built from the trace,
+    opt.kernel_timing = 1;  // with costs measured in this call
+  }
   GS_HIP(ctx, hipSetDevice(ctx->device));
   const double t_start = now_ms();
   hipStream_t st = ctx->stream;
@@ -350,6 +487,10 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   ctx->stats.t_stage_ms = t_staged - t_start;
   ctx->pair_counts.assign((size_t)n_h * 6, 0);
   ctx->trace.clear();
+  ctx->trace_feat.clear();
+  ctx->trace_feas.clear();
+  ctx->policy.log.clear();
+  ctx->policy.log_keys.clear();
   ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
   ctx->kernel_timing = opt.kernel_timing != 0;
 

@@ -22,6 +22,7 @@
 
 #include "gs_host.h"
 #include "gs_internal.h"
+#include "gs_policy.h"
 #include "gs_series.h"
 #include "gs_traverse.h"
 #include "gs_tree.h"
@@ -452,6 +453,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* d_invh = BUF(double, "h_invh", n_h);
   double* d_sc = BUF(double, "h_sc", n_h);
   float* d_s2 = BUF(float, "h_s2", n_h);
+  double* d_hs = BUF(double, "h_hs", n_h);
+  DT_HIP(upload(hs, d_hs, st));
   DT_HIP(upload(h_inv2h2, d_inv2h2, st));
   DT_HIP(upload(h_inv4h2, d_inv4h2, st));
   DT_HIP(upload(h_invh, d_invh, st));
@@ -468,6 +471,16 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   dc.Wtot = Wtot;
   dc.eps_alg = (1.0 - opt.eps_round_share) * eps;
   dc.fmm_mask = (opt.fmm_mask & 7) ? (opt.fmm_mask & 7) : 7;
+  const bool use_policy = use_fmm && opt.policy == GS_LEARNED;
+  const bool log_pairs = use_fmm && opt.log_pairs;
+  dc.policy = use_policy ? 1 : 0;
+  dc.log_feas = log_pairs ? 1 : 0;
+  dc.explore = opt.log_explore;
+  PolicyDevModel pmodel;
+  if (use_policy) {
+    s = policy_device_model(ctx, &pmodel);
+    if (s != GS_OK) return s;
+  }
   for (int p = 1; p <= P; ++p) {
     dc.bconst[p] = bound_const(D, p);
     dc.binomD[p] = (double)binom(D + p - 1, D);
@@ -487,16 +500,17 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* lco = use_fmm ? BUF(double, "lco", (int64_t)n_h * nQ * C) : nullptr;
   double* gx = BUF(double, "gx", (int64_t)n_h * Mq);
   double* gdh = BUF(double, "gdh", (int64_t)n_h * Mq);
-  // [n_h][6] decisions per type, then two per-chunk event counters: base
-  // point-pair evaluations and base distance evaluations.
-  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 2);
+  // [n_h][6] decisions per type, then four per-chunk event counters: base
+  // point-pair evaluations, base distance evaluations, policy consultations,
+  // policy fallbacks.
+  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 4);
   unsigned long long* chunk_ev = hcount + n_h * 6;
   DT_HIP(hipMemsetAsync(Gest, 0, sizeof(double) * n_h * nQ, st));
   DT_HIP(hipMemsetAsync(pL, 0, sizeof(int32_t) * n_h * nQ, st));
   if (lco) DT_HIP(hipMemsetAsync(lco, 0, sizeof(double) * n_h * nQ * C, st));
   DT_HIP(hipMemsetAsync(gx, 0, sizeof(double) * n_h * Mq, st));
   DT_HIP(hipMemsetAsync(gdh, 0, sizeof(double) * n_h * Mq, st));
-  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 2), st));
+  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 4), st));
   float* rec = nullptr;  // base-case reference records, built on first use
   bool rec_ready = false;
   BaseRecordsArgs ra;
@@ -521,7 +535,9 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double t_trav = 0.0, t_work = 0.0;
   int64_t peak = 0;
   int max_level = 0;
-  int64_t base_evals = 0, dist_evals = 0;
+  int64_t base_evals = 0, dist_evals = 0, pol_calls = 0, pol_falls = 0;
+  PolicyTreeView pqt{qt.lo, qt.hi, qt.rinf, qt.count, qt.left};
+  PolicyTreeView prt{rt.lo, rt.hi, rt.rinf, rt.count, rt.left};
 
   // Steps 3 and 4 for the bandwidths [hc0, hc1).  Bandwidths never interact
   // in the traversal, so any split of the sweep makes the same decisions.
@@ -542,6 +558,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       DT_HIP(hipMemsetAsync(hcount + hc0 * 6, 0, sizeof(unsigned long long) * nh * 6, st));
       DT_HIP(hipStreamSynchronize(st));
       ctx->trace.resize(trace0);
+      ctx->trace_feat.resize(trace0 / 6 * kPolicyIn);
+      ctx->trace_feas.resize(trace0 / 6);
       return GS_OK;
     };
     // A failed allocation during the traversal is retried with fewer bandwidths.
@@ -552,7 +570,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     if (_s != GS_OK) return _s;                            \
   } while (0)
     const double ta = now_ms();
-    DT_HIP(hipMemsetAsync(chunk_ev, 0, 2 * sizeof(unsigned long long), st));
+    DT_HIP(hipMemsetAsync(chunk_ev, 0, 4 * sizeof(unsigned long long), st));
     FrontierLevel cur, nxt;
     int64_t nseg = nh, npair = nh;
     CHUNK_ALLOC(level_bufs(0, nseg, npair, cur));
@@ -575,12 +593,17 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
     std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
     std::vector<int8_t> tr_code, tr_p;
+    std::vector<float> tr_feat;
+    std::vector<int16_t> tr_feas;
     while (nseg > 0) {
       peak = std::max(peak, npair);
       int8_t* code;
       int8_t* pord;
       SegCount *cnt, *incl;
       void* temp;
+      float4* scores = nullptr;
+      float* pfeat = nullptr;
+      int16_t* pfeas = nullptr;
       const size_t tb = scan_counts_temp_bytes((int)nseg);
       CHUNK_ALLOC(([&]() -> gs_status {
         code = BUF(int8_t, "p_code", npair);
@@ -588,11 +611,23 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         cnt = BUF(SegCount, "seg_cnt", nseg);
         incl = BUF(SegCount, "seg_incl", nseg);
         temp = BUF(char, "scan_temp", tb);
+        if (use_policy) scores = BUF(float4, "p_scores", npair);
+        if (log_pairs) {
+          pfeat = BUF(float, "p_feat", npair * kPolicyIn);
+          pfeas = BUF(int16_t, "p_feas", npair);
+        }
         return GS_OK;
       })());
-      DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
-                           Gest, cnt, hcount, chunk_ev, st));
-      DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
+      const PolicyPairs pp{cur.h, cur.Q, cur.seg, cur.R, d_hs, d_invh};
+      {
+        KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
+        if (use_policy) DT_HIP(launch_policy_infer_pairs((int)npair, pp, pqt, prt, D, pmodel, scores, st));
+        if (log_pairs) DT_HIP(launch_policy_features((int)npair, pp, pqt, prt, D, pfeat, st));
+        DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
+                             Gest, cnt, hcount, chunk_ev, scores, pfeas, chunk_ev + 2, st));
+        DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
+        kt.stop(st, 2 + (use_policy ? 1 : 0) + (log_pairs ? 1 : 0));
+      }
       SegCount tot;
       DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
       DT_HIP(hipStreamSynchronize(st));
@@ -611,12 +646,24 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         DT_HIP(hipMemcpyAsync(tr_R.data(), cur.R, npair * 4, hipMemcpyDeviceToHost, st));
         DT_HIP(hipMemcpyAsync(tr_code.data(), code, npair, hipMemcpyDeviceToHost, st));
         DT_HIP(hipMemcpyAsync(tr_p.data(), pord, npair, hipMemcpyDeviceToHost, st));
+        if (log_pairs) {
+          tr_feat.resize(npair * kPolicyIn);
+          tr_feas.resize(npair);
+          DT_HIP(hipMemcpyAsync(tr_feat.data(), pfeat, npair * kPolicyIn * sizeof(float),
+                                hipMemcpyDeviceToHost, st));
+          DT_HIP(hipMemcpyAsync(tr_feas.data(), pfeas, npair * sizeof(int16_t), hipMemcpyDeviceToHost, st));
+        }
         DT_HIP(hipStreamSynchronize(st));
         for (int64_t k = 0; k < nseg; ++k)
           for (int j = 0; j < tr_len[k]; ++j) {
             const int64_t o = tr_off[k] + j;
             const int32_t r6[6] = {tr_h[k], level, tr_Q[k], tr_R[o], tr_code[o], tr_p[o]};
             ctx->trace.insert(ctx->trace.end(), r6, r6 + 6);
+            if (log_pairs) {
+              ctx->trace_feat.insert(ctx->trace_feat.end(), tr_feat.begin() + o * kPolicyIn,
+                                     tr_feat.begin() + (o + 1) * kPolicyIn);
+              ctx->trace_feas.push_back(tr_feas[o]);
+            }
           }
       }
       const int64_t nseg2 = tot.v[1], npair2 = tot.v[0];
@@ -633,7 +680,11 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         lo.grp[x] = (int32_t)used_grp[x];
       }
       CHUNK_ALLOC(level_bufs(1 - which, nseg2, npair2, nxt));
-      DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
+      {
+        KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
+        DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
+        kt.stop(st, 1);
+      }
       for (int x = 0; x < 4; ++x) {
         used_ent[x] += tot.v[2 + x];
         used_grp[x] += tot.v[6 + x];
@@ -757,11 +808,20 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     if (use_fmm) {
       KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
       const bool fast = series_fast_available(D, P);
-      if (fast)
-        DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-      else
-        DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-      DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
+      {
+        KernelTimer kd(ctx, ctx->kernel_timing, GS_K_DL, st);
+        if (fast)
+          DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+        else
+          DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+        kd.stop(st, 1);
+      }
+      {
+        KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, st);
+        DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
+        kh.stop(st, 1);
+      }
+      KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, st);
       for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
         const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
         // query nodes of traversal level lv: depth lv (at most ceil(M / 2^lv)
@@ -775,6 +835,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
           DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
                                  Mom, d_sc, (int)Mq, gdh, st));
       }
+      kdh.stop(st, (int)dh_level_begin.size() - 1);
       kt.stop(st, 2 + (int)dh_level_begin.size() - 1);
     }
     if (any_base) {
@@ -788,11 +849,13 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       DT_HIP(launch_base_fused(ba, plan, st));
       kt.stop(st, 1);
     }
-    unsigned long long ev[2] = {0, 0};
+    unsigned long long ev[4] = {0, 0, 0, 0};
     DT_HIP(hipMemcpyAsync(ev, chunk_ev, sizeof(ev), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
     base_evals += (int64_t)ev[0];
     dist_evals += (int64_t)ev[1];
+    pol_calls += (int64_t)ev[2];
+    pol_falls += (int64_t)ev[3];
     t_work += now_ms() - tb0;
     return GS_OK;
   };
@@ -820,6 +883,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   S.h_chunks = h_chunks;
   S.base_pair_evals = base_evals;
   S.base_dist_evals = dist_evals;
+  S.policy_calls = pol_calls;
+  S.policy_fallbacks = pol_falls;
 
   // 5. Post-pass.
   for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
@@ -851,6 +916,11 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     s = keep_tree(ctx, rt, D, ctx->host_tree[0], st);
     if (s != GS_OK) return s;
     s = keep_tree(ctx, qt, D, ctx->host_tree[1], st);
+    if (s != GS_OK) return s;
+  }
+  if (log_pairs) {
+    policy_calibrate_costs(ctx, D);
+    s = policy_build_records(ctx, D, hs);
     if (s != GS_OK) return s;
   }
   return GS_OK;

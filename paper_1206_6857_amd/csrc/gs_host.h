@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/gausssum.h"
+#include "gs_policy.h"
 
 namespace gs {
 
@@ -42,8 +43,11 @@ struct gs_ctx_base {
   Workspace ws;
   std::vector<int64_t> pair_counts;   // [n_h][6]
   std::vector<int32_t> trace;         // [n][6]
+  std::vector<float> trace_feat;      // [n][16] pair features (policy logging)
+  std::vector<int16_t> trace_feas;    // [n] admitted orders (policy logging)
   HostTree host_tree[2];
   bool kernel_timing = false;
+  PolicyState policy;
 };
 
 // Staged, validated inputs in device memory.
@@ -76,6 +80,23 @@ struct KernelTimer {
 
 // Graded multi-index set with |alpha| < p (section 2), library order.
 std::vector<std::vector<int>> multi_indices(int D, int p);
+
+// Learned pair policy (policy.cpp).
+void policy_default_costs(PolicyState& ps);
+gs_status policy_device_model(gs_ctx_base* ctx, PolicyDevModel* m);
+void policy_calibrate_costs(gs_ctx_base* ctx, int D);
+gs_status policy_build_records(gs_ctx_base* ctx, int D, const std::vector<double>& hs);
+gs_status policy_train(gs_ctx_base* ctx, const float* rec, int64_t n, const gs_train_opts& o,
+                       float* final_loss);
+gs_status policy_gradient(gs_ctx_base* ctx, const float* rec, int64_t n, float* grad, float* loss);
+gs_status policy_predict(gs_ctx_base* ctx, const float* feat, int64_t n, float* scores);
+int64_t policy_param_floats();
+void policy_get_params(const PolicyState& ps, float* out);
+gs_status policy_set_params(gs_ctx_base* ctx, const float* in);
+gs_status policy_save(gs_ctx_base* ctx, const char* path);
+gs_status policy_load(gs_ctx_base* ctx, const char* path);
+gs_status policy_write_log(gs_ctx_base* ctx, const char* path);
+gs_status policy_read_log(gs_ctx_base* ctx, const char* path, std::vector<float>* rec);
 
 // Dual-tree summation (GS_DUALTREE, GS_DFD, GS_DFDO) into G_dev[n_h][M].
 gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vector<double>& hs,

@@ -18,6 +18,10 @@ struct DecideConst {
   int mono = 0, use_tokens = 1, use_fmm = 1;
   int log_pairs = 0;
   int fmm_mask = 7;  // allowed series methods: bit 0 DH, bit 1 DL, bit 2 H2L
+  int policy = 0;    // 1: choose by the scores of the learned policy
+  int log_feas = 0;  // 1: record the admitted orders where bestMethod is reached
+  double explore = 0.0;  // logging: probability of taking the direct path
+                         // instead of the rule's series choice
   double Wtot = 0.0, eps_alg = 0.0;
   double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
   double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
@@ -54,11 +58,15 @@ struct LevelOffsets {
   int32_t grp[4];
 };
 
+// scores (policy): per pair of the level, predicted log2 costs of DH, DL,
+// H2L, recurse.  feas (log_feas): per pair, 0x8000 | q_DH | q_DL << 4 |
+// q_H2L << 8 (smallest admitted orders, 0 = none) where bestMethod is
+// reached, else 0.  pcount[0..1] += policy consultations, fallbacks.
 hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
                          SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
-                         hipStream_t s);
+                         const float4* scores, int16_t* feas, unsigned long long* pcount, hipStream_t s);
 
 hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, size_t temp_bytes,
                        hipStream_t s);

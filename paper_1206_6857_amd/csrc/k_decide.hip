@@ -179,7 +179,10 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
                                                     double* __restrict__ Gest,
                                                     SegCount* __restrict__ cnt,
                                                     unsigned long long* __restrict__ hcount,
-                                                    unsigned long long* __restrict__ base_evals) {
+                                                    unsigned long long* __restrict__ base_evals,
+                                                    const float4* __restrict__ scores,
+                                                    int16_t* __restrict__ feas_out,
+                                                    unsigned long long* __restrict__ pcount) {
   constexpr double kSqrt2 = 1.4142135623730951;
   const int s = blockIdx.x;
   if (s >= S) return;
@@ -216,11 +219,16 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   double gest = 0.0;
   bool any_fd = false;
   int nFD = 0, nDH = 0, nDL = 0, nH2L = 0, nBASE = 0, nSPLIT = 0, nchild = 0;
+  int ncalls = 0, nfall = 0;
   long long bevals = 0;
+  // When logging, every pair that reaches bestMethod needs its admitted
+  // orders: no DIRECT shortcut.
+  const bool all_orders = c.log_feas != 0;
   for (int b0 = 0; b0 < len; b0 += 64) {
     const int n = len - b0 < 64 ? len - b0 : 64;
     double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY;
-    int NR = 0, rleaf = 0;
+    int NR = 0, rleaf = 0, Rid = 0;
+    int kstar = 0;  // learned policy: cheapest predicted action (3 = recurse)
     double pm0[P], pm1[P], pm2[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) pm0[p] = pm1[p] = pm2[p] = INFINITY;
@@ -232,6 +240,15 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
       const double kmin = own_exp(-dmin2 * i2);
       WR = rt.W[R];
       NR = rt.count[R];
+      Rid = R;
+      if (scores) {
+        // ties go to the earlier of DH, DL, H2L, recurse
+        const float4 sc = scores[off + b0 + lane];
+        float sb = sc.x;
+        if (sc.y < sb) { kstar = 1; sb = sc.y; }
+        if (sc.z < sb) { kstar = 2; sb = sc.z; }
+        if (sc.w < sb) { kstar = 3; sb = sc.w; }
+      }
       rleaf = rt.left[R] < 0 ? 1 : 0;
       lterm = WR * kmax;
       fdval = 0.5 * (WR * (kmin + kmax));
@@ -269,11 +286,11 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
             mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
           if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
         }
-        astar = division_threshold(mstar, c.Wtot);
+        astar = all_orders ? -INFINITY : division_threshold(mstar, c.Wtot);
       }
     }
     // The token rule, pair by pair, the wave in lockstep.
-    int my_code = -1, my_p = 0;
+    int my_code = -1, my_p = 0, my_feas = 0;
     for (int j = 0; j < n; ++j) {
       const double ndj = rl(nd, j);
       int cd;
@@ -286,7 +303,43 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
         const double WRj = rl(WR, j);
         const double tt = c.use_tokens ? t : 0.0;
         const double a = (c.eps_alg * (WRj + tt)) * L;
-        if (c.use_fmm && a >= rl(astar, j)) {
+        double Esel = 0.0;
+        bool rule = c.use_fmm != 0;
+        if (c.use_fmm && c.policy) {
+          // The learned policy: its cheapest predicted action, a series
+          // method only at an order its bound admits, else the rule decides.
+          const int kj = rl(kstar, j);
+          ++ncalls;
+          if (kj == 3) {
+            rule = false;
+          } else {
+            const double maxerr = a / c.Wtot;
+            int qk = 0;
+            double ek = 0.0;
+            if (lane == j) {
+              int ak = 0;
+#pragma unroll
+              for (int pp = 0; pp < P; ++pp) {
+                const double e = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
+                ak += e > maxerr ? 1 : 0;
+              }
+              qk = ak < P ? ak + 1 : 0;
+#pragma unroll
+              for (int pp = 0; pp < P; ++pp)
+                if (pp + 1 == qk) ek = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
+            }
+            qk = rl(qk, j);
+            if (qk) {
+              cd = kj == 0 ? DH : kj == 1 ? DL : H2L;
+              p = qk;
+              Esel = rl(ek, j);
+              rule = false;
+            } else {
+              ++nfall;
+            }
+          }
+        }
+        if (rule && (all_orders || a >= rl(astar, j))) {
           const double maxerr = a / c.Wtot;
           int q0 = 0, q1 = 0, q2 = 0;
           double e0 = 0.0, e1 = 0.0, e2 = 0.0;
@@ -319,22 +372,50 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           int64_t best = c0 < c1 ? c0 : c1;
           best = c2 < best ? c2 : best;
           best = c3 < best ? c3 : best;
-          double Esel = 0.0;
           if (q0 && c0 == best) {
             cd = DH;
             p = q0;
-            Esel = rl(e0, j);
           } else if (q1 && c1 == best) {
             cd = DL;
             p = q1;
-            Esel = rl(e1, j);
           } else if (q2 && c2 == best) {
             cd = H2L;
             p = q2;
-            Esel = rl(e2, j);
           }
-          if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, c.Wtot, c.eps_alg);
+          if (c.log_feas && c.explore > 0.0) {
+            // Exploration while logging: for a fixed pseudo-random share of
+            // the pairs, an admitted action drawn uniformly (each admitted
+            // series method at its order, or the direct path) replaces the
+            // rule's, so that the log also holds costs the rule never incurs.
+            unsigned long long x = ((unsigned long long)h << 56) ^ ((unsigned long long)Q << 28) ^
+                                   (unsigned long long)rl(Rid, j);
+            x += 0x9e3779b97f4a7c15ull;
+            x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+            x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+            x ^= x >> 31;
+            if ((double)(x >> 11) * 0x1.0p-53 < c.explore) {
+              const int ncand = (q0 ? 1 : 0) + (q1 ? 1 : 0) + (q2 ? 1 : 0) + 1;
+              int pick = (int)((x & 0x3ff) * (unsigned long long)ncand >> 10);
+              cd = -1;
+              p = 0;
+              if (q0 && pick-- == 0) {
+                cd = DH;
+                p = q0;
+              } else if (q1 && pick-- == 0) {
+                cd = DL;
+                p = q1;
+              } else if (q2 && pick-- == 0) {
+                cd = H2L;
+                p = q2;
+              }
+            }
+          }
+          if (cd == DH) Esel = rl(e0, j);
+          else if (cd == DL) Esel = rl(e1, j);
+          else if (cd == H2L) Esel = rl(e2, j);
+          if (c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
         }
+        if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, c.Wtot, c.eps_alg);
         if (cd < 0) {
           if (qleaf && rl(rleaf, j)) {
             if (c.use_tokens) t = t + WRj;
@@ -374,6 +455,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
     if (act) {
       code_out[off + b0 + lane] = (int8_t)my_code;
       p_out[off + b0 + lane] = (int8_t)my_p;
+      if (feas_out) feas_out[off + b0 + lane] = (int16_t)my_feas;
     }
   }
   if (lane != 0) return;
@@ -400,6 +482,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   if (nBASE) atomicAdd(&hc[BASE], (unsigned long long)nBASE);
   if (nSPLIT) atomicAdd(&hc[SPLIT], (unsigned long long)nSPLIT);
   if (bevals) atomicAdd(base_evals, (unsigned long long)bevals);
+  if (ncalls) atomicAdd(&pcount[0], (unsigned long long)ncalls);
+  if (nfall) atomicAdd(&pcount[1], (unsigned long long)nfall);
 }
 
 struct SegCountPlus {
@@ -498,12 +582,13 @@ hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, co
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
                          SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
+                         const float4* scores, int16_t* feas, unsigned long long* pcount,
                          hipStream_t s) {
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \
     hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)S), dim3(64), 0, s, S, cur, qt, rt,   \
                        inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, hcount,           \
-                       base_evals);                                                            \
+                       base_evals, scores, feas, pcount);                                      \
     break;
   switch (c.P) {
     GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)

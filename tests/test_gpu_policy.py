@@ -1,0 +1,264 @@
+"""The learned pair policy through the C ABI, against the FP64 oracle.
+
+* Inference (half-precision MFMA): equal to the oracle network evaluated with
+  the same half-precision roundings, and close to the plain FP64 network.
+* Gradient (single precision) and one Adam step: equal to the oracle's within
+  single-precision rounding.
+* Training records (features, admitted orders, cost-to-go targets) of a logged
+  traversal: equal to the oracle's records of the same decisions.
+* Every choice of the learned policy is certified: the oracle replays the
+  GPU's decisions with its own bounds and token book and reproduces the pair
+  lists bit for bit; Theorem 2 holds against the exhaustive sum.
+"""
+import numpy as np
+import pytest
+
+import oracle.dualtree as DT
+from oracle import mlp
+from oracle.exhaustive import gauss_sum_exhaustive
+from oracle.policy import CostModel, records
+from paper_1206_6857_amd import _lib
+from paper_1206_6857_amd.datagen import mixture
+from tests.gpu_util import banner, ctx
+
+pytestmark = pytest.mark.gpu
+
+f16 = lambda a: np.asarray(a, dtype=np.float16).astype(np.float64)
+
+
+def _random_model(seed, scale=0.35):
+    rng = np.random.default_rng(seed)
+    theta = rng.normal(0, scale, mlp.N_PARAMS)
+    mu_x = rng.normal(0, 1, 16)
+    sd_x = rng.uniform(0.5, 2.0, 16)
+    mu_y, sd_y = 3.0, 2.5
+    params = np.concatenate([theta, mu_x, sd_x, [mu_y, sd_y]]).astype(np.float32)
+    return params
+
+
+def _split(params):
+    p = params.astype(np.float64)
+    theta = p[:mlp.N_PARAMS]
+    o = p[mlp.N_PARAMS:]
+    return theta, o[:16], o[16:32], o[32], o[33]
+
+
+def test_policy_predict_matches_oracle():
+    banner("policy predict")
+    c = ctx()
+    params = _random_model(1)
+    c.policy_set_params(params)
+    rng = np.random.default_rng(2)
+    n = 16 * 40 + 7                      # several tiles and a ragged tail
+    F = rng.normal(0, 2, (n, 16)).astype(np.float32)
+    got = c.policy_predict(F)
+    theta, mu, sd, _, _ = _split(params)
+    P = mlp.unpack(theta.astype(np.float32).astype(np.float64))
+    xs = (F.astype(np.float64) - mu.astype(np.float32)) * (1.0 / sd.astype(np.float32)).astype(np.float32)
+    # the kernel's roundings: half inputs, weights and hidden activations
+    h1 = f16(np.maximum(f16(xs) @ f16(P["W1"]).T + P["b1"], 0))
+    h2 = f16(np.maximum(h1 @ f16(P["W2"]).T + P["b2"], 0))
+    emu = h2 @ f16(P["W3"]).T + P["b3"]
+    scale = np.abs(emu).max()
+    assert np.abs(got - emu).max() <= 1e-4 * scale, np.abs(got - emu).max()
+    exact, _ = mlp.forward(theta, (F.astype(np.float64) - mu) / sd)
+    assert np.abs(got - exact).max() <= 3e-2 * max(1.0, np.abs(exact).max())
+
+
+def _records(seed, n):
+    rng = np.random.default_rng(seed)
+    rec = np.zeros((n, 24), dtype=np.float32)
+    rec[:, :10] = rng.normal(0, 2, (n, 10))
+    rec[:, 16:20] = rng.normal(5, 3, (n, 4))
+    rec[:, 20:24] = (rng.random((n, 4)) < 0.7)
+    rec[:, 16:20] *= rec[:, 20:24]
+    return rec
+
+
+def _std(params, rec):
+    theta, mu, sd, mu_y, sd_y = _split(params)
+    X = (rec[:, :16].astype(np.float64) - mu) / sd
+    T = (rec[:, 16:20].astype(np.float64) - mu_y) / sd_y
+    return theta, X, T, rec[:, 20:24].astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 37, 5000])
+def test_policy_gradient_matches_oracle(n):
+    banner("policy gradient", n)
+    c = ctx()
+    params = _random_model(3, scale=0.2)
+    c.policy_set_params(params)
+    rec = _records(4, n)
+    g, loss = c.policy_gradient(rec)
+    theta, X, T, Mk = _std(params, rec)
+    want = mlp.gradient(theta, X, T, Mk)
+    assert np.abs(g - want).max() <= 2e-4 * np.abs(want).max(), np.abs(g - want).max()
+    assert abs(loss - mlp.loss(theta, X, T, Mk)) <= 1e-4 * mlp.loss(theta, X, T, Mk)
+
+
+def test_policy_adam_step_matches_oracle():
+    banner("policy adam")
+    c = ctx()
+    params = _random_model(5, scale=0.2)
+    c.policy_set_params(params)
+    rec = _records(6, 300)
+    c.policy_train(rec, steps=1, batch=300, reinit=0, lr=1e-3)
+    after = c.policy_params()
+    theta, X, T, Mk = _std(params, rec)
+    g = mlp.gradient(theta, X, T, Mk)
+    want, _, _ = mlp.adam_step(theta, np.zeros_like(theta), np.zeros_like(theta), g, 1, 1e-3)
+    sel = np.abs(g) > 1e-5             # Adam's first step is lr * g / (|g| + eps)
+    assert sel.sum() > 1000
+    assert np.abs(after[:mlp.N_PARAMS][sel] - want[sel]).max() <= 2e-6
+    assert np.array_equal(after[mlp.N_PARAMS:], params[mlp.N_PARAMS:])
+
+
+def test_policy_training_fits_a_learnable_target():
+    banner("policy training")
+    c = ctx()
+    rng = np.random.default_rng(7)
+    n = 6000
+    rec = np.zeros((n, 24), dtype=np.float32)
+    X = rng.normal(0, 1, (n, 10))
+    rec[:, :10] = X
+    rec[:, 16] = 2 * X[:, 0] - X[:, 1] + 10
+    rec[:, 17] = np.abs(X[:, 2]) * 3
+    rec[:, 18] = X[:, 3] ** 2
+    rec[:, 19] = X[:, 4] - X[:, 5]
+    rec[:, 20:24] = 1
+    loss0 = c.policy_train(rec, steps=0, seed=3)
+    loss = c.policy_train(rec, steps=1500, batch=1024, seed=3, lr=3e-3)
+    assert loss < 0.05 * loss0, (loss0, loss)
+
+
+def _pair_trace_replay(trace):
+    return {tuple(int(v) for v in t[:4]): (int(t[4]), int(t[5])) for t in trace}
+
+
+def _sorted(a):
+    a = np.asarray(a, dtype=np.int64)
+    return a[np.lexsort(a.T[::-1])]
+
+
+def test_policy_log_records_match_oracle():
+    banner("policy log records")
+    r, w, _ = mixture((31, 2), 1500, 2, 4, (0.02, 0.1))
+    hs = np.array([0.01, 0.04, 0.15, 0.6])
+    c = ctx()
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, log_pairs=1, log_explore=0.3)
+    cm = c.policy_cost_model()       # measured in the logged call
+    rec, keys = c.policy_log()
+    tr = c.get_trace()
+    assert rec.shape[0] > 100 and c.stats().policy_calls == 0
+    ref = DT.dualtree(r, r, w, hs, 0.01, leaf_size=32, trace=True, replay=_pair_trace_replay(tr),
+                      record_feasible=True)
+    assert np.array_equal(_sorted(ref.trace), _sorted(tr))
+    ocm = CostModel(cm["pair_ns"], cm["dh_ns"], cm["dl_ns"], cm["h2l_ns"], cm["base_ns"])
+    okeys, F, T, Mk = records(ref.trace, ref.feasible, ref.qtree, ref.rtree, hs, 2, ocm)
+    order = np.lexsort(keys.T[::-1])
+    assert np.array_equal(keys[order], np.array(okeys, dtype=np.int32))
+    g = rec[order]
+    assert np.array_equal(g[:, 20:24], Mk.astype(np.float32))
+    assert np.allclose(g[:, :16], F, rtol=1e-6, atol=1e-6)
+    assert np.abs((g[:, 16:20] - T) * Mk).max() <= 1e-5
+
+
+def test_learned_policy_is_certified_and_keeps_theorem_2():
+    banner("learned policy replay")
+    c = ctx()
+    r, w, _ = mixture((41, 3), 3000, 3, 6, (0.02, 0.1))
+    hs = np.logspace(-2, 0, 6)
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, log_pairs=1, log_explore=0.3)
+    rec, _ = c.policy_log()
+    c.policy_train(rec, steps=800, batch=2048, seed=5)
+    r2, w2, _ = mixture((42, 3), 3000, 3, 6, (0.02, 0.1))
+    G = c.gauss_sum(r2, r2, w2, hs, 0.01, leaf_size=32, policy="learned", keep_trace=1)
+    st = c.stats()
+    assert st.policy_calls > 0
+    tr = c.get_trace()
+    ref = DT.dualtree(r2, r2, w2, hs, 0.01, leaf_size=32, trace=True, replay=_pair_trace_replay(tr))
+    assert np.array_equal(_sorted(ref.trace), _sorted(tr))
+    exact = gauss_sum_exhaustive(r2, r2, w2, hs)
+    assert (np.abs(G - ref.G) / exact).max() <= 1e-4
+    assert (np.abs(G - exact) / exact).max() <= 0.01
+
+
+def test_policy_save_load_roundtrip(tmp_path):
+    banner("policy save/load")
+    c = ctx()
+    params = _random_model(9)
+    c.policy_set_params(params)
+    old = c.policy_cost_model()
+    c.policy_cost_model(pair_ns=0.7)
+    c.policy_save(tmp_path / "p.bin")
+    import paper_1206_6857_amd as g
+    c2 = g.Context(0)
+    c2.policy_load(tmp_path / "p.bin")
+    assert np.array_equal(c2.policy_params(), params)
+    assert c2.policy_cost_model()["pair_ns"] == 0.7
+    c.policy_cost_model(**old)
+    (tmp_path / "bad.bin").write_bytes(b"not a policy")
+    with pytest.raises(g.GaussSumError):
+        c2.policy_load(tmp_path / "bad.bin")
+    c2.close()
+
+
+def test_learned_policy_needs_parameters():
+    import paper_1206_6857_amd as g
+    c = g.Context(0)
+    r = np.random.default_rng(0).random((100, 2))
+    with pytest.raises(g.GaussSumError) as e:
+        c.gauss_sum(r, r, np.ones(100), [0.1], 0.01, policy="learned")
+    assert e.value.status == _lib.GS_EINVAL
+    c.close()
+
+
+def _modeled_cost(trace, qc, rc, D, cm):
+    """Sum over decided pairs of the cost model's action costs (= the
+    cost-to-go of the root pairs)."""
+    import math
+    code, p = trace[:, 4], trace[:, 5]
+    NQ = qc[trace[:, 2]].astype(np.float64)
+    NR = rc[trace[:, 3]].astype(np.float64)
+    Cp = np.array([math.comb(D + k - 1, D) if k > 0 else 0 for k in range(11)], dtype=np.float64)[p]
+    c = np.full(len(trace), cm["pair_ns"])
+    c += np.where(code == 1, NQ * Cp * cm["dh_ns"], 0.0)
+    c += np.where(code == 2, NR * Cp * cm["dl_ns"], 0.0)
+    c += np.where(code == 3, Cp * Cp * cm["h2l_ns"], 0.0)
+    c += np.where(code == 4, NQ * NR * cm["base_ns"], 0.0)
+    return float(c.sum())
+
+
+def test_learned_policy_gain_on_held_out_data():
+    """Trained on one draw, evaluated on another draw of the same
+    distribution: the learned policy's decisions cost less under the measured
+    cost model than the paper's rule, and still meet Theorem 2."""
+    banner("learned policy gain")
+    import time
+    import paper_1206_6857_amd as g
+    c = g.Context(0)
+    D, N = 3, 20000
+    hs = np.logspace(-3, 0, 10)
+    r, w, _ = mixture((51, D), N, D, 8, (0.01, 0.1))
+    c.gauss_sum(r, r, w, hs, 0.01, log_pairs=1, log_explore=0.3)
+    cm = c.policy_cost_model()
+    rec, _ = c.policy_log()
+    c.policy_train(rec, steps=1500, batch=4096, seed=2)
+    r2, w2, _ = mixture((52, D), N, D, 8, (0.01, 0.1))
+    cost, ms, G = {}, {}, {}
+    for pol in ("rule", "learned"):
+        G[pol] = c.gauss_sum(r2, r2, w2, hs, 0.01, policy=pol, keep_trace=1)
+        qc, rc = c.get_tree(1, D)["count"], c.get_tree(0, D)["count"]
+        cost[pol] = _modeled_cost(c.get_trace(), qc, rc, D, cm)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            c.gauss_sum(r2, r2, w2, hs, 0.01, policy=pol)
+        ms[pol] = (time.perf_counter() - t0) / 3 * 1e3
+    print("[gain] modeled ns rule %.0f learned %.0f (%.3f); wall ms rule %.2f learned %.2f"
+          % (cost["rule"], cost["learned"], cost["learned"] / cost["rule"], ms["rule"], ms["learned"]),
+          flush=True)
+    assert cost["learned"] < 0.97 * cost["rule"]
+    idx = np.random.default_rng(3).choice(N, 800, replace=False)
+    exact = gauss_sum_exhaustive(r2[idx], r2, w2, hs)
+    assert (np.abs(G["learned"][:, idx] - exact) / exact).max() <= 0.01
+    c.close()
