@@ -106,10 +106,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=1, help="workload index (see datagen.workload)")
-    ap.add_argument("--cpu-queries", type=int, default=300)
+    ap.add_argument("--cpu-queries", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exhaustive", action="store_true")
-    ap.add_argument("--leaf-size", type=int, default=64)
+    ap.add_argument("--leaf-size", type=int, default=0,
+                    help="kd-tree leaf size; 0 (default): chosen by the library's autotuner "
+                         "during the warm-up steps")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-policy leg (trained on another draw of the workload)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy (y = x * 1) of this many MiB, "
                          "to calibrate HBM byte counters against a known size")
@@ -136,17 +140,19 @@ def main():
     ctx = g.Context(0)
     pair_evals = float(M) * N * n_h
 
-    def run(method, steps, warmup):
-        for _ in range(warmup):
-            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, leaf_size=args.leaf_size)
+    tune = dict(leaf_size=args.leaf_size) if args.leaf_size > 0 else dict(autotune=1)
+
+    def run(method, steps, warmup, **extra):
+        kw = dict(tune, **extra) if method != "exhaustive" else {}
+        for _ in range(max(1, warmup)):
+            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, **kw)
         torch.cuda.synchronize()
         kms = np.zeros(12)
         kl = np.zeros(12, dtype=np.int64)
         evals = np.zeros(2, dtype=np.int64)
         t0 = time.perf_counter()
         for _ in range(steps):
-            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, kernel_timing=1,
-                          leaf_size=args.leaf_size)
+            ctx.gauss_sum(qd, rd, wd, hd, wl.eps, out=out, method=method, kernel_timing=1, **kw)
             st = ctx.stats()
             kms += np.array(st.k_ms[:])
             kl += np.array(st.k_launches[:])
@@ -164,6 +170,8 @@ def main():
 
     t_dt, kms, kl, evals, st_dt = run("dualtree", args.steps, args.warmup)
     base_evals, dist_evals = int(evals[0]), int(evals[1])
+    leaf = st_dt.tuned_leaf_size
+    method_used = {g.GS_DUALTREE: "dualtree", g.GS_EXHAUSTIVE: "exhaustive"}.get(st_dt.tuned_method, "?")
     pc = ctx.pair_counts(n_h)
     result = {
         "metric": "pair-evals/sec equiv. at eps=0.01, dual-tree vs GPU exhaustive; % of roofline",
@@ -179,8 +187,8 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "D": D, "N": N, "M": M, "n_bandwidths": n_h,
-                   "eps": wl.eps, "method": "dualtree", "leaf_size": args.leaf_size,
-                   "parallelism": "single-gpu"},
+                   "eps": wl.eps, "method": method_used, "leaf_size": leaf,
+                   "autotune": args.leaf_size <= 0, "parallelism": "single-gpu"},
     }
 
     # Dominant kernel of the dual-tree step: the bandwidth-fused base tiles
@@ -191,11 +199,9 @@ def main():
         flops, slots = fused_base_model(D, dist_evals / n, base_evals / n)
         achieved = flops / (avg_ms * 1e-3) / 1e12
         peak = LANE_SLOTS_PER_S * flops / slots / 1e12
-        traffic = None
-        if args.leaf_size == 64:
-            traffic = measured_traffic(
-                os.path.join(ROOT, "paper_1206_6857_amd", "csrc", "k_base.hip"),
-                os.path.join(ROOT, "profiles", "base_fused_kernel_%s_hbm_bytes.txt" % wl.name))
+        traffic = measured_traffic(
+            os.path.join(ROOT, "paper_1206_6857_amd", "csrc", "k_base.hip"),
+            os.path.join(ROOT, "profiles", "base_fused_kernel_%s_leaf%d_hbm_bytes.txt" % (wl.name, leaf)))
         result["roofline"] = {"bound": "alu", "kernel": "base_fused_kernel", "achieved": achieved,
                               "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                               "traffic": traffic, "avg_launch_ms": avg_ms,
@@ -208,6 +214,23 @@ def main():
         "series_kernels": float(kms[_lib.K_SERIES] / args.steps)}
     result["pairs"] = {k: int(pc[:, i].sum()) for i, k in enumerate(["FD", "DH", "DL", "H2L", "BASE", "SPLIT"])}
     result["base_pair_evals_frac"] = base_evals / args.steps / pair_evals
+
+    if not args.no_learned and method_used == "dualtree":
+        # The learned pair policy, trained on another draw of the same
+        # workload (logging and training are parameter selection, not timed).
+        tr = workload(args.workload, draw=1)
+        t0 = time.perf_counter()
+        ctx.gauss_sum(tr.refs, tr.refs, tr.weights, tr.bandwidths, tr.eps, leaf_size=leaf, log_pairs=1,
+                      log_explore=0.3)
+        rec, _ = ctx.policy_log()
+        loss = ctx.policy_train(rec, steps=1500, batch=4096, seed=1)
+        t_train = time.perf_counter() - t0
+        t_lp, _, _, _, st_lp = run("dualtree", args.steps, args.warmup, policy="learned")
+        result["learned_policy"] = {
+            "ms_per_step": t_lp * 1e3, "value": pair_evals / t_lp, "speedup_vs_rule": t_dt / t_lp,
+            "train_records": int(rec.shape[0]), "train_loss": loss, "train_s": t_train,
+            "policy_calls": int(st_lp.policy_calls), "policy_fallbacks": int(st_lp.policy_fallbacks),
+            "trained_on": tr.name + " (another draw)"}
 
     if not args.no_exhaustive:
         t_ex, kms_e, kl_e, _, _ = run("exhaustive", max(1, args.steps), 1)

@@ -91,6 +91,12 @@ typedef struct gs_options {
                                at its order, or the direct path) instead of the
                                rule's, so that the log also holds costs the rule
                                never incurs.  log_pairs needs policy = GS_RULE. */
+  int32_t autotune;         /* 1: choose the leaf size (32..256) and, for GS_DUALTREE,
+                               between the dual-tree and the exhaustive path, by timing
+                               each once per workload signature (dimension, sizes, the
+                               bandwidth range, eps, method options); the choice is
+                               cached in the context.  Ignored with keep_trace. */
+  int32_t reserved2;
 } gs_options;
 
 typedef struct gs_stats {
@@ -113,7 +119,9 @@ typedef struct gs_stats {
   int64_t base_dist_evals;  /* point pairs whose squared distance the base tiles
                                formed (one per pair for all bandwidths of a block) */
   int32_t h_chunks;         /* bandwidth chunks the traversal was split into */
-  int32_t reserved1;
+  int32_t tuned_leaf_size;  /* leaf size the call used */
+  int32_t tuned_method;     /* method the call used (the autotuner may pick GS_EXHAUSTIVE) */
+  int32_t autotune_trials;  /* timed trial runs this call made (0: cached or off) */
 } gs_stats;
 
 /* Kernel classes of gs_stats.k_ms. */

@@ -41,7 +41,8 @@ class GsOptions(ctypes.Structure):
                 ("log_pairs", ctypes.c_int32), ("fmm_mask", ctypes.c_int32),
                 ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
                 ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
-                ("log_explore", ctypes.c_double)]
+                ("log_explore", ctypes.c_double), ("autotune", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class GsCostModel(ctypes.Structure):
@@ -65,7 +66,8 @@ class GsStats(ctypes.Structure):
                 ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 12),
                 ("k_launches", ctypes.c_int64 * 12), ("base_dist_evals", ctypes.c_int64),
-                ("h_chunks", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("h_chunks", ctypes.c_int32), ("tuned_leaf_size", ctypes.c_int32),
+                ("tuned_method", ctypes.c_int32), ("autotune_trials", ctypes.c_int32)]
 K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS, K_DH, K_DL, K_H2L = range(10)
 
 

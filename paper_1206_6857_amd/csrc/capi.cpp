@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -58,34 +59,57 @@ bool is_device_pointer(const void* p) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+static hipEvent_t pooled_event(gs_ctx_base* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
 KernelTimer::KernelTimer(gs_ctx_base* c, bool enabled, int k, hipStream_t s) : ctx(c), cls(k) {
   if (!enabled) return;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-    (void)hipGetLastError();
-    return;
-  }
+  a = pooled_event(ctx);
+  b = pooled_event(ctx);
+  if (!a || !b) return;
   on = hipEventRecord(a, s) == hipSuccess;
 }
 
 void KernelTimer::stop(hipStream_t s, int n_launches) {
   if (!on) return;
-  launches = n_launches;
-  if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+  on = false;
+  if (hipEventRecord(b, s) != hipSuccess) {
     (void)hipGetLastError();
-    on = false;
     return;
   }
-  float ms = 0.0f;
-  if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
-    ctx->stats.k_ms[cls] += ms;
-    ctx->stats.k_launches[cls] += launches;
-  }
-  on = false;
+  ctx->pending.push_back({a, b, cls, n_launches});
+  a = b = nullptr;  // owned by the pending list now
 }
 
 KernelTimer::~KernelTimer() {
-  if (a) hipEventDestroy(a);
-  if (b) hipEventDestroy(b);
+  if (a) ctx->ev_pool.push_back(a);
+  if (b) ctx->ev_pool.push_back(b);
+}
+
+void flush_kernel_timers(gs_ctx_base* ctx) {
+  for (const PendingTimer& p : ctx->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->stats.k_ms[p.cls] += ms;
+      ctx->stats.k_launches[p.cls] += p.launches;
+    } else {
+      (void)hipGetLastError();
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
 }
 
 }  // namespace gs
@@ -187,6 +211,9 @@ gs_status gs_destroy(gs_ctx* ctx) {
   if (!ctx) return GS_OK;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  flush_kernel_timers(ctx);
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  ctx->ev_pool.clear();
   ctx->ws.release_all();
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -379,6 +406,24 @@ gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records) {
   return GS_OK;
 }
 
+// Workload signature of the autotuner: method, policy, order limit and
+// method mask, dimension, mono/bichromatic, M and N to a factor of 2^(1/2),
+// the bandwidth count and range to a quarter decade, eps to an eighth decade.
+static std::string autotune_key(const gs_options& o, int D, bool mono, int64_t M, int64_t N,
+                                const std::vector<double>& hs, double eps) {
+  double hmin = hs[0], hmax = hs[0];
+  for (double h : hs) {
+    hmin = std::min(hmin, h);
+    hmax = std::max(hmax, h);
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d/%ld/%ld/%zu/%ld/%ld/%ld", o.method, o.policy, o.plimit,
+                o.fmm_mask, D, mono ? 1 : 0, std::lround(2.0 * std::log2((double)M)),
+                std::lround(2.0 * std::log2((double)N)), hs.size(), std::lround(4.0 * std::log10(hmin)),
+                std::lround(4.0 * std::log10(hmax)), std::lround(8.0 * std::log10(eps)));
+  return buf;
+}
+
 gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double* refs,
                     const double* weights, int64_t N, int32_t D, const double* bandwidths,
                     int32_t n_h, double eps, double* G_out, const gs_options* opt_in) {
@@ -481,37 +526,88 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   const bool out_dev = is_device_pointer(G_out);
   double* Gd = out_dev ? G_out : WS(double, "G_tmp", (int64_t)n_h * M);
 
-  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
-  ctx->stats.struct_size = sizeof(gs_stats);
-  ctx->stats.n_h = n_h;
-  ctx->stats.t_stage_ms = t_staged - t_start;
-  ctx->pair_counts.assign((size_t)n_h * 6, 0);
-  ctx->trace.clear();
-  ctx->trace_feat.clear();
-  ctx->trace_feas.clear();
-  ctx->policy.log.clear();
-  ctx->policy.log_keys.clear();
-  ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
-  ctx->kernel_timing = opt.kernel_timing != 0;
+  // One summation with the options o into Gd; resets the statistics.
+  auto run_once = [&](const gs_options& o) -> gs_status {
+    GS_HIP(ctx, hipStreamSynchronize(st));
+    flush_kernel_timers(ctx);  // timers of an earlier trial
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.struct_size = sizeof(gs_stats);
+    ctx->stats.n_h = n_h;
+    ctx->stats.t_stage_ms = t_staged - t_start;
+    ctx->pair_counts.assign((size_t)n_h * 6, 0);
+    ctx->trace.clear();
+    ctx->trace_feat.clear();
+    ctx->trace_feas.clear();
+    ctx->policy.log.clear();
+    ctx->policy.log_keys.clear();
+    ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
+    ctx->kernel_timing = o.kernel_timing != 0;
+    if (o.method == GS_EXHAUSTIVE) {
+      float* rec = WS(float, "ex_rec", N * exhaustive_record_stride(D));
+      unsigned long long* wb = WS(unsigned long long, "wmax_bits", 1);
+      GS_HIP(ctx, launch_exhaustive_records(in.r_aos, in.w, N, D, rec, wb, st));
+      double* partial = WS(double, "ex_partial", exhaustive_partial_elems(M, N, n_h));
+      KernelTimer kt(ctx, ctx->kernel_timing, GS_K_EXHAUSTIVE, st);
+      GS_HIP(ctx, launch_exhaustive(in.q_aos, M, rec, N, D, hs.data(), n_h, wb, partial, Gd, st));
+      kt.stop(st, 1);
+      return GS_OK;
+    }
+    return run_dualtree(ctx, in, hs, eps, o, Gd);
+  };
 
-  if (opt.method == GS_EXHAUSTIVE) {
-    float* rec = WS(float, "ex_rec", N * exhaustive_record_stride(D));
-    unsigned long long* wb = WS(unsigned long long, "wmax_bits", 1);
-    GS_HIP(ctx, launch_exhaustive_records(in.r_aos, in.w, N, D, rec, wb, st));
-    double* partial = WS(double, "ex_partial", exhaustive_partial_elems(M, N, n_h));
-    KernelTimer kt(ctx, ctx->kernel_timing, GS_K_EXHAUSTIVE, st);
-    GS_HIP(ctx, launch_exhaustive(in.q_aos, M, rec, N, D, hs.data(), n_h, wb, partial, Gd, st));
-    kt.stop(st, 1);
-  } else {
-    s = run_dualtree(ctx, in, hs, eps, opt, Gd);
-    if (s != GS_OK) return s;
+  // Autotuning (dual-tree methods): the fastest of the leaf sizes 32..256 and,
+  // for GS_DUALTREE, the exhaustive path, per workload signature, measured
+  // once per context and reused.
+  int trials = 0;
+  if (opt.autotune && opt.method != GS_EXHAUSTIVE && !opt.keep_trace) {
+    const std::string key = autotune_key(opt, D, mono, M, N, hs, eps);
+    auto it = ctx->tuned.find(key);
+    if (it == ctx->tuned.end()) {
+      std::vector<std::pair<int, int>> cand;  // (method, leaf)
+      for (int leaf : {32, 64, 128, 256}) cand.push_back({opt.method, leaf});
+      if (opt.method == GS_DUALTREE) cand.push_back({GS_EXHAUSTIVE, opt.leaf_size});
+      double best_ms = 0.0;
+      std::pair<int, int> best = cand[0];
+      for (const auto& c : cand) {
+        gs_options o = opt;
+        o.method = c.first;
+        o.leaf_size = c.second;
+        o.kernel_timing = 0;
+        // The exhaustive path runs at most ~5e12 pair-evaluations/s on one
+        // MI355X: skip it when even that rate loses to the best leaf size.
+        if (c.first == GS_EXHAUSTIVE && best_ms > 0.0 && (double)M * (double)N * n_h / 5e9 > best_ms) continue;
+        double ms = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run also sizes the workspace
+          const double t0 = now_ms();
+          s = run_once(o);
+          if (s != GS_OK) return s;
+          GS_HIP(ctx, hipStreamSynchronize(st));
+          ms = now_ms() - t0;
+          ++trials;
+          if (ms > 100.0) break;  // allocation no longer matters at this size
+        }
+        if (best_ms == 0.0 || ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      it = ctx->tuned.emplace(key, best).first;
+    }
+    opt.method = it->second.first;
+    opt.leaf_size = it->second.second;
   }
+  s = run_once(opt);
+  if (s != GS_OK) return s;
+  ctx->stats.autotune_trials = trials;
+  ctx->stats.tuned_method = opt.method;
+  ctx->stats.tuned_leaf_size = opt.leaf_size;
   if (!out_dev) {
     GS_HIP(ctx, hipMemcpyAsync(G_out, Gd, (size_t)n_h * M * sizeof(double), hipMemcpyDeviceToHost, st));
     GS_HIP(ctx, hipStreamSynchronize(st));
   } else if (opt.blocking) {
     GS_HIP(ctx, hipStreamSynchronize(st));
   }
+  flush_kernel_timers(ctx);
   ctx->stats.t_total_ms = now_ms() - t_start;
   return GS_OK;
 }

@@ -919,6 +919,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     if (s != GS_OK) return s;
   }
   if (log_pairs) {
+    DT_HIP(hipStreamSynchronize(st));
+    flush_kernel_timers(ctx);
     policy_calibrate_costs(ctx, D);
     s = policy_build_records(ctx, D, hs);
     if (s != GS_OK) return s;

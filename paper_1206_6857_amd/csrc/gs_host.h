@@ -34,6 +34,12 @@ struct HostTree {
   std::vector<double> lo, hi, ctr, rinf, W, wmin;
 };
 
+// A recorded pair of timing events not yet read (see KernelTimer).
+struct PendingTimer {
+  hipEvent_t a, b;
+  int cls, launches;
+};
+
 struct gs_ctx_base {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -48,6 +54,9 @@ struct gs_ctx_base {
   HostTree host_tree[2];
   bool kernel_timing = false;
   PolicyState policy;
+  std::map<std::string, std::pair<int, int>> tuned;  // autotuner: signature -> (method, leaf)
+  std::vector<hipEvent_t> ev_pool;                    // reusable timing events
+  std::vector<PendingTimer> pending;                  // recorded, not yet read
 };
 
 // Staged, validated inputs in device memory.
@@ -65,18 +74,19 @@ struct DeviceInputs {
 bool is_device_pointer(const void* p);
 
 // Optional HIP-event timing of one kernel class on the context's stream:
-// construct before the launches, call stop() after them; the elapsed device
-// time is added to stats.k_ms[cls] once the stream is synchronised (flush()).
+// construct before the launches, call stop() after them.  No synchronisation:
+// the events are read by flush_kernel_timers (end of the call), which adds
+// the elapsed device time to stats.k_ms[cls].
 struct KernelTimer {
   gs_ctx_base* ctx = nullptr;
   int cls = 0;
-  int launches = 0;
   hipEvent_t a = nullptr, b = nullptr;
   bool on = false;
   KernelTimer(gs_ctx_base* c, bool enabled, int k, hipStream_t s);
   void stop(hipStream_t s, int n_launches);
   ~KernelTimer();
 };
+void flush_kernel_timers(gs_ctx_base* ctx);
 
 // Graded multi-index set with |alpha| < p (section 2), library order.
 std::vector<std::vector<int>> multi_indices(int D, int p);

@@ -95,13 +95,19 @@ def mixture(seed_key, n, D, k, sigma, sizes="equal", weights="uniform_n", stream
     return refs, np.ascontiguousarray(w), q
 
 
+def _mixture_draw(seed_key, *a, **k):
+    return mixture(seed_key, *a, **k)
+
+
 def logspace_bandwidths(lo_exp, hi_exp, n):
     return np.array([10.0 ** (lo_exp + (hi_exp - lo_exp) * i / (n - 1)) for i in range(n)]) if n > 1 \
         else np.array([10.0 ** lo_exp])
 
 
-def workload(cfg, scale=1.0, D=None):
+def workload(cfg, scale=1.0, D=None, draw=0):
     """The five workloads (by index 0..4), optionally with N and M scaled down.
+    draw > 0 gives another independent draw of the same workload (its points
+    and weights; the bandwidths and eps are the same).
 
     0: D=2, N=M=10,000 monochromatic, 4 components sigma=0.05, w=1/N, h=0.1.
     1: D=3, N=M=100,000 monochromatic, 8 components sigma~U(0.01,0.1), w=1/N,
@@ -115,6 +121,9 @@ def workload(cfg, scale=1.0, D=None):
     eps = 0.01 for all."""
     def n_of(base):
         return max(2, int(round(base * scale)))
+
+    def mixture(seed_key, *a, **k):
+        return _mixture_draw(tuple(seed_key) + ((draw,) if draw else ()), *a, **k)
     if cfg == 0:
         N = n_of(10_000)
         r, w, _ = mixture((0, 2), N, 2, 4, 0.05)

@@ -159,3 +159,30 @@ def test_dualtree_frontier_cap_retry():
     with pytest.raises(g.GaussSumError) as ei:
         c.gauss_sum(r, r, w, hs, 0.01, leaf_size=16, max_frontier=one - 1)
     assert ei.value.status == _lib.GS_EOVERFLOW
+
+
+def test_autotune_picks_and_caches_a_configuration():
+    """autotune=1 times the leaf sizes and the exhaustive path once per
+    workload signature, then reuses the choice; every candidate is a correct
+    method, so the result meets Theorem 2 whichever is chosen."""
+    import paper_1206_6857_amd as g
+    banner("autotune")
+    c = g.Context(0)
+    r, w, _ = mixture((93, 3), 6000, 3, 6, (0.01, 0.1))
+    hs = np.logspace(-3, 0, 6)
+    G1 = c.gauss_sum(r, r, w, hs, 0.01, autotune=1)
+    st1 = c.stats()
+    assert st1.autotune_trials >= 5
+    assert st1.tuned_method in (g.GS_DUALTREE, g.GS_EXHAUSTIVE)
+    assert st1.tuned_leaf_size in (32, 64, 128, 256) or st1.tuned_method == g.GS_EXHAUSTIVE
+    G2 = c.gauss_sum(r, r, w, hs, 0.01, autotune=1)
+    st2 = c.stats()
+    assert st2.autotune_trials == 0
+    assert (st2.tuned_method, st2.tuned_leaf_size) == (st1.tuned_method, st1.tuned_leaf_size)
+    assert np.array_equal(G1, G2)
+    exact = gauss_sum_exhaustive(r, r, w, hs)
+    assert (np.abs(G2 - exact) / exact).max() <= 0.01
+    # another signature (bandwidth range) is tuned on its own
+    c.gauss_sum(r, r, w, hs * 10, 0.01, autotune=1)
+    assert c.stats().autotune_trials > 0
+    c.close()
