@@ -9,7 +9,9 @@ implementation's reading is:
   * otherwise it is split on the dimension of widest bounding-box extent
     (ties to the smallest dimension index); the node's points are ordered by
     (coordinate in that dimension, original index) and the left child takes
-    the first floor(n/2), the right child the rest;
+    the first n_left = leaf_size * ceil(n / (2 leaf_size)) (half of n rounded
+    up to a multiple of leaf_size), the right child the rest, so that all
+    leaves but one hold exactly leaf_size points;
   * nodes are numbered breadth first, level by level, left child before right;
   * the points of every node occupy a contiguous range [begin, end) of the
     permutation `perm`; inside a leaf the points are in increasing original
@@ -24,7 +26,7 @@ smallest weight wmin, and the point count.  Raw Hermite moments are attached by
 buildInternal by H2H from the children).
 
 Pinned by tests/test_oracle_tree.py: brute-force box/radius/weight checks,
-median-split property, permutation invariance of the tree geometry.
+leaf-aligned split property, permutation invariance of the tree geometry.
 """
 
 import numpy as np
@@ -60,7 +62,7 @@ def build_kdtree(x, w, leaf_size):
             dstar = int(np.argmax(ext))          # first maximum -> smallest d
             order = np.lexsort((pts, xs[:, dstar]))  # by (x_dstar, index)
             srt = pts[order]
-            half = n // 2
+            half = leaf_size * ((n + 2 * leaf_size - 1) // (2 * leaf_size))
             left.append(len(nodes_pts))
             for child, b in ((srt[:half], begin[head]), (srt[half:], begin[head] + half)):
                 nodes_pts.append(child)

@@ -3,15 +3,19 @@
 // Split rule (the paper leaves it open): a node with more than leaf_size
 // points is split on its dimension of widest bounding-box extent (ties to the
 // smallest dimension); its points ordered by (coordinate, original index)
-// go to the left child for the first floor(n/2) and to the right child for the
-// rest.  Nodes are numbered breadth first, left before right.
+// go to the left child for the first left_count(n) = half of n rounded up to a
+// multiple of leaf_size, and to the right child for the rest.  Every node
+// whose count is a multiple of leaf_size then splits into two such nodes, so
+// all leaves but one hold exactly leaf_size points: whole waves of 64 lanes
+// for the kernels that put one point per lane.  Nodes are numbered breadth
+// first, left before right.
 //
 // Construction without per-level sorting: each dimension d keeps a list of
 // point ids sorted by (x_d, id) inside every node's position range
 // [begin, begin+count) (one stable radix sort per dimension at the start), plus
 // one extra list sorted by id.  A node's bounding box is then read off the
 // first and last entry of each list, and its split assigns the first
-// floor(n/2) entries of the split dimension's list to the left child.  Every
+// left_count(n) entries of the split dimension's list to the left child.  Every
 // list is then stably partitioned by that assignment (one exclusive scan of
 // the per-entry flags over all lists at once), which keeps each list sorted
 // inside both children.  The extra list becomes the final permutation, whose
@@ -31,6 +35,10 @@
 namespace gs {
 
 namespace {
+
+__device__ __forceinline__ int64_t left_count(int64_t n, int leaf_size) {
+  return (int64_t)leaf_size * ((n + 2 * (int64_t)leaf_size - 1) / (2 * (int64_t)leaf_size));
+}
 
 __global__ void iota_kernel(int32_t* __restrict__ v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,11 +104,12 @@ __global__ __launch_bounds__(1024) void children_kernel(int lb, int le, int leaf
       if (f) {
         const int l = le + 2 * (carry + incl - 1);
         const int b = begin[i], c = count[i];
+        const int lc = (int)left_count(c, leaf_size);
         left[i] = l;
         begin[l] = b;
-        count[l] = c / 2;
-        begin[l + 1] = b + c / 2;
-        count[l + 1] = c - c / 2;
+        count[l] = lc;
+        begin[l + 1] = b + lc;
+        count[l + 1] = c - lc;
         depth[l] = depth[l + 1] = depth[i] + 1;
       } else {
         left[i] = -1;
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(1024) void children_kernel(int lb, int le, int leaf
 }
 
 // Per position of the level: left/right assignment and next-level node.
-__global__ void mark_kernel(int64_t n, const int32_t* __restrict__ lists,
+__global__ void mark_kernel(int64_t n, int leaf_size, const int32_t* __restrict__ lists,
                             const int32_t* __restrict__ pos_node,
                             int32_t* __restrict__ pos_node_next, int32_t* __restrict__ leaf_of_pos,
                             const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
@@ -128,7 +137,7 @@ __global__ void mark_kernel(int64_t n, const int32_t* __restrict__ lists,
   }
   const int l = left[node];
   if (l >= 0) {
-    const int64_t mid = (int64_t)begin[node] + count[node] / 2;
+    const int64_t mid = (int64_t)begin[node] + left_count(count[node], leaf_size);
     const int sd = splitdim[node];
     isleft[lists[(int64_t)sd * n + i]] = i < mid ? 1 : 0;
     pos_node_next[i] = i < mid ? l : l + 1;
@@ -148,7 +157,7 @@ __global__ void flags_kernel(int64_t n, int nl, const int32_t* __restrict__ list
   flags[t] = (node >= 0 && left[node] >= 0) ? isleft[lists[t]] : 0;
 }
 
-__global__ void scatter_kernel(int64_t n, int nl, const int32_t* __restrict__ lists,
+__global__ void scatter_kernel(int64_t n, int nl, int leaf_size, const int32_t* __restrict__ lists,
                                const int32_t* __restrict__ pos_node, const int32_t* __restrict__ left,
                                const int32_t* __restrict__ begin, const int32_t* __restrict__ count,
                                const int32_t* __restrict__ flags, const int32_t* __restrict__ scan,
@@ -161,7 +170,7 @@ __global__ void scatter_kernel(int64_t n, int nl, const int32_t* __restrict__ li
   int64_t dst = i;
   if (node >= 0 && left[node] >= 0) {
     const int64_t b = begin[node];
-    const int64_t half = count[node] / 2;
+    const int64_t half = left_count(count[node], leaf_size);
     const int64_t rank = (int64_t)scan[t] - (int64_t)scan[k * n + b];
     dst = flags[t] ? b + rank : b + half + (i - b - rank);
   }
@@ -256,7 +265,7 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
                        t.rinf);
     hipLaunchKernelGGL(children_kernel, dim3(1), dim3(1024), 0, s, lb, le, a.leaf_size, t.begin,
                        t.count, t.left, t.depth, a.n_children);
-    hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, lists, pos, pos_alt,
+    hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, a.leaf_size, lists, pos, pos_alt,
                        t.leaf_of_pos, t.begin, t.count, t.left, a.splitdim, a.isleft);
     int32_t nchild = 0;
     e = hipMemcpyAsync(&nchild, a.n_children, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -269,7 +278,7 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
     e = rocprim::exclusive_scan(a.temp, bytes, a.flags, a.scan, 0, (size_t)n * nl,
                                 rocprim::plus<int32_t>(), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scatter_kernel, dim3(gl), dim3(256), 0, s, n, nl, lists, pos, t.left, t.begin,
+    hipLaunchKernelGGL(scatter_kernel, dim3(gl), dim3(256), 0, s, n, nl, a.leaf_size, lists, pos, t.left, t.begin,
                        t.count, a.flags, a.scan, lists_alt);
     std::swap(lists, lists_alt);
     std::swap(pos, pos_alt);

@@ -31,14 +31,19 @@ def test_tree_properties(D, n, leaf):
             l, r = t.left[i], t.left[i] + 1
             assert t.depth[l] == t.depth[r] == t.depth[i] + 1
             assert t.begin[l] == t.begin[i] and t.end[l] == t.begin[r] and t.end[r] == t.end[i]
-            assert t.count[l] == t.count[i] // 2
+            # left child: the smallest multiple of leaf_size that is >= half
+            assert t.count[l] % leaf == 0
+            assert 2 * t.count[l] >= t.count[i] > 2 * (t.count[l] - leaf)
             ext = t.hi[i] - t.lo[i]
             d = int(np.argmax(ext))
             key = lambda j: (x[j, d], j)
             lpts = sorted(t.perm[t.begin[l]:t.end[l]].tolist(), key=key)
             rpts = sorted(t.perm[t.begin[r]:t.end[r]].tolist(), key=key)
-            assert key(lpts[-1]) < key(rpts[0])      # median split by (x_d, index)
+            assert key(lpts[-1]) < key(rpts[0])      # split by (x_d, index)
     assert np.all(np.diff(t.depth) >= 0)                # breadth-first numbering
+    leaves = t.count[t.left < 0]
+    if n > leaf:
+        assert np.sum(leaves != leaf) <= 1              # all leaves but one are full
 
 
 def test_tree_geometry_is_permutation_invariant():
