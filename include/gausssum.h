@@ -289,6 +289,22 @@ gs_status gs_policy_set_params(gs_ctx* ctx, const float* params, int64_t n);
 gs_status gs_policy_save(gs_ctx* ctx, const char* path);
 gs_status gs_policy_load(gs_ctx* ctx, const char* path);
 
+/* Least-squares cross-validation score of the Gaussian kernel density
+ * estimate of points[N][D] (the bandwidth-selection criterion of the
+ * experiments, section 7), for every bandwidth:
+ *   LSCV(h) = integral of f_h^2 - (2/N) sum_i f_{h,-i}(x_i)
+ *           = (4 pi h^2)^(-D/2)/N^2 sum_i G_{sqrt2 h}(x_i)
+ *             - 2 (2 pi h^2)^(-D/2)/(N(N-1)) sum_i (G_h(x_i) - 1),
+ * with G the multi-bandwidth sum of the points against themselves, unit
+ * weights (one gauss_sum sweep over h and sqrt(2) h).  scores[n_h] and, if
+ * not NULL, bounds[n_h] (host or device): |score - exact| <= bound, from the
+ * per-query guarantee of Theorem 2 (eps; 1e-3 for GS_EXHAUSTIVE's float
+ * tiles).  opt as for gauss_sum (monochromatic is implied; keep_trace and
+ * log_pairs are rejected).  GS_EINVAL for N < 2, n_h outside [1, 2048], a
+ * bandwidth <= 0, or any gauss_sum argument error. */
+gs_status gs_lscv(gs_ctx* ctx, const double* points, int64_t N, int32_t D, const double* bandwidths,
+                  int32_t n_h, double eps, double* scores, double* bounds, const gs_options* opt);
+
 /* Multi-index set of the O(D^p) expansions (section 2): every alpha with
  * |alpha| < p, ordered by degree and, inside a degree, in decreasing
  * lexicographic order (for D = 2, p = 2: (0,0), (1,0), (0,1)).  Writes

@@ -155,6 +155,35 @@ class Context:
                                     *[t[k].ctypes.data for k in order]))
         return t
 
+    def lscv(self, points, bandwidths, eps=0.01, **opts):
+        """Least-squares cross-validation scores and error bounds (gs_lscv)
+        of the Gaussian KDE of `points` for every bandwidth."""
+        lib = _lib.load()
+        x = _Arr(points)
+        hsrc = bandwidths
+        if not _is_torch(hsrc):
+            hsrc = np.atleast_1d(np.asarray(hsrc, dtype=np.float64))
+        hb = _Arr(hsrc)
+        n_h = int(np.prod(hb.shape))
+        N, D = x.shape
+        scores = np.zeros(n_h)
+        bounds = np.zeros(n_h)
+        opt = gs_default_options()
+        for k, v in opts.items():
+            if k == "method":
+                v = _lib.METHODS[v] if isinstance(v, str) else int(v)
+            elif k == "policy":
+                v = _lib.POLICIES[v] if isinstance(v, str) else int(v)
+            if not hasattr(opt, k):
+                raise TypeError("unknown option %r" % k)
+            setattr(opt, k, v)
+        if x.is_cuda or hb.is_cuda:
+            import torch
+            torch.cuda.current_stream().synchronize()
+        self._check(lib.gs_lscv(self._h, x.ptr, N, D, hb.ptr, n_h, float(eps), scores.ctypes.data,
+                                bounds.ctypes.data, ctypes.byref(opt)))
+        return scores, bounds
+
     # ---- learned pair policy (gs_policy_*) ----
 
     def policy_log(self):

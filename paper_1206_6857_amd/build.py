@@ -34,6 +34,7 @@ SOURCES = [
     ("k_series_fast.hip", []),
     ("k_base.hip", []),
     ("k_policy.hip", []),
+    ("k_lscv.hip", []),
     ("policy.cpp", []),
     ("dualtree.hip", NO_CONTRACT),
     ("capi.cpp", NO_CONTRACT),

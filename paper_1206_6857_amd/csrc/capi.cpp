@@ -612,4 +612,56 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   return GS_OK;
 }
 
+gs_status gs_lscv(gs_ctx* ctx, const double* points, int64_t N, int32_t D, const double* bandwidths,
+                  int32_t n_h, double eps, double* scores, double* bounds, const gs_options* opt_in) {
+  if (!ctx) return GS_EINVAL;
+  ctx->err.clear();
+  if (!points || !bandwidths || !scores) GS_FAIL(ctx, GS_EINVAL, "null array pointer");
+  if (N < 2) GS_FAIL(ctx, GS_EINVAL, "the score needs N >= 2 points");
+  if (n_h < 1 || n_h > 2048) GS_FAIL(ctx, GS_EINVAL, "n_h must be in [1, 2048]");
+  gs_options opt;
+  gs_default_options(&opt);
+  if (opt_in) {
+    if (opt_in->struct_size != (int32_t)sizeof(gs_options))
+      GS_FAIL(ctx, GS_EINVAL, "gs_options.struct_size does not match this library");
+    opt = *opt_in;
+  }
+  if (opt.keep_trace || opt.log_pairs) GS_FAIL(ctx, GS_EINVAL, "keep_trace and log_pairs do not apply to gs_lscv");
+  opt.monochromatic = 1;
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  std::vector<double> hs(n_h);
+  if (is_device_pointer(bandwidths)) {
+    GS_HIP(ctx, hipMemcpyAsync(hs.data(), bandwidths, n_h * sizeof(double), hipMemcpyDeviceToHost, st));
+    GS_HIP(ctx, hipStreamSynchronize(st));
+  } else {
+    std::copy(bandwidths, bandwidths + n_h, hs.begin());
+  }
+  for (double h : hs)
+    if (!(h > 0.0) || !std::isfinite(h)) GS_FAIL(ctx, GS_EINVAL, "every bandwidth must be finite and > 0");
+  // one sweep over h and sqrt(2) h, unit weights, the points against themselves
+  std::vector<double> ext(2 * (size_t)n_h);
+  for (int k = 0; k < n_h; ++k) {
+    ext[k] = hs[k];
+    ext[n_h + k] = std::sqrt(2.0) * hs[k];
+  }
+  double* w = WS(double, "lscv_w", N);
+  GS_HIP(ctx, launch_fill(w, N, 1.0, st));
+  double* G = WS(double, "lscv_G", 2 * (int64_t)n_h * N);
+  gs_status s = gauss_sum(ctx, points, N, points, w, N, D, ext.data(), 2 * n_h, eps, G, &opt);
+  if (s != GS_OK) return s;
+  double* sums = WS(double, "lscv_sums", 2 * n_h);
+  double* dh = WS(double, "lscv_hs", n_h);
+  double* out = WS(double, "lscv_out", 2 * n_h);
+  GS_HIP(ctx, hipMemcpyAsync(dh, hs.data(), n_h * sizeof(double), hipMemcpyHostToDevice, st));
+  GS_HIP(ctx, launch_lscv_reduce(G, 2 * n_h, N, sums, st));
+  // the exhaustive path's float tiles stay within 1e-3 relative per query
+  const double e = opt.method == GS_EXHAUSTIVE ? 1e-3 : eps;
+  GS_HIP(ctx, launch_lscv_combine(sums, dh, n_h, N, D, e, out, out + n_h, st));
+  GS_HIP(ctx, hipMemcpyAsync(scores, out, n_h * sizeof(double), hipMemcpyDefault, st));
+  if (bounds) GS_HIP(ctx, hipMemcpyAsync(bounds, out + n_h, n_h * sizeof(double), hipMemcpyDefault, st));
+  GS_HIP(ctx, hipStreamSynchronize(st));
+  return GS_OK;
+}
+
 }  // extern "C"

@@ -44,4 +44,12 @@ hipError_t launch_exhaustive(const double* xq_aos, int64_t M, const float* rec, 
                              const unsigned long long* wmax_bits, double* partial, double* G_out,
                              hipStream_t s);
 
+// ------------------------------------------------------------------- LSCV
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// sums[r] = sum_i G[r][i] (fixed order), for r < rows.
+hipError_t launch_lscv_reduce(const double* G, int rows, int64_t N, double* sums, hipStream_t s);
+// score/bound[n_h] from sums[2 n_h] (h rows, then sqrt(2) h rows) and hs[n_h] (device).
+hipError_t launch_lscv_combine(const double* sums, const double* hs, int n_h, int64_t N, int D, double eps,
+                               double* score, double* bound, hipStream_t s);
+
 }  // namespace gs
