@@ -82,6 +82,15 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libgausssum.so is not built (run __graft_entry__.build()); "
                            "there is no CPU fallback")
+    # The library uses the system ROCm runtime; PyTorch ships its own.  When
+    # both live in one process, PyTorch's must initialise first or it finds no
+    # device, so initialise it before the library's first HIP call.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double

@@ -42,10 +42,33 @@ void* Workspace::get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hi
   return b.p;
 }
 
+void* Workspace::get_pinned(const std::string& name, size_t bytes, hipError_t* err) {
+  Buf& b = pinned[name];
+  if (bytes == 0) bytes = 16;
+  if (b.cap < bytes) {
+    if (b.p) hipHostFree(b.p);
+    b.p = nullptr;
+    size_t cap = std::max(bytes, b.cap + b.cap / 2);
+    hipError_t e = hipHostMalloc(&b.p, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      b.cap = 0;
+      *err = e;
+      return nullptr;
+    }
+    b.cap = cap;
+  }
+  return b.p;
+}
+
 void Workspace::release_all() {
   for (auto& kv : bufs)
     if (kv.second.p) hipFree(kv.second.p);
   bufs.clear();
+  for (auto& kv : pinned)
+    if (kv.second.p) hipHostFree(kv.second.p);
+  pinned.clear();
 }
 
 bool is_device_pointer(const void* p) {
@@ -225,8 +248,18 @@ const char* gs_last_error(gs_ctx* ctx) {
   return ctx->err.c_str();
 }
 
+// Pending counters and timers of a non-blocking call: drain the stream first.
+static void settle(gs_ctx* ctx) {
+  if (!ctx->stats_pending && ctx->pending.empty()) return;
+  (void)hipSetDevice(ctx->device);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) (void)hipGetLastError();
+  finish_dualtree_stats(ctx);
+  flush_kernel_timers(ctx);
+}
+
 gs_status gs_get_stats(gs_ctx* ctx, gs_stats* out) {
   if (!ctx || !out) return GS_EINVAL;
+  settle(ctx);
   if (out->struct_size < (int32_t)sizeof(gs_stats)) GS_FAIL(ctx, GS_EINVAL, "gs_stats.struct_size too small");
   *out = ctx->stats;
   out->struct_size = (int32_t)sizeof(gs_stats);
@@ -235,6 +268,7 @@ gs_status gs_get_stats(gs_ctx* ctx, gs_stats* out) {
 
 gs_status gs_get_pair_counts(gs_ctx* ctx, int64_t* counts) {
   if (!ctx || !counts) return GS_EINVAL;
+  settle(ctx);
   std::copy(ctx->pair_counts.begin(), ctx->pair_counts.end(), counts);
   return GS_OK;
 }
@@ -529,6 +563,7 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   // One summation with the options o into Gd; resets the statistics.
   auto run_once = [&](const gs_options& o) -> gs_status {
     GS_HIP(ctx, hipStreamSynchronize(st));
+    ctx->stats_pending = nullptr;
     flush_kernel_timers(ctx);  // timers of an earlier trial
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.struct_size = sizeof(gs_stats);
@@ -607,7 +642,10 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   } else if (opt.blocking) {
     GS_HIP(ctx, hipStreamSynchronize(st));
   }
-  flush_kernel_timers(ctx);
+  if (!out_dev || opt.blocking) {
+    finish_dualtree_stats(ctx);
+    flush_kernel_timers(ctx);
+  }
   ctx->stats.t_total_ms = now_ms() - t_start;
   return GS_OK;
 }

@@ -296,10 +296,14 @@ static gs_status build_tree(gs_ctx_base* ctx, const char* pre, const double* xs,
   a.flags = BUF(int32_t, "tb_flags", n * (D + 1));
   a.scan = BUF(int32_t, "tb_scan", n * (D + 1));
   a.splitdim = BUF(int32_t, "tb_splitdim", cap);
-  a.n_children = BUF(int32_t, "tb_nchild", 1);
   a.sort_keys = BUF(double, "tb_sortkeys", n);
   a.temp_bytes = tree_sort_temp_bytes(n, D);
   a.temp = BUF(char, "tb_temp", a.temp_bytes);
+  {
+    hipError_t pe = hipSuccess;
+    a.host_topo = static_cast<int32_t*>(ctx->ws.get_pinned(P + "topo", 4 * cap * sizeof(int32_t), &pe));
+    if (!a.host_topo) DT_FAIL(GS_ENOMEM, "pinned host allocation failed for the tree topology");
+  }
   hipError_t e = build_tree_device(a, t, t.level_begin, st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -341,6 +345,22 @@ static gs_status keep_tree(gs_ctx_base* ctx, const DevTree& t, int D, HostTree& 
   return GS_OK;
 }
 
+void finish_dualtree_stats(gs_ctx_base* ctx) {
+  const unsigned long long* hc = ctx->stats_pending;
+  if (!hc) return;
+  const int n_h = ctx->stats_pending_nh;
+  gs_stats& S = ctx->stats;
+  for (int k = 0; k < n_h * 6; ++k) {
+    ctx->pair_counts[k] = (int64_t)hc[k];
+    S.pairs[k % 6] += (int64_t)hc[k];
+  }
+  S.base_pair_evals = (int64_t)hc[n_h * 6];
+  S.base_dist_evals = (int64_t)hc[n_h * 6 + 1];
+  S.policy_calls = (int64_t)hc[n_h * 6 + 2];
+  S.policy_fallbacks = (int64_t)hc[n_h * 6 + 3];
+  ctx->stats_pending = nullptr;
+}
+
 gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vector<double>& hs,
                        double eps, const gs_options& opt, double* G_dev) {
   hipStream_t st = ctx->stream;
@@ -359,6 +379,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double t0 = now_ms();
 
   // 1. Trees.
+  KernelTimer ktree(ctx, ctx->kernel_timing, GS_K_TREE, st);
   DevTree rt, qt_own;
   gs_status s = build_tree(ctx, "rt_", in.r_soa, in.w, N, D, opt.leaf_size, rt, st);
   if (s != GS_OK) return s;
@@ -381,9 +402,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   }
   unsigned long long* wmax_bits = BUF(unsigned long long, "wmax_bits", 1);
   DT_HIP(launch_max_positive(in.w, N, wmax_bits, st));
-  double Wtot = 0.0;
-  DT_HIP(hipMemcpyAsync(&Wtot, rt.W, sizeof(double), hipMemcpyDeviceToHost, st));
-  DT_HIP(hipStreamSynchronize(st));
+  ktree.stop(st, 1);
   double t1 = now_ms();
   S.t_tree_ms = t1 - t0;
 
@@ -428,11 +447,12 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* Mom = nullptr;
   if (use_fmm) {
     Mom = BUF(double, "moments", (int64_t)nR * C);
+    KernelTimer km(ctx, ctx->kernel_timing, GS_K_MOMENTS, st);
     DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, st));
     for (int lv = (int)rt.level_begin.size() - 2; lv >= 0; --lv)
       DT_HIP(launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st));
+    km.stop(st, (int)rt.level_begin.size());
   }
-  DT_HIP(hipStreamSynchronize(st));
   double t2 = now_ms();
   S.t_moments_ms = t2 - t1;
 
@@ -468,7 +488,6 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   dc.mono = in.mono ? 1 : 0;
   dc.use_tokens = use_tokens ? 1 : 0;
   dc.use_fmm = use_fmm ? 1 : 0;
-  dc.Wtot = Wtot;
   dc.eps_alg = (1.0 - opt.eps_round_share) * eps;
   dc.fmm_mask = (opt.fmm_mask & 7) ? (opt.fmm_mask & 7) : 7;
   const bool use_policy = use_fmm && opt.policy == GS_LEARNED;
@@ -500,17 +519,17 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* lco = use_fmm ? BUF(double, "lco", (int64_t)n_h * nQ * C) : nullptr;
   double* gx = BUF(double, "gx", (int64_t)n_h * Mq);
   double* gdh = BUF(double, "gdh", (int64_t)n_h * Mq);
-  // [n_h][6] decisions per type, then four per-chunk event counters: base
+  // [n_h][6] decisions per type, then four event counters of the call: base
   // point-pair evaluations, base distance evaluations, policy consultations,
-  // policy fallbacks.
-  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 4);
+  // policy fallbacks; then their copy taken at the start of each chunk.
+  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 8);
   unsigned long long* chunk_ev = hcount + n_h * 6;
   DT_HIP(hipMemsetAsync(Gest, 0, sizeof(double) * n_h * nQ, st));
   DT_HIP(hipMemsetAsync(pL, 0, sizeof(int32_t) * n_h * nQ, st));
   if (lco) DT_HIP(hipMemsetAsync(lco, 0, sizeof(double) * n_h * nQ * C, st));
   DT_HIP(hipMemsetAsync(gx, 0, sizeof(double) * n_h * Mq, st));
   DT_HIP(hipMemsetAsync(gdh, 0, sizeof(double) * n_h * Mq, st));
-  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 4), st));
+  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 8), st));
   float* rec = nullptr;  // base-case reference records, built on first use
   bool rec_ready = false;
   BaseRecordsArgs ra;
@@ -535,7 +554,6 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double t_trav = 0.0, t_work = 0.0;
   int64_t peak = 0;
   int max_level = 0;
-  int64_t base_evals = 0, dist_evals = 0, pol_calls = 0, pol_falls = 0;
   PolicyTreeView pqt{qt.lo, qt.hi, qt.rinf, qt.count, qt.left};
   PolicyTreeView prt{rt.lo, rt.hi, rt.rinf, rt.count, rt.left};
 
@@ -556,6 +574,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       // Undo the chunk's decisions: lower-bound sums, counters and trace.
       DT_HIP(hipMemsetAsync(Gest + (int64_t)hc0 * nQ, 0, sizeof(double) * nh * nQ, st));
       DT_HIP(hipMemsetAsync(hcount + hc0 * 6, 0, sizeof(unsigned long long) * nh * 6, st));
+      DT_HIP(hipMemcpyAsync(chunk_ev, chunk_ev + 4, 4 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
       DT_HIP(hipStreamSynchronize(st));
       ctx->trace.resize(trace0);
       ctx->trace_feat.resize(trace0 / 6 * kPolicyIn);
@@ -570,7 +589,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     if (_s != GS_OK) return _s;                            \
   } while (0)
     const double ta = now_ms();
-    DT_HIP(hipMemsetAsync(chunk_ev, 0, 4 * sizeof(unsigned long long), st));
+    // the event counters run over the whole call; a retried chunk restores them
+    DT_HIP(hipMemcpyAsync(chunk_ev + 4, chunk_ev, 4 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
     FrontierLevel cur, nxt;
     int64_t nseg = nh, npair = nh;
     CHUNK_ALLOC(level_bufs(0, nseg, npair, cur));
@@ -695,7 +715,6 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       npair = npair2;
       ++level;
     }
-    DT_HIP(hipStreamSynchronize(st));
     const double tb0 = now_ms();
     t_trav += tb0 - ta;
     max_level = std::max(max_level, level);
@@ -824,10 +843,10 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, st);
       for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
         const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
-        // query nodes of traversal level lv: depth lv (at most ceil(M / 2^lv)
-        // points) or leaves of earlier levels (at most leaf_size points)
-        const int64_t depth_max = lv < 62 ? ((Mq + ((int64_t)1 << lv) - 1) >> lv) : 1;
-        const int max_q = (int)std::max<int64_t>(depth_max, opt.leaf_size);
+        // query nodes of traversal level lv: nodes of depth lv, or leaves of
+        // earlier levels (at most leaf_size points)
+        const int depth_max = lv < qt.level_max.size() ? qt.level_max[lv] : 0;
+        const int max_q = std::max(depth_max, opt.leaf_size);
         if (fast)
           DT_HIP(launch_dh_fast(D, P, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
                                 Mom, d_sc, (int)Mq, gdh, st));
@@ -849,13 +868,6 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       DT_HIP(launch_base_fused(ba, plan, st));
       kt.stop(st, 1);
     }
-    unsigned long long ev[4] = {0, 0, 0, 0};
-    DT_HIP(hipMemcpyAsync(ev, chunk_ev, sizeof(ev), hipMemcpyDeviceToHost, st));
-    DT_HIP(hipStreamSynchronize(st));
-    base_evals += (int64_t)ev[0];
-    dist_evals += (int64_t)ev[1];
-    pol_calls += (int64_t)ev[2];
-    pol_falls += (int64_t)ev[3];
     t_work += now_ms() - tb0;
     return GS_OK;
   };
@@ -881,36 +893,29 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   S.levels = max_level;
   S.frontier_peak = peak;
   S.h_chunks = h_chunks;
-  S.base_pair_evals = base_evals;
-  S.base_dist_evals = dist_evals;
-  S.policy_calls = pol_calls;
-  S.policy_fallbacks = pol_falls;
 
   // 5. Post-pass.
+  KernelTimer kpost(ctx, ctx->kernel_timing, GS_K_POST, st);
   for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
     DT_HIP(launch_l2l_level(T, qv, qt.level_begin[lv], qt.level_begin[lv + 1], n_h, nQ, d_sc,
                             lco ? lco : Gest, pL, Gest, st));
-  std::vector<int32_t> qleft(nQ);
-  DT_HIP(hipMemcpyAsync(qleft.data(), qt.left, nQ * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  DT_HIP(hipStreamSynchronize(st));
-  std::vector<int32_t> leaves;
-  for (int i = 0; i < nQ; ++i)
-    if (qleft[i] < 0) leaves.push_back(i);
-  int32_t* d_leaves = BUF(int32_t, "q_leaves", leaves.size());
-  DT_HIP(upload(leaves, d_leaves, st));
-  DT_HIP(launch_leaf_eval(T, qv, d_leaves, (int)leaves.size(), n_h, nQ, (int)Mq, d_sc, xq_perm,
-                          qt.perm, gx, gdh, Gest, lco ? lco : Gest, pL, G_dev, st));
-  DT_HIP(hipStreamSynchronize(st));
+  // one workgroup per query node; internal nodes exit at once
+  DT_HIP(launch_leaf_eval(T, qv, nullptr, nQ, n_h, nQ, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh, Gest,
+                          lco ? lco : Gest, pL, G_dev, st));
+  kpost.stop(st, (int)qt.level_begin.size());
   double t5 = now_ms();
   S.t_post_ms = t5 - t4;
 
-  // Statistics.
-  std::vector<unsigned long long> hc(n_h * 6);
-  DT_HIP(hipMemcpyAsync(hc.data(), hcount, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-  DT_HIP(hipStreamSynchronize(st));
-  for (int k = 0; k < n_h * 6; ++k) {
-    ctx->pair_counts[k] = (int64_t)hc[k];
-    S.pairs[k % 6] += (int64_t)hc[k];
+  // Statistics: copied to pinned memory now, read after the call's final
+  // synchronisation (finish_dualtree_stats).
+  {
+    hipError_t pe = hipSuccess;
+    auto* hc = static_cast<unsigned long long*>(
+        ctx->ws.get_pinned("stats_counts", sizeof(unsigned long long) * (n_h * 6 + 4), &pe));
+    if (!hc) DT_FAIL(GS_ENOMEM, "pinned host allocation failed for the statistics");
+    DT_HIP(hipMemcpyAsync(hc, hcount, sizeof(unsigned long long) * (n_h * 6 + 4), hipMemcpyDeviceToHost, st));
+    ctx->stats_pending = hc;
+    ctx->stats_pending_nh = n_h;
   }
   if (opt.keep_trace) {
     s = keep_tree(ctx, rt, D, ctx->host_tree[0], st);
@@ -920,6 +925,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   }
   if (log_pairs) {
     DT_HIP(hipStreamSynchronize(st));
+    finish_dualtree_stats(ctx);
     flush_kernel_timers(ctx);
     policy_calibrate_costs(ctx, D);
     s = policy_build_records(ctx, D, hs);

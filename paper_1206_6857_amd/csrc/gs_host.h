@@ -22,7 +22,9 @@ struct gs_ctx_base;
 // Named device buffers, grown geometrically and reused across calls.
 struct Workspace {
   std::map<std::string, Buf> bufs;
+  std::map<std::string, Buf> pinned;  // page-locked host buffers (hipHostMalloc)
   void* get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hipError_t* err);
+  void* get_pinned(const std::string& name, size_t bytes, hipError_t* err);
   void release_all();
 };
 
@@ -56,6 +58,10 @@ struct gs_ctx_base {
   PolicyState policy;
   std::map<std::string, std::pair<int, int>> tuned;  // autotuner: signature -> (method, leaf)
   std::vector<hipEvent_t> ev_pool;                    // reusable timing events
+  // decision counters of the last dual-tree call, being copied to pinned
+  // memory; read by finish_dualtree_stats once the stream has drained
+  const unsigned long long* stats_pending = nullptr;
+  int stats_pending_nh = 0;
   std::vector<PendingTimer> pending;                  // recorded, not yet read
 };
 
@@ -107,6 +113,10 @@ gs_status policy_save(gs_ctx_base* ctx, const char* path);
 gs_status policy_load(gs_ctx_base* ctx, const char* path);
 gs_status policy_write_log(gs_ctx_base* ctx, const char* path);
 gs_status policy_read_log(gs_ctx_base* ctx, const char* path, std::vector<float>* rec);
+
+// Folds the counters of the last dual-tree call into stats and pair_counts;
+// the stream must have drained.
+void finish_dualtree_stats(gs_ctx_base* ctx);
 
 // Dual-tree summation (GS_DUALTREE, GS_DFD, GS_DFDO) into G_dev[n_h][M].
 gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vector<double>& hs,

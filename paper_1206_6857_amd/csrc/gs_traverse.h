@@ -22,7 +22,7 @@ struct DecideConst {
   int log_feas = 0;  // 1: record the admitted orders where bestMethod is reached
   double explore = 0.0;  // logging: probability of taking the direct path
                          // instead of the rule's series choice
-  double Wtot = 0.0, eps_alg = 0.0;
+  double eps_alg = 0.0;
   double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
   double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
   int64_t powD[2 * kMaxPlimit + 2];  // D^k, saturated at INT64_MAX (cost model)

@@ -19,6 +19,7 @@ struct DevTree {
   double *rinf = nullptr, *W = nullptr, *wmin = nullptr;
   const int32_t* perm_list = nullptr;
   std::vector<int> level_begin;    // host: first node of each level, then n_nodes
+  std::vector<int> level_max;      // host: most points in a node of each level
 };
 
 struct TreeBuildArgs {
@@ -31,13 +32,16 @@ struct TreeBuildArgs {
   int32_t *pos_node = nullptr, *pos_node_alt = nullptr, *isleft = nullptr;  // [n]
   int32_t *flags = nullptr, *scan = nullptr;                             // [(D+1) n]
   int32_t *splitdim = nullptr;                                           // [capacity]
-  int32_t *n_children = nullptr;                                         // [1]
   double* sort_keys = nullptr;                                           // [n]
+  int32_t* host_topo = nullptr;  // pinned host memory, 4 * capacity: the node topology
   void* temp = nullptr;
   size_t temp_bytes = 0;
 };
 
 int64_t tree_node_capacity(int64_t n, int leaf_size);
+// Node counts follow from n and leaf_size alone (the split rule takes whole
+// leaves), so the topology -- begin, count, left, depth of every node and the
+// level boundaries -- is computed on the host; the device only sorts points.
 size_t tree_sort_temp_bytes(int64_t n, int D);
 hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int>& level_begin,
                              hipStream_t s);

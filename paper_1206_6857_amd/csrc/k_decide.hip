@@ -196,11 +196,15 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   const double* hiQ = qt.hi + (int64_t)Q * D;
   const double i2 = inv2h2[h], i4 = inv4h2[h], ih = invh[h];
   const bool qleaf = qt.left[Q] < 0;
+  const double Wtot = rt.W[0];  // total reference weight (the root's)
   const int64_t NQ = qt.count[Q];
   const double rQ = qt.rinf[Q] * ih;
 
-  // Lower bound L over Q, summed in pair order.
+  // Lower bound L over Q, summed in pair order.  The first 64 pairs' box
+  // distances and K(dmax) stay in registers for the decision pass.
   double L = cur.Lp[s];
+  int R0 = 0;
+  double dmin2_0 = 0.0, dmax2_0 = 0.0, kmax_0 = 0.0, WR_0 = 0.0;
   for (int b0 = 0; b0 < len; b0 += 64) {
     const int n = len - b0 < 64 ? len - b0 : 64;
     double lterm = 0.0;
@@ -208,7 +212,16 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
       const int R = cur.R[off + b0 + lane];
       double dmin2, dmax2;
       box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
-      lterm = rt.W[R] * own_exp(-dmax2 * i2);
+      const double kmax = own_exp(-dmax2 * i2);
+      const double WR = rt.W[R];
+      lterm = WR * kmax;
+      if (b0 == 0) {
+        R0 = R;
+        dmin2_0 = dmin2;
+        dmax2_0 = dmax2;
+        kmax_0 = kmax;
+        WR_0 = WR;
+      }
     }
     for (int j = 0; j < n; ++j) L = L + rl(lterm, j);
   }
@@ -233,12 +246,21 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
 #pragma unroll
     for (int p = 0; p < P; ++p) pm0[p] = pm1[p] = pm2[p] = INFINITY;
     if (lane < n) {
-      const int R = cur.R[off + b0 + lane];
-      double dmin2, dmax2;
-      box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
-      const double kmax = own_exp(-dmax2 * i2);
+      int R;
+      double dmin2, dmax2, kmax;
+      if (b0 == 0) {
+        R = R0;
+        dmin2 = dmin2_0;
+        dmax2 = dmax2_0;
+        kmax = kmax_0;
+        WR = WR_0;
+      } else {
+        R = cur.R[off + b0 + lane];
+        box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
+        kmax = own_exp(-dmax2 * i2);
+        WR = rt.W[R];
+      }
       const double kmin = own_exp(-dmin2 * i2);
-      WR = rt.W[R];
       NR = rt.count[R];
       Rid = R;
       if (scores) {
@@ -252,7 +274,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
       rleaf = rt.left[R] < 0 ? 1 : 0;
       lterm = WR * kmax;
       fdval = 0.5 * (WR * (kmin + kmax));
-      nd = need_fn(0.5 * (WR * (kmin - kmax)), WR, L, c.Wtot, c.eps_alg);
+      nd = need_fn(0.5 * (WR * (kmin - kmax)), WR, L, Wtot, c.eps_alg);
       if (c.use_fmm) {
         const double g = own_exp(-dmin2 * i4);
         const double rR = rt.rinf[R] * ih;
@@ -286,7 +308,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
             mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
           if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
         }
-        astar = all_orders ? -INFINITY : division_threshold(mstar, c.Wtot);
+        astar = all_orders ? -INFINITY : division_threshold(mstar, Wtot);
       }
     }
     // The token rule, pair by pair, the wave in lockstep.
@@ -313,7 +335,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           if (kj == 3) {
             rule = false;
           } else {
-            const double maxerr = a / c.Wtot;
+            const double maxerr = a / Wtot;
             int qk = 0;
             double ek = 0.0;
             if (lane == j) {
@@ -340,7 +362,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           }
         }
         if (rule && (all_orders || a >= rl(astar, j))) {
-          const double maxerr = a / c.Wtot;
+          const double maxerr = a / Wtot;
           int q0 = 0, q1 = 0, q2 = 0;
           double e0 = 0.0, e1 = 0.0, e2 = 0.0;
           if (lane == j) {
@@ -415,7 +437,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           else if (cd == H2L) Esel = rl(e2, j);
           if (c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
         }
-        if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, c.Wtot, c.eps_alg);
+        if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, Wtot, c.eps_alg);
         if (cd < 0) {
           if (qleaf && rl(rleaf, j)) {
             if (c.use_tokens) t = t + WRj;

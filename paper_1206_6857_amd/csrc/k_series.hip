@@ -370,7 +370,9 @@ __global__ __launch_bounds__(kW) void leaf_eval_kernel(SeriesTables T, NodeView 
   const int li = blockIdx.x;
   const int h = blockIdx.y;
   if (li >= n_leaves) return;
-  const int Q = leaves[li];
+  // leaves == nullptr: one workgroup per node, internal nodes exit
+  const int Q = leaves ? leaves[li] : li;
+  if (!leaves && qt.left[Q] >= 0) return;
   const int D = T.D, P = T.P, C = T.C;
   const int64_t me = (int64_t)h * nQ + Q;
   const int p = pL[me];

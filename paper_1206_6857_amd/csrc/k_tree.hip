@@ -29,6 +29,8 @@
 #include <cstring>  // rocprim uses memset without including it
 #include <rocprim/rocprim.hpp>
 
+#include <algorithm>
+
 #include "gs_internal.h"
 #include "gs_tree.h"
 
@@ -76,49 +78,6 @@ __global__ void node_stats_kernel(int lb, int le, int D, int64_t n, const int32_
   }
   splitdim[i] = best;
   rinf[i] = r;
-}
-
-// One workgroup: number the children of the level's split nodes.
-__global__ __launch_bounds__(1024) void children_kernel(int lb, int le, int leaf_size,
-                                                       int32_t* __restrict__ begin,
-                                                       int32_t* __restrict__ count,
-                                                       int32_t* __restrict__ left,
-                                                       int32_t* __restrict__ depth,
-                                                       int32_t* __restrict__ n_children_out) {
-  __shared__ int sc[1024];
-  int carry = 0;
-  for (int base = lb; base < le; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int f = (i < le && count[i] > leaf_size) ? 1 : 0;
-    sc[threadIdx.x] = f;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
-      __syncthreads();
-      sc[threadIdx.x] += v;
-      __syncthreads();
-    }
-    const int incl = sc[threadIdx.x];
-    const int total = sc[1023];
-    if (i < le) {
-      if (f) {
-        const int l = le + 2 * (carry + incl - 1);
-        const int b = begin[i], c = count[i];
-        const int lc = (int)left_count(c, leaf_size);
-        left[i] = l;
-        begin[l] = b;
-        count[l] = lc;
-        begin[l + 1] = b + lc;
-        count[l + 1] = c - lc;
-        depth[l] = depth[l + 1] = depth[i] + 1;
-      } else {
-        left[i] = -1;
-      }
-    }
-    carry += total;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *n_children_out = 2 * carry;
 }
 
 // Per position of the level: left/right assignment and next-level node.
@@ -243,11 +202,50 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
   e = hipMemcpyAsync(a.lists + (int64_t)D * n, a.ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
 
-  // Root.
-  int32_t root[3] = {0, (int32_t)n, 0};
-  e = hipMemcpyAsync(t.begin, &root[0], sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(t.count, &root[1], sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(t.depth, &root[2], sizeof(int32_t), hipMemcpyHostToDevice, s);
+  // Topology on the host (the counts depend on n and leaf_size only), in
+  // breadth-first numbering, uploaded from pinned memory without a wait.
+  const int64_t cap = t.capacity;
+  int32_t* hb = a.host_topo;
+  int32_t* hc = hb + cap;
+  int32_t* hl = hc + cap;
+  int32_t* hd = hl + cap;
+  hb[0] = 0;
+  hc[0] = (int32_t)n;
+  hd[0] = 0;
+  int64_t nn = 1;
+  level_begin.clear();
+  int lb = 0, le = 1;
+  while (true) {
+    level_begin.push_back(lb);
+    const int64_t before = nn;
+    for (int i = lb; i < le; ++i) {
+      if (hc[i] > a.leaf_size) {
+        if (nn + 2 > cap) return hipErrorInvalidValue;
+        const int64_t lc = (int64_t)a.leaf_size * ((hc[i] + 2 * (int64_t)a.leaf_size - 1) / (2 * (int64_t)a.leaf_size));
+        hl[i] = (int32_t)nn;
+        hb[nn] = hb[i];
+        hc[nn] = (int32_t)lc;
+        hb[nn + 1] = hb[i] + (int32_t)lc;
+        hc[nn + 1] = hc[i] - (int32_t)lc;
+        hd[nn] = hd[nn + 1] = hd[i] + 1;
+        nn += 2;
+      } else {
+        hl[i] = -1;
+      }
+    }
+    if (nn == before) break;
+    lb = le;
+    le = (int)nn;
+  }
+  t.level_max.assign(level_begin.size(), 0);
+  for (size_t lv = 0; lv < level_begin.size(); ++lv) {
+    const int e0 = lv + 1 < level_begin.size() ? level_begin[lv + 1] : (int)nn;
+    for (int i = level_begin[lv]; i < e0; ++i) t.level_max[lv] = std::max(t.level_max[lv], hc[i]);
+  }
+  e = hipMemcpyAsync(t.begin, hb, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.count, hc, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.left, hl, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.depth, hd, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(a.pos_node, 0, n * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
 
@@ -255,23 +253,16 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
   int32_t* lists_alt = a.lists_alt;
   int32_t* pos = a.pos_node;
   int32_t* pos_alt = a.pos_node_alt;
-  level_begin.clear();
-  int lb = 0, le = 1;
-  while (true) {
-    level_begin.push_back(lb);
-    const int width = le - lb;
-    hipLaunchKernelGGL(node_stats_kernel, dim3((unsigned)ceil_div(width, 256)), dim3(256), 0, s, lb,
-                       le, D, n, lists, a.xs, t.begin, t.count, t.lo, t.hi, t.ctr, a.splitdim,
+  for (size_t lv = 0; lv + 1 < level_begin.size() || lv + 1 == level_begin.size(); ++lv) {
+    const int b0 = level_begin[lv];
+    const int e0 = lv + 1 < level_begin.size() ? level_begin[lv + 1] : (int)nn;
+    const int width = e0 - b0;
+    hipLaunchKernelGGL(node_stats_kernel, dim3((unsigned)ceil_div(width, 256)), dim3(256), 0, s, b0,
+                       e0, D, n, lists, a.xs, t.begin, t.count, t.lo, t.hi, t.ctr, a.splitdim,
                        t.rinf);
-    hipLaunchKernelGGL(children_kernel, dim3(1), dim3(1024), 0, s, lb, le, a.leaf_size, t.begin,
-                       t.count, t.left, t.depth, a.n_children);
     hipLaunchKernelGGL(mark_kernel, dim3(g1), dim3(256), 0, s, n, a.leaf_size, lists, pos, pos_alt,
                        t.leaf_of_pos, t.begin, t.count, t.left, a.splitdim, a.isleft);
-    int32_t nchild = 0;
-    e = hipMemcpyAsync(&nchild, a.n_children, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    if (nchild == 0) break;
+    if (lv + 1 == level_begin.size()) break;  // the last level has no children
     hipLaunchKernelGGL(flags_kernel, dim3(gl), dim3(256), 0, s, n, nl, lists, pos, t.left, a.isleft,
                        a.flags);
     size_t bytes = a.temp_bytes;
@@ -282,10 +273,8 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
                        t.count, a.flags, a.scan, lists_alt);
     std::swap(lists, lists_alt);
     std::swap(pos, pos_alt);
-    lb = le;
-    le = le + nchild;
-    if (le > t.capacity) return hipErrorInvalidValue;
   }
+  le = (int)nn;
   level_begin.push_back(le);
   t.n_nodes = le;
   t.n_points = n;
