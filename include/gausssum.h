@@ -251,7 +251,10 @@ typedef struct gs_train_opts {
 void gs_default_train_opts(gs_train_opts* opts);
 
 /* Cost model of the policy's training targets (defaults: measured on one
- * MI355X).  All fields must be >= 0. */
+ * MI355X).  Each logging call (log_pairs = 1) first recalibrates the model
+ * from its own kernel timings (every cost whose kernels ran for at least
+ * 0.2 ms), unless a model was set here: a caller's model is kept as given.
+ * All fields must be >= 0. */
 gs_status gs_policy_set_cost_model(gs_ctx* ctx, const gs_cost_model* cm);
 gs_status gs_policy_get_cost_model(gs_ctx* ctx, gs_cost_model* cm);
 

@@ -329,6 +329,7 @@ gs_status gs_policy_set_cost_model(gs_ctx* ctx, const gs_cost_model* cm) {
   ps.c_dl = v[2];
   ps.c_h2l = v[3];
   ps.c_base = v[4];
+  ps.costs_pinned = true;
   return GS_OK;
 }
 

@@ -644,7 +644,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         if (use_policy) DT_HIP(launch_policy_infer_pairs((int)npair, pp, pqt, prt, D, pmodel, scores, st));
         if (log_pairs) DT_HIP(launch_policy_features((int)npair, pp, pqt, prt, D, pfeat, st));
         DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
-                             Gest, cnt, hcount, chunk_ev, scores, pfeas, chunk_ev + 2, st));
+                             Gest, cnt, scores, pfeas, st));
         DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
         kt.stop(st, 2 + (use_policy ? 1 : 0) + (log_pairs ? 1 : 0));
       }
@@ -702,7 +702,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       CHUNK_ALLOC(level_bufs(1 - which, nseg2, npair2, nxt));
       {
         KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
-        DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo, st));
+        DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo,
+                           hcount, chunk_ev, st));
         kt.stop(st, 1);
       }
       for (int x = 0; x < 4; ++x) {

@@ -73,6 +73,7 @@ struct PolicyState {
   bool dev_fresh = false;  // the workspace copies (pol_theta, pol_wpack) match theta
   // cost model, ns per unit
   double c_pair = 0.0, c_dh = 0.0, c_dl = 0.0, c_h2l = 0.0, c_base = 0.0;
+  bool costs_pinned = false;  // set by the caller: logging does not recalibrate
   // training records of the last logged call, and their (h, level, Q, R)
   std::vector<float> log;
   std::vector<int32_t> log_keys;

@@ -30,8 +30,10 @@ struct DecideConst {
 
 // Counters of one frontier segment (one (bandwidth, query node) pair list).
 struct SegCount {
-  int64_t v[10];  // [0] next-level pairs, [1] next-level segments,
-                  // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags
+  int64_t v[16];  // [0] next-level pairs, [1] next-level segments,
+                  // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags,
+                  // [10] FD pairs, [11] SPLIT pairs, [12] base-case point
+                  // pairs, [13] policy consultations, [14] policy fallbacks
 };
 
 struct FrontierLevel {
@@ -61,20 +63,24 @@ struct LevelOffsets {
 // scores (policy): per pair of the level, predicted log2 costs of DH, DL,
 // H2L, recurse.  feas (log_feas): per pair, 0x8000 | q_DH | q_DL << 4 |
 // q_H2L << 8 (smallest admitted orders, 0 = none) where bestMethod is
-// reached, else 0.  pcount[0..1] += policy consultations, fallbacks.
+// reached, else 0.
 hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
-                         SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
-                         const float4* scores, int16_t* feas, unsigned long long* pcount, hipStream_t s);
+                         SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s);
 
 hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, size_t temp_bytes,
                        hipStream_t s);
 size_t scan_counts_temp_bytes(int S);
 
+// Also adds the level's decision counters: hcount[h * 6 + code] (pairs per
+// bandwidth and code) and ev[0], ev[2], ev[3] (base-case point pairs, policy
+// consultations, fallbacks), from the inclusive scan at the ends of each run
+// of equal bandwidths, a few atomics per bandwidth.
 hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt,
                        const int32_t* qleft, const int32_t* rleft, const int8_t* code,
                        const int8_t* porder, const SegCount* cnt, const SegCount* incl,
-                       const WorkLists& wl, LevelOffsets base, hipStream_t s);
+                       const WorkLists& wl, LevelOffsets base, unsigned long long* hcount,
+                       unsigned long long* ev, hipStream_t s);
 
 }  // namespace gs

@@ -113,14 +113,17 @@ __device__ __forceinline__ double rl(double v, int j) {
 }
 
 // Smallest double a with fl(a / W) >= m (W > 0): correctly rounded division is
-// monotone, so fl(a / W) >= m exactly when a >= astar.  -INFINITY if the search
-// does not settle within a few units in the last place (the caller then
-// divides), +INFINITY for m = +INFINITY.
+// monotone, so fl(a / W) >= m exactly when a >= astar.  m = +INFINITY (or NaN)
+// gives +INFINITY.  -INFINITY, which sends the caller to the division itself,
+// for m below the smallest normal double (there the quotient's rounding to
+// zero or to a subnormal makes the threshold depend on W's last bits) and when
+// the search does not settle within a few units in the last place.
 __device__ double division_threshold(double m, double W) {
   if (!(m < INFINITY)) return INFINITY;
+  if (!(m >= 2.2250738585072014e-308)) return -INFINITY;
   double a = m * W;
   if (a / W >= m) {
-    for (int it = 0; it < 64; ++it) {
+    for (int it = 0; it < 4; ++it) {
       const double b = nextafter(a, -INFINITY);
       if (b / W >= m)
         a = b;
@@ -128,7 +131,7 @@ __device__ double division_threshold(double m, double W) {
         return a;
     }
   } else {
-    for (int it = 0; it < 64; ++it) {
+    for (int it = 0; it < 4; ++it) {
       a = nextafter(a, INFINITY);
       if (a / W >= m) return a;
     }
@@ -163,12 +166,18 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 // "(eps (W_R + t)) L >= astar" (see division_threshold).
 //
 // The token rule (Figures 6-7) then walks the pairs in order with the whole
-// wave in lockstep, reading pair j's values from lane j by register broadcast;
-// the per-method order search runs on lane j itself.  The lower bound L, the
-// finite-difference sum Gest_Q and Lpush_Q are summed in pair order the same
-// way; counters are wave reductions.  Every expression and its operation
-// order is that of the single-threaded formulation, so the decisions and sums
-// are identical to it.
+// wave in lockstep, reading pair j's values from lane j by register broadcast.
+// A pair takes one of two paths.  The short one covers the finite-difference
+// prune and every pair whose maxerr stays below the threshold at which a
+// series method can be chosen (DIRECT: base case or split): a comparison with
+// the token, maxerr's numerator, one comparison with the precomputed
+// threshold and the token update, with the pair's code kept as a bit of a
+// wave-uniform mask.  The long one, taken only above the threshold, runs the
+// order search of bestMethod on lane j itself.  Gest_Q and Lpush_Q are summed
+// in pair order inside the same walk (adding +0.0 for a pair that does not
+// contribute, exact for these non-negative sums); counters come from the
+// masks.  Every expression and its operation order is that of the
+// single-threaded formulation, so the decisions and sums are identical to it.
 template <int P>
 __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, TreeView qt,
                                                     TreeView rt, const double* __restrict__ inv2h2,
@@ -178,11 +187,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
                                                     int8_t* __restrict__ p_out,
                                                     double* __restrict__ Gest,
                                                     SegCount* __restrict__ cnt,
-                                                    unsigned long long* __restrict__ hcount,
-                                                    unsigned long long* __restrict__ base_evals,
                                                     const float4* __restrict__ scores,
-                                                    int16_t* __restrict__ feas_out,
-                                                    unsigned long long* __restrict__ pcount) {
+                                                    int16_t* __restrict__ feas_out) {
   constexpr double kSqrt2 = 1.4142135623730951;
   const int s = blockIdx.x;
   if (s >= S) return;
@@ -199,6 +205,10 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   const double Wtot = rt.W[0];  // total reference weight (the root's)
   const int64_t NQ = qt.count[Q];
   const double rQ = qt.rinf[Q] * ih;
+  __shared__ double4 sh_pair[64];  // need(E_FD), W_R, series threshold, FD value
+  __shared__ double sh_lterm[64];  // W_R K(dmax)
+  double* gest_at = Gest + (int64_t)h * nQ + Q;
+  const double gest_in = *gest_at;
 
   // Lower bound L over Q, summed in pair order.  The first 64 pairs' box
   // distances and K(dmax) stay in registers for the decision pass.
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
 
   double t = cur.T[s];
   double Lp = cur.Lp[s];
-  double gest = 0.0;
+  double gest = gest_in;
   bool any_fd = false;
   int nFD = 0, nDH = 0, nDL = 0, nH2L = 0, nBASE = 0, nSPLIT = 0, nchild = 0;
   int ncalls = 0, nfall = 0;
@@ -237,9 +247,10 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   // When logging, every pair that reaches bestMethod needs its admitted
   // orders: no DIRECT shortcut.
   const bool all_orders = c.log_feas != 0;
+  const bool learned = c.use_fmm && c.policy;
   for (int b0 = 0; b0 < len; b0 += 64) {
     const int n = len - b0 < 64 ? len - b0 : 64;
-    double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY;
+    double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY, thr = INFINITY;
     int NR = 0, rleaf = 0, Rid = 0;
     int kstar = 0;  // learned policy: cheapest predicted action (3 = recurse)
     double pm0[P], pm1[P], pm2[P];
@@ -309,56 +320,89 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
         }
         astar = all_orders ? -INFINITY : division_threshold(mstar, Wtot);
+        thr = astar;
+        if (learned) {
+          // the preferred series method is admitted at some order exactly
+          // when maxerr reaches its smallest bound; recursing never needs
+          // the order search
+          if (kstar == 3) {
+            thr = INFINITY;
+          } else {
+            const double mk = kstar == 0 ? pm0[P - 1] : kstar == 1 ? pm1[P - 1] : pm2[P - 1];
+            const double ak = division_threshold(mk, Wtot);
+            thr = ak < astar ? ak : astar;
+          }
+        }
       }
     }
+    const unsigned long long base_ok = qleaf ? __ballot(lane < n && rleaf) : 0ull;
+    const unsigned long long kfall = learned ? __ballot(lane < n && kstar != 3) : 0ull;
+    // Pair values the walk reads, staged in LDS and read back as broadcasts
+    // one pair ahead of their use.
+    __syncthreads();
+    if (lane < n) {
+      sh_pair[lane] = make_double4(nd, WR, thr, fdval);
+      sh_lterm[lane] = lterm;
+    }
+    __syncthreads();
     // The token rule, pair by pair, the wave in lockstep.
+    unsigned long long m_fd = 0, m_slow = 0, m_base = 0;
     int my_code = -1, my_p = 0, my_feas = 0;
+    double4 nxt = sh_pair[0];
+    double nxt_lt = sh_lterm[0];
     for (int j = 0; j < n; ++j) {
-      const double ndj = rl(nd, j);
-      int cd;
-      int p = 0;
-      if (ndj <= (c.use_tokens ? t : 0.0)) {
-        if (c.use_tokens) t = t - ndj;
-        cd = FD;
+      const unsigned long long bit = 1ull << j;
+      const double ndj = nxt.x, WRj = nxt.y, thrj = nxt.z, fdj = nxt.w, ltj = nxt_lt;
+      nxt = sh_pair[(j + 1) & 63];
+      nxt_lt = sh_lterm[(j + 1) & 63];
+      const double tt = c.use_tokens ? t : 0.0;
+      const double a = (c.eps_alg * (WRj + tt)) * L;
+      const bool fd = ndj <= tt;
+      bool is_fd = fd, is_split = false;
+      if (fd || !(a >= thrj)) {
+        // finite difference, or DIRECT below the series threshold (and the
+        // learned policy's recursion): base case if both nodes are leaves,
+        // else split
+        const bool base = !fd && (base_ok & bit);
+        if (c.use_tokens) t = fd ? t - ndj : (base ? t + WRj : t);
+        m_fd |= fd ? bit : 0ull;
+        m_base |= base ? bit : 0ull;
+        is_split = !fd && !base;
       } else {
-        cd = -1;
-        const double WRj = rl(WR, j);
-        const double tt = c.use_tokens ? t : 0.0;
-        const double a = (c.eps_alg * (WRj + tt)) * L;
+        m_slow |= bit;
+        int cd = -1;
+        int p = 0;
         double Esel = 0.0;
-        bool rule = c.use_fmm != 0;
-        if (c.use_fmm && c.policy) {
+        bool rule = true;
+        if (learned) {
           // The learned policy: its cheapest predicted action, a series
           // method only at an order its bound admits, else the rule decides.
           const int kj = rl(kstar, j);
-          ++ncalls;
+          const double maxerr = a / Wtot;
+          if (kj == 3) rule = false;
+          int qk = 0;
+          double ek = 0.0;
+          if (lane == j) {
+            int ak = 0;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+              const double e = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
+              ak += e > maxerr ? 1 : 0;
+            }
+            qk = ak < P ? ak + 1 : 0;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp)
+              if (pp + 1 == qk) ek = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
+          }
+          qk = rl(qk, j);
           if (kj == 3) {
+          } else if (qk) {
+            cd = kj == 0 ? DH : kj == 1 ? DL : H2L;
+            p = qk;
+            Esel = rl(ek, j);
             rule = false;
           } else {
-            const double maxerr = a / Wtot;
-            int qk = 0;
-            double ek = 0.0;
-            if (lane == j) {
-              int ak = 0;
-#pragma unroll
-              for (int pp = 0; pp < P; ++pp) {
-                const double e = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
-                ak += e > maxerr ? 1 : 0;
-              }
-              qk = ak < P ? ak + 1 : 0;
-#pragma unroll
-              for (int pp = 0; pp < P; ++pp)
-                if (pp + 1 == qk) ek = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
-            }
-            qk = rl(qk, j);
-            if (qk) {
-              cd = kj == 0 ? DH : kj == 1 ? DL : H2L;
-              p = qk;
-              Esel = rl(ek, j);
-              rule = false;
-            } else {
-              ++nfall;
-            }
+            ++nfall;
           }
         }
         if (rule && (all_orders || a >= rl(astar, j))) {
@@ -439,49 +483,58 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
         }
         if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, Wtot, c.eps_alg);
         if (cd < 0) {
-          if (qleaf && rl(rleaf, j)) {
+          if (base_ok & bit) {
             if (c.use_tokens) t = t + WRj;
             cd = BASE;
           } else {
             cd = SPLIT;
+            is_split = true;
           }
         }
-      }
-      if (lane == j) {
-        my_code = cd;
-        my_p = p;
-      }
-    }
-    // Order-dependent sums of the chunk, in pair order.
-    for (int j = 0; j < n; ++j) {
-      const int cj = rl(my_code, j);
-      if (cj == FD) {
-        if (!any_fd) {
-          gest = Gest[(int64_t)h * nQ + Q];
-          any_fd = true;
+        nDH += cd == DH;
+        nDL += cd == DL;
+        nH2L += cd == H2L;
+        nBASE += cd == BASE;
+        nSPLIT += cd == SPLIT;
+        if (lane == j) {
+          my_code = cd;
+          my_p = p;
         }
-        gest = gest + rl(fdval, j);
       }
-      if (cj != SPLIT) Lp = Lp + rl(lterm, j);
+      // Order-dependent sums, in pair order.
+      gest = gest + (is_fd ? fdj : 0.0);
+      Lp = Lp + (is_split ? 0.0 : ltj);
+      any_fd = any_fd || is_fd;
     }
-    // Counters.
+    const unsigned long long bitl = 1ull << lane;
+    int code;
+    if (m_fd & bitl) code = FD;
+    else if (m_slow & bitl) code = my_code;
+    else if (m_base & bitl) code = BASE;
+    else code = SPLIT;
+    const unsigned long long live = n == 64 ? ~0ull : (1ull << n) - 1;
+    const unsigned long long m_fast = live & ~(m_fd | m_slow);
+    nFD += __popcll(m_fd);
+    nBASE += __popcll(m_base);
+    nSPLIT += __popcll(m_fast & ~m_base);
+    if (learned) {
+      ncalls += __popcll(live & ~m_fd);
+      nfall += __popcll(m_fast & kfall);
+    }
     const bool act = lane < n;
-    nFD += wave_sum_int(act && my_code == FD);
-    nDH += wave_sum_int(act && my_code == DH);
-    nDL += wave_sum_int(act && my_code == DL);
-    nH2L += wave_sum_int(act && my_code == H2L);
-    nBASE += wave_sum_int(act && my_code == BASE);
-    nSPLIT += wave_sum_int(act && my_code == SPLIT);
-    nchild += wave_sum_int(act && my_code == SPLIT ? (rleaf ? 1 : 2) : 0);
-    bevals += wave_sum_ll(act && my_code == BASE ? (long long)NQ * NR : 0ll);
+    const unsigned long long m_split = __ballot(act && code == SPLIT);
+    const unsigned long long m_rleaf = __ballot(act && rleaf);
+    nchild += __popcll(m_split & m_rleaf) + 2 * __popcll(m_split & ~m_rleaf);
+    if (__ballot(act && code == BASE))
+      bevals += wave_sum_ll(act && code == BASE ? (long long)NQ * NR : 0ll);
     if (act) {
-      code_out[off + b0 + lane] = (int8_t)my_code;
-      p_out[off + b0 + lane] = (int8_t)my_p;
-      if (feas_out) feas_out[off + b0 + lane] = (int16_t)my_feas;
+      code_out[off + b0 + lane] = (int8_t)code;
+      p_out[off + b0 + lane] = (int8_t)((m_slow & bitl) ? my_p : 0);
+      if (feas_out) feas_out[off + b0 + lane] = (int16_t)((m_slow & bitl) ? my_feas : 0);
     }
   }
   if (lane != 0) return;
-  if (any_fd) Gest[(int64_t)h * nQ + Q] = gest;
+  if (any_fd) *gest_at = gest;
   cur.T[s] = t;
   cur.Lp[s] = Lp;
   SegCount sc;
@@ -495,23 +548,19 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   sc.v[7] = nDL > 0;
   sc.v[8] = nH2L > 0;
   sc.v[9] = nBASE > 0;
+  sc.v[10] = nFD;
+  sc.v[11] = nSPLIT;
+  sc.v[12] = bevals;
+  sc.v[13] = ncalls;
+  sc.v[14] = nfall;
+  sc.v[15] = 0;
   cnt[s] = sc;
-  unsigned long long* hc = hcount + h * 6;
-  if (nFD) atomicAdd(&hc[FD], (unsigned long long)nFD);
-  if (nDH) atomicAdd(&hc[DH], (unsigned long long)nDH);
-  if (nDL) atomicAdd(&hc[DL], (unsigned long long)nDL);
-  if (nH2L) atomicAdd(&hc[H2L], (unsigned long long)nH2L);
-  if (nBASE) atomicAdd(&hc[BASE], (unsigned long long)nBASE);
-  if (nSPLIT) atomicAdd(&hc[SPLIT], (unsigned long long)nSPLIT);
-  if (bevals) atomicAdd(base_evals, (unsigned long long)bevals);
-  if (ncalls) atomicAdd(&pcount[0], (unsigned long long)ncalls);
-  if (nfall) atomicAdd(&pcount[1], (unsigned long long)nfall);
 }
 
 struct SegCountPlus {
   __device__ __host__ SegCount operator()(const SegCount& a, const SegCount& b) const {
     SegCount r;
-    for (int k = 0; k < 10; ++k) r.v[k] = a.v[k] + b.v[k];
+    for (int k = 0; k < 16; ++k) r.v[k] = a.v[k] + b.v[k];
     return r;
   }
 };
@@ -538,7 +587,9 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
                                                   const int8_t* __restrict__ porder,
                                                   const SegCount* __restrict__ cnt,
                                                   const SegCount* __restrict__ incl, WorkLists wl,
-                                                  LevelOffsets base) {
+                                                  LevelOffsets base,
+                                                  unsigned long long* __restrict__ hcount,
+                                                  unsigned long long* __restrict__ ev) {
   const int s = blockIdx.x;
   if (s >= S) return;
   const int lane = threadIdx.x;
@@ -552,6 +603,25 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
   const int off = cur.off[s];
   const int len = cur.len[s];
   const bool qleaf = qleft[Q] < 0;
+  if (lane == 0) {
+    // Counters of the bandwidth run this segment ends (+ its inclusive sums)
+    // or starts (- the sums before it): a run's net is its own total.
+    const int sl[6] = {10, 2, 3, 4, 5, 11};  // FD, DH, DL, H2L, BASE, SPLIT
+    unsigned long long* hc = hcount + h * 6;
+    if (s == S - 1 || cur.h[s + 1] != h)
+      for (int k = 0; k < 6; ++k)
+        if (in.v[sl[k]]) atomicAdd(&hc[k], (unsigned long long)in.v[sl[k]]);
+    if (s > 0 && cur.h[s - 1] != h) {
+      const SegCount before = incl[s - 1];
+      for (int k = 0; k < 6; ++k)
+        if (before.v[sl[k]]) atomicAdd(&hc[k], 0ull - (unsigned long long)before.v[sl[k]]);
+    }
+    if (s == S - 1) {
+      if (in.v[12]) atomicAdd(&ev[0], (unsigned long long)in.v[12]);
+      if (in.v[13]) atomicAdd(&ev[2], (unsigned long long)in.v[13]);
+      if (in.v[14]) atomicAdd(&ev[3], (unsigned long long)in.v[14]);
+    }
+  }
   const int nsegs = (int)own.v[1];
   const int nch = nsegs ? (int)(own.v[0] / nsegs) : 0;
   const int pb = ex[0];
@@ -603,14 +673,11 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
 hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
-                         SegCount* cnt, unsigned long long* hcount, unsigned long long* base_evals,
-                         const float4* scores, int16_t* feas, unsigned long long* pcount,
-                         hipStream_t s) {
+                         SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s) {
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \
     hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)S), dim3(64), 0, s, S, cur, qt, rt,   \
-                       inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, hcount,           \
-                       base_evals, scores, feas, pcount);                                      \
+                       inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, scores, feas);    \
     break;
   switch (c.P) {
     GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)
@@ -625,7 +692,7 @@ hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, co
 size_t scan_counts_temp_bytes(int S) {
   size_t bytes = 0;
   SegCount zero;
-  for (int k = 0; k < 10; ++k) zero.v[k] = 0;
+  for (int k = 0; k < 16; ++k) zero.v[k] = 0;
   (void)rocprim::inclusive_scan((void*)nullptr, bytes, (const SegCount*)nullptr, (SegCount*)nullptr,
                           (size_t)S, SegCountPlus());
   (void)zero;
@@ -641,9 +708,10 @@ hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, s
 hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt,
                        const int32_t* qleft, const int32_t* rleft, const int8_t* code,
                        const int8_t* porder, const SegCount* cnt, const SegCount* incl,
-                       const WorkLists& wl, LevelOffsets base, hipStream_t s) {
+                       const WorkLists& wl, LevelOffsets base, unsigned long long* hcount,
+                       unsigned long long* ev, hipStream_t s) {
   hipLaunchKernelGGL(emit_kernel, dim3((unsigned)S), dim3(64), 0, s, S, cur, nxt, qleft, rleft,
-                     code, porder, cnt, incl, wl, base);
+                     code, porder, cnt, incl, wl, base, hcount, ev);
   return hipGetLastError();
 }
 

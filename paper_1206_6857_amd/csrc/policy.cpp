@@ -170,7 +170,7 @@ void policy_calibrate_costs(gs_ctx_base* ctx, int D) {
   const HostTree& qt = ctx->host_tree[1];
   const std::vector<int32_t>& tr = ctx->trace;
   const int64_t n = (int64_t)tr.size() / 6;
-  if (n == 0 || !qt.valid || !rt.valid) return;
+  if (ps.costs_pinned || n == 0 || !qt.valid || !rt.valid) return;
   double u[5] = {(double)n, 0.0, 0.0, 0.0, 0.0};  // pairs, DH, DL, H2L, base
   for (int64_t i = 0; i < n; ++i) {
     const int code = tr[6 * i + 4], p = tr[6 * i + 5];

@@ -231,8 +231,10 @@ def _modeled_cost(trace, qc, rc, D, cm):
 
 def test_learned_policy_gain_on_held_out_data():
     """Trained on one draw, evaluated on another draw of the same
-    distribution: the learned policy's decisions cost less under the measured
-    cost model than the paper's rule, and still meet Theorem 2."""
+    distribution: the learned policy's decisions cost less under the cost
+    model it was trained for than the paper's rule, and still meet Theorem 2.
+    The model is pinned to the library's defaults (measured on one MI355X),
+    so that training targets and costs do not vary with this run's timings."""
     banner("learned policy gain")
     import time
     import paper_1206_6857_amd as g
@@ -240,8 +242,9 @@ def test_learned_policy_gain_on_held_out_data():
     D, N = 3, 20000
     hs = np.logspace(-3, 0, 10)
     r, w, _ = mixture((51, D), N, D, 8, (0.01, 0.1))
+    cm = c.policy_cost_model(**c.policy_cost_model())
     c.gauss_sum(r, r, w, hs, 0.01, log_pairs=1, log_explore=0.3)
-    cm = c.policy_cost_model()
+    assert c.policy_cost_model() == cm
     rec, _ = c.policy_log()
     c.policy_train(rec, steps=1500, batch=4096, seed=2)
     r2, w2, _ = mixture((52, D), N, D, 8, (0.01, 0.1))
