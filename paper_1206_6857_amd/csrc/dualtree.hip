@@ -597,20 +597,26 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     hipLaunchKernelGGL(init_level0_kernel, dim3((unsigned)ceil_div(nh, 64)), dim3(64), 0, st, hc0, nh, cur);
     DT_HIP(hipGetLastError());
     WorkLists wl;
-    int64_t used_ent[4] = {0, 0, 0, 0}, used_grp[4] = {0, 0, 0, 0};
-    auto grow_lists = [&](const int64_t* add_ent, const int64_t* add_grp) -> gs_status {
+    int64_t used_ent[4] = {0, 0, 0, 0}, used_grp[4] = {0, 0, 0, 0}, used_slc[2] = {0, 0};
+    auto grow_lists = [&](const int64_t* add_ent, const int64_t* add_grp, const int64_t* add_slc) -> gs_status {
       for (int x = 0; x < 4; ++x) {
         wl.ent[x] = GROW(int32_t, std::string("wl_ent_") + tname[x], used_ent[x], used_ent[x] + add_ent[x]);
         wl.grp[x] = GROW(int4, std::string("wl_grp_") + tname[x], used_grp[x], used_grp[x] + add_grp[x]);
       }
+      wl.dh_first = GROW(int32_t, "wl_dh_first", used_grp[0], used_grp[0] + add_grp[0]);
+      wl.dl_first = GROW(int2, "wl_dl_first", used_grp[1], used_grp[1] + add_grp[1]);
+      wl.dl_cpre = GROW(int32_t, "wl_dl_cpre", used_ent[1], used_ent[1] + add_ent[1]);
+      wl.dh_slice = GROW(int4, "wl_dh_slice", used_slc[0], used_slc[0] + add_slc[0]);
+      wl.dl_slice = GROW(int4, "wl_dl_slice", used_slc[1], used_slc[1] + add_slc[1]);
       return GS_OK;
     };
     {
-      const int64_t e0[4] = {1024, 1024, 1024, 1024}, g0[4] = {256, 256, 256, 256};
-      CHUNK_ALLOC(grow_lists(e0, g0));
+      const int64_t e0[4] = {1024, 1024, 1024, 1024}, g0[4] = {256, 256, 256, 256}, s0[2] = {256, 256};
+      CHUNK_ALLOC(grow_lists(e0, g0, s0));
     }
     int level = 0, which = 0;
     std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
+    std::vector<int64_t> dh_slice_begin;  // first DH slice of each traversal level
     std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
     std::vector<int8_t> tr_code, tr_p;
     std::vector<float> tr_feat;
@@ -691,25 +697,29 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       for (int x = 0; x < 4; ++x)
         too_big = too_big || used_ent[x] + tot.v[2 + x] > kMaxFrontier ||
                   used_grp[x] + tot.v[6 + x] > kMaxFrontier;
+      for (int x = 0; x < 2; ++x) too_big = too_big || used_slc[x] + tot.v[15 + x] > kMaxFrontier;
       if (too_big) return overflow();
       dh_level_begin.push_back(used_grp[0]);
-      CHUNK_ALLOC(grow_lists(tot.v + 2, tot.v + 6));
+      dh_slice_begin.push_back(used_slc[0]);
+      CHUNK_ALLOC(grow_lists(tot.v + 2, tot.v + 6, tot.v + 15));
       LevelOffsets lo;
       for (int x = 0; x < 4; ++x) {
         lo.ent[x] = (int32_t)used_ent[x];
         lo.grp[x] = (int32_t)used_grp[x];
       }
+      for (int x = 0; x < 2; ++x) lo.slc[x] = (int32_t)used_slc[x];
       CHUNK_ALLOC(level_bufs(1 - which, nseg2, npair2, nxt));
       {
         KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
-        DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, wl, lo,
-                           hcount, chunk_ev, st));
+        DT_HIP(launch_emit((int)nseg, cur, nxt, qt.left, rt.left, code, pord, cnt, incl, rt.count, wl,
+                           lo, hcount, chunk_ev, st));
         kt.stop(st, 1);
       }
       for (int x = 0; x < 4; ++x) {
         used_ent[x] += tot.v[2 + x];
         used_grp[x] += tot.v[6 + x];
       }
+      for (int x = 0; x < 2; ++x) used_slc[x] += tot.v[15 + x];
       std::swap(cur, nxt);
       which = 1 - which;
       nseg = nseg2;
@@ -720,6 +730,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     t_trav += tb0 - ta;
     max_level = std::max(max_level, level);
     dh_level_begin.push_back(used_grp[0]);
+    dh_slice_begin.push_back(used_slc[0]);
 
     // 4. Work.  Every scratch buffer is taken before the first work kernel,
     // so a failed allocation can still be retried.
@@ -729,7 +740,25 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     size_t gsort_bytes = 0;
     BaseFusedArgs ba;
     const bool any_base = used_grp[3] > 0;
+    const bool fast = use_fmm && series_fast_available(D, P);
+    double* dh_part = nullptr;
+    double* dl_part = nullptr;
+    int32_t* dl_part_p = nullptr;
     CHUNK_ALLOC(([&]() -> gs_status {
+      if (fast) {
+        // partial sums of the sliced DH and DL kernels
+        int64_t dh_need = 0;
+        for (size_t lv = 0; lv + 1 < dh_slice_begin.size(); ++lv) {
+          const int depth_max = lv < qt.level_max.size() ? qt.level_max[lv] : 0;
+          const int64_t cy = ceil_div(std::max(depth_max, opt.leaf_size), 64);
+          dh_need = std::max(dh_need, (dh_slice_begin[lv + 1] - dh_slice_begin[lv]) * cy * 64);
+        }
+        if (dh_need) dh_part = BUF(double, "dh_part", dh_need);
+        if (used_slc[1]) {
+          dl_part = BUF(double, "dl_part", used_slc[1] * series_terms(D, P));
+          dl_part_p = BUF(int32_t, "dl_part_p", used_slc[1]);
+        }
+      }
       for (int x = 1; x < 3; ++x) {
         const int n = (int)used_grp[x];
         sg[x].n = n;
@@ -827,14 +856,15 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     }
     if (use_fmm) {
       KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
-      const bool fast = series_fast_available(D, P);
       {
         KernelTimer kd(ctx, ctx->kernel_timing, GS_K_DL, st);
         if (fast)
-          DT_HIP(launch_dl_fast(D, P, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
+          DT_HIP(launch_dl_fast(D, P, sg[1], wl.dl_slice, (int)used_slc[1], wl.dl_first, wl.dl_cpre,
+                                wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, dl_part,
+                                dl_part_p, st));
         else
           DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-        kd.stop(st, 1);
+        kd.stop(st, fast ? 2 : 1);
       }
       {
         KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, st);
@@ -842,21 +872,28 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         kh.stop(st, 1);
       }
       KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, st);
+      int dh_launches = 0;
       for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
         const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
         // query nodes of traversal level lv: nodes of depth lv, or leaves of
         // earlier levels (at most leaf_size points)
         const int depth_max = lv < qt.level_max.size() ? qt.level_max[lv] : 0;
         const int max_q = std::max(depth_max, opt.leaf_size);
-        if (fast)
-          DT_HIP(launch_dh_fast(D, P, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
-                                Mom, d_sc, (int)Mq, gdh, st));
-        else
+        const int64_t sb = dh_slice_begin[lv], se = dh_slice_begin[lv + 1];
+        if (ge == gb) continue;
+        if (fast) {
+          DT_HIP(launch_dh_fast(D, P, wl.dh_slice + sb, (int)(se - sb), (int)sb, wl.grp[0], wl.dh_first,
+                                (int)gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm, Mom, d_sc,
+                                (int)Mq, gdh, dh_part, st));
+          dh_launches += se - sb > ge - gb ? 2 : 1;
+        } else {
           DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
                                  Mom, d_sc, (int)Mq, gdh, st));
+          dh_launches += 1;
+        }
       }
-      kdh.stop(st, (int)dh_level_begin.size() - 1);
-      kt.stop(st, 2 + (int)dh_level_begin.size() - 1);
+      kdh.stop(st, dh_launches);
+      kt.stop(st, (fast ? 3 : 2) + dh_launches);
     }
     if (any_base) {
       if (!rec_ready) {

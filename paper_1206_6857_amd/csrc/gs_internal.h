@@ -16,6 +16,12 @@ constexpr int kMaxPlimit = 10;
 constexpr int kMaxTerms = 286;      // C(D+p-1, D) bound enforced by the host
 constexpr int kMaxHBlock = 16;      // bandwidths fused per exhaustive pass
 
+// Slices of the series work lists, so that one long group spreads over many
+// waves: a DH group's entries in runs of kDHSliceEntries, a DL group's point
+// chunks (64 reference points, entry after entry) in runs of kDLSliceChunks.
+constexpr int kDHSliceEntries = 8;
+constexpr int kDLSliceChunks = 16;
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------- staging

@@ -66,14 +66,31 @@ hipError_t launch_leaf_eval(const SeriesTables& T, const NodeView& qt, const int
 // Compile-time specialisations of DH and DL for the order-limit table's
 // (D, P) pairs; launch_*_fast return hipErrorInvalidValue for other pairs.
 bool series_fast_available(int D, int P);
-// max_q: an upper bound on the point count of the groups' query nodes.
-hipError_t launch_dh_fast(int D, int P, const int4* grp, int ng, int max_q, const int32_t* ent,
+//
+// DH of one traversal level: slices[0..ns) {group, first entry, entries,
+// slice of the group} of its groups grp[g0..g0+ng), first[g] = the global
+// index of group g's first slice, slice0 = the global index of slices[0].
+// max_q: an upper bound on the point count of the groups' query nodes.  A
+// group of one slice adds into gdh directly; the slices of a longer group
+// write part[slice][chunk][64] (ns * ceil(max_q / 64) * 64 doubles), summed
+// in slice order by a second kernel.
+hipError_t launch_dh_fast(int D, int P, const int4* slices, int ns, int slice0, const int4* grp,
+                          const int32_t* first, int g0, int ng, int max_q, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xq_perm,
-                          const double* M, const double* sc, int Mq, double* gdh, hipStream_t s);
-hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+                          const double* M, const double* sc, int Mq, double* gdh, double* part,
+                          hipStream_t s);
+// DL of the whole traversal: slices[0..ns) {group, first chunk, end chunk}
+// over each group's entries (cpre[entry] = chunks of the group's earlier
+// entries), one partial coefficient vector per slice (part: ns * C doubles,
+// part_p: ns orders), then per (h, Q) run of the sorted groups g the sum over
+// its groups' slices (first[group] = {first slice, slices}) in order into lco.
+hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slices, int ns,
+                          const int2* first, const int32_t* cpre, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xr_perm,
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
-                          hipStream_t s);
+                          double* part, int32_t* part_p, hipStream_t s);
+// Size of the DL partial coefficient vectors (C(D+P-1, D)).
+int series_terms(int D, int P);
 
 // Base cases (DITOBase), fused over blocks of 8 bandwidths.
 int base_record_stride(int D);

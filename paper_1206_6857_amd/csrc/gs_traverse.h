@@ -30,10 +30,11 @@ struct DecideConst {
 
 // Counters of one frontier segment (one (bandwidth, query node) pair list).
 struct SegCount {
-  int64_t v[16];  // [0] next-level pairs, [1] next-level segments,
+  int64_t v[18];  // [0] next-level pairs, [1] next-level segments,
                   // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags,
                   // [10] FD pairs, [11] SPLIT pairs, [12] base-case point
-                  // pairs, [13] policy consultations, [14] policy fallbacks
+                  // pairs, [13] policy consultations, [14] policy fallbacks,
+                  // [15] DH slices, [16] DL slices, [17] unused
 };
 
 struct FrontierLevel {
@@ -50,14 +51,25 @@ struct TreeView {
 };
 
 // Work list entries: (R << 4) | p; groups: {h, Q, first entry, entries}.
+// Slices: DH {group, first entry, entries, slice of the group}, with
+// dh_first[group] = its first slice; DL {group, first chunk, end chunk, 0},
+// chunks counted over the group's entries in order, with dl_first[group] =
+// {first slice, slices} and dl_cpre[entry] = chunks of the group's earlier
+// entries.  Group and slice indices are global over the traversal.
 struct WorkLists {
   int32_t* ent[4];
   int4* grp[4];
+  int4* dh_slice;
+  int32_t* dh_first;
+  int4* dl_slice;
+  int2* dl_first;
+  int32_t* dl_cpre;
 };
 
 struct LevelOffsets {
   int32_t ent[4];
   int32_t grp[4];
+  int32_t slc[2];  // DH, DL slices
 };
 
 // scores (policy): per pair of the level, predicted log2 costs of DH, DL,
@@ -80,7 +92,7 @@ size_t scan_counts_temp_bytes(int S);
 hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt,
                        const int32_t* qleft, const int32_t* rleft, const int8_t* code,
                        const int8_t* porder, const SegCount* cnt, const SegCount* incl,
-                       const WorkLists& wl, LevelOffsets base, unsigned long long* hcount,
-                       unsigned long long* ev, hipStream_t s);
+                       const int32_t* rcount, const WorkLists& wl, LevelOffsets base,
+                       unsigned long long* hcount, unsigned long long* ev, hipStream_t s);
 
 }  // namespace gs

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   bool any_fd = false;
   int nFD = 0, nDH = 0, nDL = 0, nH2L = 0, nBASE = 0, nSPLIT = 0, nchild = 0;
   int ncalls = 0, nfall = 0;
-  long long bevals = 0;
+  long long bevals = 0, dlchunks = 0;
   // When logging, every pair that reaches bestMethod needs its admitted
   // orders: no DIRECT shortcut.
   const bool all_orders = c.log_feas != 0;
@@ -527,6 +527,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
     nchild += __popcll(m_split & m_rleaf) + 2 * __popcll(m_split & ~m_rleaf);
     if (__ballot(act && code == BASE))
       bevals += wave_sum_ll(act && code == BASE ? (long long)NQ * NR : 0ll);
+    if (__ballot(act && code == DL)) dlchunks += wave_sum_ll(act && code == DL ? (NR + 63) / 64 : 0);
     if (act) {
       code_out[off + b0 + lane] = (int8_t)code;
       p_out[off + b0 + lane] = (int8_t)((m_slow & bitl) ? my_p : 0);
@@ -553,14 +554,16 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   sc.v[12] = bevals;
   sc.v[13] = ncalls;
   sc.v[14] = nfall;
-  sc.v[15] = 0;
+  sc.v[15] = (nDH + kDHSliceEntries - 1) / kDHSliceEntries;
+  sc.v[16] = (dlchunks + kDLSliceChunks - 1) / kDLSliceChunks;
+  sc.v[17] = 0;
   cnt[s] = sc;
 }
 
 struct SegCountPlus {
   __device__ __host__ SegCount operator()(const SegCount& a, const SegCount& b) const {
     SegCount r;
-    for (int k = 0; k < 16; ++k) r.v[k] = a.v[k] + b.v[k];
+    for (int k = 0; k < 18; ++k) r.v[k] = a.v[k] + b.v[k];
     return r;
   }
 };
@@ -586,7 +589,8 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
                                                   const int8_t* __restrict__ code,
                                                   const int8_t* __restrict__ porder,
                                                   const SegCount* __restrict__ cnt,
-                                                  const SegCount* __restrict__ incl, WorkLists wl,
+                                                  const SegCount* __restrict__ incl,
+                                                  const int32_t* __restrict__ rcount, WorkLists wl,
                                                   LevelOffsets base,
                                                   unsigned long long* __restrict__ hcount,
                                                   unsigned long long* __restrict__ ev) {
@@ -640,6 +644,18 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
     if (lane == 0 && own.v[2 + x] > 0)
       wl.grp[x][base.grp[x] + ex[6 + x]] = make_int4(h, Q, eb[x], (int)own.v[2 + x]);
   }
+  if (own.v[2] > 0) {
+    // DH slices: runs of kDHSliceEntries entries
+    const int g = base.grp[0] + ex[6];
+    const int sb = base.slc[0] + (int)(in.v[15] - own.v[15]);
+    const int ne = (int)own.v[2], ns = (int)own.v[15];
+    for (int k = lane; k < ns; k += 64) {
+      const int e0 = k * kDHSliceEntries;
+      wl.dh_slice[sb + k] = make_int4(g, eb[0] + e0, min(kDHSliceEntries, ne - e0), k);
+    }
+    if (lane == 0) wl.dh_first[g] = sb;
+  }
+  int dl_run = 0;  // chunks of this segment's DL entries so far
   int kc = 0;
   for (int b0 = 0; b0 < len; b0 += 64) {
     const bool act = b0 + lane < len;
@@ -663,8 +679,24 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
       int tx;
       const int ep = wave_excl_scan(f, &tx);
       if (f) wl.ent[x][eb[x] + ep] = (R << 4) | porder[off + b0 + lane];
+      if (x == 1 && tx) {
+        const int ch = f ? (rcount[R] + 63) / 64 : 0;
+        int tch;
+        const int cp = wave_excl_scan(ch, &tch);
+        if (f) wl.dl_cpre[eb[1] + ep] = dl_run + cp;
+        dl_run += tch;
+      }
       eb[x] += tx;
     }
+  }
+  if (own.v[3] > 0) {
+    // DL slices: runs of kDLSliceChunks chunks over the entries in order
+    const int g = base.grp[1] + ex[7];
+    const int sb = base.slc[1] + (int)(in.v[16] - own.v[16]);
+    const int ns = (int)own.v[16];
+    for (int k = lane; k < ns; k += 64)
+      wl.dl_slice[sb + k] = make_int4(g, k * kDLSliceChunks, min(dl_run, (k + 1) * kDLSliceChunks), 0);
+    if (lane == 0) wl.dl_first[g] = make_int2(sb, ns);
   }
 }
 
@@ -692,7 +724,7 @@ hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, co
 size_t scan_counts_temp_bytes(int S) {
   size_t bytes = 0;
   SegCount zero;
-  for (int k = 0; k < 16; ++k) zero.v[k] = 0;
+  for (int k = 0; k < 18; ++k) zero.v[k] = 0;
   (void)rocprim::inclusive_scan((void*)nullptr, bytes, (const SegCount*)nullptr, (SegCount*)nullptr,
                           (size_t)S, SegCountPlus());
   (void)zero;
@@ -708,10 +740,10 @@ hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, s
 hipError_t launch_emit(int S, const FrontierLevel& cur, const FrontierLevel& nxt,
                        const int32_t* qleft, const int32_t* rleft, const int8_t* code,
                        const int8_t* porder, const SegCount* cnt, const SegCount* incl,
-                       const WorkLists& wl, LevelOffsets base, unsigned long long* hcount,
-                       unsigned long long* ev, hipStream_t s) {
+                       const int32_t* rcount, const WorkLists& wl, LevelOffsets base,
+                       unsigned long long* hcount, unsigned long long* ev, hipStream_t s) {
   hipLaunchKernelGGL(emit_kernel, dim3((unsigned)S), dim3(64), 0, s, S, cur, nxt, qleft, rleft,
-                     code, porder, cnt, incl, wl, base, hcount, ev);
+                     code, porder, cnt, incl, rcount, wl, base, hcount, ev);
   return hipGetLastError();
 }
 

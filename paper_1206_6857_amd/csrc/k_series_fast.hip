@@ -10,10 +10,13 @@
 // dimensions of a point.
 //
 //   DH:  gdh[h][q] += sum_{|a|<p} M_a s^{|a|} h_a((x_q - x_R) s)   (one wave per
-//        group of a traversal level, lanes over the points of Q)
+//        slice of up to 8 entries of a group of a traversal level and per 64
+//        points of Q, lanes over the points; the slices of a longer group
+//        summed in order by a second kernel)
 //   DL:  lco[h][Q][b] += sum_{r in R} w_r/b! h_b((x_r - x_Q) s)    (one wave per
-//        run of a (h, Q) key, lanes over the points of R, per-lane partial
-//        coefficients reduced across the wave once per run)
+//        slice of up to 16 chunks of 64 reference points, lanes over the
+//        points, per-lane partial coefficients reduced across the wave once
+//        per slice; then per (h, Q) run the slices summed in order)
 #include "gs_series.h"
 
 namespace gs {
@@ -89,18 +92,21 @@ __device__ __forceinline__ void hermite_polys(double t, double* H) {
   for (int k = 1; k + 1 < P; ++k) H[k + 1] = 2.0 * t * H[k] - 2.0 * k * H[k - 1];
 }
 
-// grid.x: groups (kWavesPerBlock per block), grid.y: 64-point chunks of Q.
+// grid.x: slices of the level (kWavesPerBlock per block), grid.y: 64-point
+// chunks of Q.
 template <int D, int P>
 __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
-    const int4* __restrict__ grp, int ng, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
-    const double* __restrict__ xq_perm, const double* __restrict__ M, const double* __restrict__ sc,
-    int Mq, double* __restrict__ gdh) {
+    const int4* __restrict__ slc, int ns, const int4* __restrict__ grp,
+    const int32_t* __restrict__ ent, NodeView qt, NodeView rt, const double* __restrict__ xq_perm,
+    const double* __restrict__ M, const double* __restrict__ sc, int Mq, double* __restrict__ gdh,
+    double* __restrict__ part) {
   constexpr MultiIndex<D, P> mi{};
   constexpr int C = MultiIndex<D, P>::C;
   const int lane = threadIdx.x % kW;
   const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
-  if (i >= ng) return;
-  const int4 gr = grp[i];
+  if (i >= ns) return;
+  const int4 sl = slc[i];
+  const int4 gr = grp[sl.x];
   const int h = gr.x, Q = gr.y;
   const int qb = qt.begin[Q], qn = qt.count[Q];
   const int base = blockIdx.y * kW;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = xq_perm[(int64_t)qpos * D + d];
   double acc = 0.0;
-  for (int e = gr.z; e < gr.z + gr.w; ++e) {
+  for (int e = sl.y; e < sl.y + sl.z; ++e) {
     const int R = ent[e] >> 4, p = ent[e] & 15;
     int nt = 0;
 #pragma unroll
@@ -145,69 +151,147 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
     }
     acc += v * exp(-tt);
   }
-  if (active) gdh[(int64_t)h * Mq + qpos] += acc;
+  if (!active) return;
+  if (gr.w <= kDHSliceEntries)
+    gdh[(int64_t)h * Mq + qpos] += acc;
+  else
+    part[((int64_t)i * gridDim.y + blockIdx.y) * kW + lane] = acc;
 }
 
+// Sum of a long DH group's slices, in slice order; grid as above over the
+// level's groups.
+__global__ __launch_bounds__(kW* kWavesPerBlock) void dh_reduce_kernel(
+    const int4* __restrict__ grp, const int32_t* __restrict__ first, int g0, int ng, int slice0,
+    NodeView qt, int Mq, const double* __restrict__ part, double* __restrict__ gdh) {
+  const int lane = threadIdx.x % kW;
+  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  if (i >= ng) return;
+  const int4 gr = grp[g0 + i];
+  if (gr.w <= kDHSliceEntries) return;
+  const int Q = gr.y, qn = qt.count[Q];
+  const int base = blockIdx.y * kW;
+  if (base + lane >= qn) return;
+  const int ns = (gr.w + kDHSliceEntries - 1) / kDHSliceEntries;
+  const int s0 = first[g0 + i] - slice0;
+  double sum = 0.0;
+  for (int k = 0; k < ns; ++k) sum += part[((int64_t)(s0 + k) * gridDim.y + blockIdx.y) * kW + lane];
+  gdh[(int64_t)gr.x * Mq + qt.begin[Q] + base + lane] += sum;
+}
+
+// One wave per DL slice: lanes over 64 reference points of a chunk, per-lane
+// partial coefficients reduced across the wave once per slice.
 template <int D, int P>
 __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
-    SortedGroups g, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
+    const int4* __restrict__ slc, int ns, const int4* __restrict__ grp,
+    const int32_t* __restrict__ ent, const int32_t* __restrict__ cpre, NodeView qt, NodeView rt,
     const double* __restrict__ xr_perm, const double* __restrict__ wr_perm,
-    const double* __restrict__ sc, int nQ, double* __restrict__ lco, int32_t* __restrict__ pL) {
+    const double* __restrict__ sc, double* __restrict__ part, int32_t* __restrict__ part_p) {
   constexpr MultiIndex<D, P> mi{};
+  constexpr int C = MultiIndex<D, P>::C;
+  const int lane = threadIdx.x % kW;
+  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  if (i >= ns) return;
+  const int4 sl = slc[i];
+  const int4 g0 = grp[sl.x];
+  const int h = g0.x, Q = g0.y;
+  const double s = sc[h];
+  double cQ[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) cQ[d] = qt.ctr[(int64_t)Q * D + d];
+  // entry holding the slice's first chunk: the last with cpre <= first chunk
+  int lo = 0, hi = g0.w - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cpre[g0.z + mid] <= sl.y)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int e = g0.z + lo;
+  int c = sl.y - cpre[e];  // chunk inside entry e
+  double B[C];
+#pragma unroll
+  for (int a = 0; a < C; ++a) B[a] = 0.0;
+  int pmax = 0;
+  int R = ent[e] >> 4, p = ent[e] & 15;
+  int rb = rt.begin[R], rn = rt.count[R];
+  for (int k = sl.y; k < sl.z; ++k, ++c) {
+    if (c * kW >= rn) {
+      ++e;
+      c = 0;
+      R = ent[e] >> 4;
+      p = ent[e] & 15;
+      rb = rt.begin[R];
+      rn = rt.count[R];
+    }
+    pmax = p > pmax ? p : pmax;
+    int nt = 0;
+#pragma unroll
+    for (int q = 0; q <= P; ++q)
+      if (q == p) nt = mi.nterms[q];
+    if (c * kW + lane >= rn) continue;
+    const int pos = rb + c * kW + lane;
+    double H[D][P];
+    double tt = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double t = (xr_perm[(int64_t)pos * D + d] - cQ[d]) * s;
+      tt += t * t;
+      hermite_polys<P>(t, H[d]);
+    }
+    const double ew = wr_perm[pos] * exp(-tt);
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      if (a < nt) {
+        double term = ew;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if (mi.a[a][d]) term *= H[d][mi.a[a][d]];
+        B[a] += term;
+      }
+    }
+  }
+  double* out = part + (int64_t)i * C;
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    const double v = wave_sum(B[a]);
+    if (lane == 0) out[a] = v;
+  }
+  if (lane == 0) part_p[i] = pmax;
+}
+
+// Per (h, Q) run of the sorted DL groups: the slices of its groups summed in
+// order, scaled by 1/b! into lco; lanes over coefficients.
+template <int D, int P>
+__global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
+    SortedGroups g, const int2* __restrict__ first, const double* __restrict__ part,
+    const int32_t* __restrict__ part_p, int nQ, double* __restrict__ lco, int32_t* __restrict__ pL) {
+  static constexpr MultiIndex<D, P> mi{};
   constexpr int C = MultiIndex<D, P>::C;
   const int lane = threadIdx.x % kW;
   const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
   if (i >= g.n || (i > 0 && g.key[i] == g.key[i - 1])) return;
   const int4 g0 = g.grp[g.order[i]];
   const int h = g0.x, Q = g0.y;
-  const double s = sc[h];
-  double cQ[D];
+  double sum[(C + kW - 1) / kW];
 #pragma unroll
-  for (int d = 0; d < D; ++d) cQ[d] = qt.ctr[(int64_t)Q * D + d];
-  double B[C];
-#pragma unroll
-  for (int a = 0; a < C; ++a) B[a] = 0.0;
+  for (int u = 0; u < (C + kW - 1) / kW; ++u) sum[u] = 0.0;
   int pmax = 0;
   for (int j = i; j < g.n && (j == i || g.key[j] == g.key[j - 1]); ++j) {
-    const int4 gr = g.grp[g.order[j]];
-    for (int e = gr.z; e < gr.z + gr.w; ++e) {
-      const int R = ent[e] >> 4, p = ent[e] & 15;
-      pmax = p > pmax ? p : pmax;
-      int nt = 0;
+    const int2 f = first[g.order[j]];
+    for (int k = f.x; k < f.x + f.y; ++k) {
+      const double* v = part + (int64_t)k * C;
 #pragma unroll
-      for (int k = 0; k <= P; ++k)
-        if (k == p) nt = mi.nterms[k];
-      const int rb = rt.begin[R], rn = rt.count[R];
-      for (int base = 0; base < rn; base += kW) {
-        if (base + lane >= rn) continue;
-        const int pos = rb + base + lane;
-        double H[D][P];
-        double tt = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const double t = (xr_perm[(int64_t)pos * D + d] - cQ[d]) * s;
-          tt += t * t;
-          hermite_polys<P>(t, H[d]);
-        }
-        const double ew = wr_perm[pos] * exp(-tt);
-#pragma unroll
-        for (int a = 0; a < C; ++a) {
-          if (a < nt) {
-            double term = ew;
-#pragma unroll
-            for (int d = 0; d < D; ++d)
-              if (mi.a[a][d]) term *= H[d][mi.a[a][d]];
-            B[a] += term;
-          }
-        }
-      }
+      for (int u = 0; u < (C + kW - 1) / kW; ++u)
+        if (u * kW + lane < C) sum[u] += v[u * kW + lane];
+      pmax = part_p[k] > pmax ? part_p[k] : pmax;
     }
   }
   double* out = lco + ((int64_t)h * nQ + Q) * C;
 #pragma unroll
-  for (int a = 0; a < C; ++a) {
-    const double v = wave_sum(B[a]);
-    if (lane == 0) out[a] += v * mi.invf[a];
+  for (int u = 0; u < (C + kW - 1) / kW; ++u) {
+    const int a = u * kW + lane;
+    if (a < C) out[a] += sum[u] * mi.invf[a];
   }
   if (lane == 0) {
     int32_t* pl = pL + (int64_t)h * nQ + Q;
@@ -216,20 +300,29 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
 }
 
 template <int D, int P>
-void dh_launch(const int4* grp, int ng, int max_q, const int32_t* ent, const NodeView& qt,
-               const NodeView& rt, const double* xq, const double* M, const double* sc, int Mq,
-               double* gdh, hipStream_t s) {
-  hipLaunchKernelGGL((dh_fast_kernel<D, P>),
-                     dim3((unsigned)ceil_div(ng, kWavesPerBlock), (unsigned)ceil_div(max_q, kW)),
-                     dim3(kW * kWavesPerBlock), 0, s, grp, ng, ent, qt, rt, xq, M, sc, Mq, gdh);
+void dh_launch(const int4* slices, int ns, int slice0, const int4* grp, const int32_t* first, int g0,
+               int ng, int max_q, const int32_t* ent, const NodeView& qt, const NodeView& rt,
+               const double* xq, const double* M, const double* sc, int Mq, double* gdh, double* part,
+               hipStream_t s) {
+  const unsigned cy = (unsigned)ceil_div(max_q, kW);
+  hipLaunchKernelGGL((dh_fast_kernel<D, P>), dim3((unsigned)ceil_div(ns, kWavesPerBlock), cy),
+                     dim3(kW * kWavesPerBlock), 0, s, slices, ns, grp, ent, qt, rt, xq, M, sc, Mq, gdh,
+                     part);
+  if (ng > 0 && ns > ng)  // some group has more than one slice
+    hipLaunchKernelGGL(dh_reduce_kernel, dim3((unsigned)ceil_div(ng, kWavesPerBlock), cy),
+                       dim3(kW * kWavesPerBlock), 0, s, grp, first, g0, ng, slice0, qt, Mq, part, gdh);
 }
 
 template <int D, int P>
-void dl_launch(const SortedGroups& g, const int32_t* ent, const NodeView& qt, const NodeView& rt,
+void dl_launch(const SortedGroups& g, const int4* slices, int ns, const int2* first,
+               const int32_t* cpre, const int32_t* ent, const NodeView& qt, const NodeView& rt,
                const double* xr, const double* wr, const double* sc, int nQ, double* lco, int32_t* pL,
-               hipStream_t s) {
-  hipLaunchKernelGGL((dl_fast_kernel<D, P>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),
-                     dim3(kW * kWavesPerBlock), 0, s, g, ent, qt, rt, xr, wr, sc, nQ, lco, pL);
+               double* part, int32_t* part_p, hipStream_t s) {
+  hipLaunchKernelGGL((dl_fast_kernel<D, P>), dim3((unsigned)ceil_div(ns, kWavesPerBlock)),
+                     dim3(kW * kWavesPerBlock), 0, s, slices, ns, g.grp, ent, cpre, qt, rt, xr, wr, sc,
+                     part, part_p);
+  hipLaunchKernelGGL((dl_reduce_kernel<D, P>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),
+                     dim3(kW * kWavesPerBlock), 0, s, g, first, part, part_p, nQ, lco, pL);
 }
 
 // (D, P) pairs with a compiled specialisation.
@@ -246,33 +339,40 @@ bool series_fast_available(int D, int P) {
   return false;
 }
 
-hipError_t launch_dh_fast(int D, int P, const int4* grp, int ng, int max_q, const int32_t* ent,
+hipError_t launch_dh_fast(int D, int P, const int4* slices, int ns, int slice0, const int4* grp,
+                          const int32_t* first, int g0, int ng, int max_q, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xq_perm,
-                          const double* M, const double* sc, int Mq, double* gdh, hipStream_t s) {
-  if (ng == 0) return hipSuccess;
-#define X(d, p)                                                                   \
-  if (D == d && P == p) {                                                         \
-    dh_launch<d, p>(grp, ng, max_q, ent, qt, rt, xq_perm, M, sc, Mq, gdh, s);     \
-    return hipGetLastError();                                               \
+                          const double* M, const double* sc, int Mq, double* gdh, double* part,
+                          hipStream_t s) {
+  if (ns == 0) return hipSuccess;
+#define X(d, p)                                                                                 \
+  if (D == d && P == p) {                                                                       \
+    dh_launch<d, p>(slices, ns, slice0, grp, first, g0, ng, max_q, ent, qt, rt, xq_perm, M, sc, \
+                    Mq, gdh, part, s);                                                          \
+    return hipGetLastError();                                                                   \
   }
   GS_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slices, int ns,
+                          const int2* first, const int32_t* cpre, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xr_perm,
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
-                          hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-#define X(d, p)                                                                \
-  if (D == d && P == p) {                                                      \
-    dl_launch<d, p>(g, ent, qt, rt, xr_perm, wr_perm, sc, nQ, lco, pL, s);     \
-    return hipGetLastError();                                                  \
+                          double* part, int32_t* part_p, hipStream_t s) {
+  if (g.n == 0 || ns == 0) return hipSuccess;
+#define X(d, p)                                                                                  \
+  if (D == d && P == p) {                                                                        \
+    dl_launch<d, p>(g, slices, ns, first, cpre, ent, qt, rt, xr_perm, wr_perm, sc, nQ, lco, pL,  \
+                    part, part_p, s);                                                            \
+    return hipGetLastError();                                                                    \
   }
   GS_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
+
+int series_terms(int D, int P) { return cbinom(D + P - 1, D); }
 
 }  // namespace gs
