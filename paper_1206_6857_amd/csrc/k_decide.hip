@@ -105,6 +105,11 @@ __device__ __forceinline__ void box_dist2(const double* loQ, const double* hiQ, 
 // Broadcast of lane j's value to the whole wave (v_readlane: register to
 // register, no memory round trip).  j must be wave-uniform.
 __device__ __forceinline__ int rl(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ long long rl(long long v, int j) {
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), j);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), j);
+  return ((long long)(unsigned)lo) | ((long long)hi << 32);
+}
 __device__ __forceinline__ double rl(double v, int j) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
@@ -248,10 +253,17 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   // orders: no DIRECT shortcut.
   const bool all_orders = c.log_feas != 0;
   const bool learned = c.use_fmm && c.policy;
+  // Cost tables of the segment, lane k holding order k: c_DH(k) = N_Q D^(k+1),
+  // c_H2L(k) = D^(2k+1) (Figure 6).
+  const long long c0_lane = lane >= 1 && lane <= P ? sat_mul(NQ, c.powD[lane + 1]) : kInfCost;
+  const long long c2_lane = lane >= 1 && lane <= P ? c.powD[2 * lane + 1] : kInfCost;
+  __shared__ double sh_pm[64][3 * P];      // PM_DH, PM_DL, PM_H2L of each pair
+  __shared__ long long sh_c1[64][P];       // c_DL(q) = N_R D^(q+1), q = 1..P
   for (int b0 = 0; b0 < len; b0 += 64) {
     const int n = len - b0 < 64 ? len - b0 : 64;
     double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY, thr = INFINITY;
     int NR = 0, rleaf = 0, Rid = 0;
+    long long c3 = 0;
     int kstar = 0;  // learned policy: cheapest predicted action (3 = recurse)
     double pm0[P], pm1[P], pm2[P];
 #pragma unroll
@@ -311,12 +323,14 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
           pm2[p - 1] = m2;
         }
         const int64_t cdir = sat_mul(c.D, sat_mul(NQ, (int64_t)NR));
+        c3 = cdir;
         double mstar = INFINITY;
 #pragma unroll
         for (int p = 1; p <= P; ++p) {
+          const int64_t c1p = sat_mul((int64_t)NR, c.powD[p + 1]);
+          sh_c1[lane][p - 1] = c1p;
           if (sat_mul(NQ, c.powD[p + 1]) <= cdir) mstar = pm0[p - 1] < mstar ? pm0[p - 1] : mstar;
-          if (sat_mul((int64_t)NR, c.powD[p + 1]) <= cdir)
-            mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
+          if (c1p <= cdir) mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
           if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
         }
         astar = all_orders ? -INFINITY : division_threshold(mstar, Wtot);
@@ -337,174 +351,161 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
     }
     const unsigned long long base_ok = qleaf ? __ballot(lane < n && rleaf) : 0ull;
     const unsigned long long kfall = learned ? __ballot(lane < n && kstar != 3) : 0ull;
-    // Pair values the walk reads, staged in LDS and read back as broadcasts
-    // one pair ahead of their use.
+    // Pair values the walk reads, staged in LDS and read back as broadcasts;
+    // the bounds as one row per pair, read across the lanes.
     __syncthreads();
     if (lane < n) {
       sh_pair[lane] = make_double4(nd, WR, thr, fdval);
       sh_lterm[lane] = lterm;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        sh_pm[lane][p] = pm0[p];
+        sh_pm[lane][P + p] = pm1[p];
+        sh_pm[lane][2 * P + p] = pm2[p];
+      }
     }
     __syncthreads();
     // The token rule, pair by pair, the wave in lockstep.
     unsigned long long m_fd = 0, m_slow = 0, m_base = 0;
     int my_code = -1, my_p = 0, my_feas = 0;
-    double4 nxt = sh_pair[0];
-    double nxt_lt = sh_lterm[0];
-    for (int j = 0; j < n; ++j) {
-      const unsigned long long bit = 1ull << j;
-      const double ndj = nxt.x, WRj = nxt.y, thrj = nxt.z, fdj = nxt.w, ltj = nxt_lt;
-      nxt = sh_pair[(j + 1) & 63];
-      nxt_lt = sh_lterm[(j + 1) & 63];
-      const double tt = c.use_tokens ? t : 0.0;
-      const double a = (c.eps_alg * (WRj + tt)) * L;
-      const bool fd = ndj <= tt;
-      bool is_fd = fd, is_split = false;
-      if (fd || !(a >= thrj)) {
+    int j = 0;
+    while (j < n) {
+      // Short path until a pair reaches the series threshold.
+      double a = 0.0, WRj = 0.0, ltj = 0.0;
+      bool slow = false;
+      double4 nx = sh_pair[j];  // read one pair ahead
+      double nx_lt = sh_lterm[j];
+      for (; j < n; ++j) {
+        const double4 pv = nx;
+        ltj = nx_lt;
+        nx = sh_pair[(j + 1) & 63];
+        nx_lt = sh_lterm[(j + 1) & 63];
+        WRj = pv.y;
+        const double tt = c.use_tokens ? t : 0.0;
+        a = (c.eps_alg * (WRj + tt)) * L;
+        const bool fd = pv.x <= tt;
+        if (!fd && a >= pv.z) {
+          slow = true;
+          break;
+        }
         // finite difference, or DIRECT below the series threshold (and the
         // learned policy's recursion): base case if both nodes are leaves,
         // else split
+        const unsigned long long bit = 1ull << j;
         const bool base = !fd && (base_ok & bit);
-        if (c.use_tokens) t = fd ? t - ndj : (base ? t + WRj : t);
+        if (c.use_tokens) t = fd ? t - pv.x : (base ? t + WRj : t);
         m_fd |= fd ? bit : 0ull;
         m_base |= base ? bit : 0ull;
-        is_split = !fd && !base;
-      } else {
-        m_slow |= bit;
-        int cd = -1;
-        int p = 0;
-        double Esel = 0.0;
-        bool rule = true;
-        if (learned) {
-          // The learned policy: its cheapest predicted action, a series
-          // method only at an order its bound admits, else the rule decides.
-          const int kj = rl(kstar, j);
-          const double maxerr = a / Wtot;
-          if (kj == 3) rule = false;
-          int qk = 0;
-          double ek = 0.0;
-          if (lane == j) {
-            int ak = 0;
-#pragma unroll
-            for (int pp = 0; pp < P; ++pp) {
-              const double e = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
-              ak += e > maxerr ? 1 : 0;
-            }
-            qk = ak < P ? ak + 1 : 0;
-#pragma unroll
-            for (int pp = 0; pp < P; ++pp)
-              if (pp + 1 == qk) ek = kj == 0 ? pm0[pp] : kj == 1 ? pm1[pp] : pm2[pp];
-          }
-          qk = rl(qk, j);
-          if (kj == 3) {
-          } else if (qk) {
-            cd = kj == 0 ? DH : kj == 1 ? DL : H2L;
+        gest = gest + (fd ? pv.w : 0.0);
+        Lp = Lp + (!fd && !base ? 0.0 : ltj);
+        any_fd = any_fd || fd;
+      }
+      if (!slow) break;
+      // bestMethod (Figure 6) at maxerr for pair j: its bounds across the
+      // lanes, the admitted order of each method counted from one ballot.
+      m_slow |= 1ull << j;
+      const double maxerr = a / Wtot;
+      const double pmv = lane < 3 * P ? sh_pm[j][lane] : INFINITY;
+      const unsigned long long gt = __ballot(lane < 3 * P && pmv > maxerr);
+      const unsigned long long fm = (1ull << P) - 1;
+      const int n0 = __popcll(gt & fm), n1 = __popcll((gt >> P) & fm),
+                n2 = __popcll((gt >> (2 * P)) & fm);
+      int q0 = n0 < P ? n0 + 1 : 0, q1 = n1 < P ? n1 + 1 : 0, q2 = n2 < P ? n2 + 1 : 0;
+      int cd = -1, p = 0, xs = 0;
+      bool rule = c.use_fmm != 0;
+      if (learned) {
+        // The learned policy: its cheapest predicted action, a series
+        // method only at an order its bound admits, else the rule decides.
+        const int kj = rl(kstar, j);
+        if (kj == 3) {
+          rule = false;
+        } else {
+          const int qk = kj == 0 ? q0 : kj == 1 ? q1 : q2;
+          if (qk) {
+            cd = DH + kj;
             p = qk;
-            Esel = rl(ek, j);
+            xs = kj;
             rule = false;
           } else {
             ++nfall;
           }
         }
-        if (rule && (all_orders || a >= rl(astar, j))) {
-          const double maxerr = a / Wtot;
-          int q0 = 0, q1 = 0, q2 = 0;
-          double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-          if (lane == j) {
-            int a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-            for (int pp = 0; pp < P; ++pp) {
-              a0 += pm0[pp] > maxerr ? 1 : 0;
-              a1 += pm1[pp] > maxerr ? 1 : 0;
-              a2 += pm2[pp] > maxerr ? 1 : 0;
-            }
-            q0 = a0 < P ? a0 + 1 : 0;
-            q1 = a1 < P ? a1 + 1 : 0;
-            q2 = a2 < P ? a2 + 1 : 0;
-#pragma unroll
-            for (int pp = 0; pp < P; ++pp) {
-              if (pp + 1 == q0) e0 = pm0[pp];
-              if (pp + 1 == q1) e1 = pm1[pp];
-              if (pp + 1 == q2) e2 = pm2[pp];
-            }
-          }
-          q0 = rl(q0, j);
-          q1 = rl(q1, j);
-          q2 = rl(q2, j);
-          const int64_t NRj = rl(NR, j);
-          const int64_t c0 = q0 ? sat_mul(NQ, c.powD[q0 + 1]) : kInfCost;
-          const int64_t c1 = q1 ? sat_mul(NRj, c.powD[q1 + 1]) : kInfCost;
-          const int64_t c2 = q2 ? c.powD[2 * q2 + 1] : kInfCost;
-          const int64_t c3 = sat_mul(c.D, sat_mul(NQ, NRj));
-          int64_t best = c0 < c1 ? c0 : c1;
-          best = c2 < best ? c2 : best;
-          best = c3 < best ? c3 : best;
-          if (q0 && c0 == best) {
-            cd = DH;
-            p = q0;
-          } else if (q1 && c1 == best) {
-            cd = DL;
-            p = q1;
-          } else if (q2 && c2 == best) {
-            cd = H2L;
-            p = q2;
-          }
-          if (c.log_feas && c.explore > 0.0) {
-            // Exploration while logging: for a fixed pseudo-random share of
-            // the pairs, an admitted action drawn uniformly (each admitted
-            // series method at its order, or the direct path) replaces the
-            // rule's, so that the log also holds costs the rule never incurs.
-            unsigned long long x = ((unsigned long long)h << 56) ^ ((unsigned long long)Q << 28) ^
-                                   (unsigned long long)rl(Rid, j);
-            x += 0x9e3779b97f4a7c15ull;
-            x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
-            x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
-            x ^= x >> 31;
-            if ((double)(x >> 11) * 0x1.0p-53 < c.explore) {
-              const int ncand = (q0 ? 1 : 0) + (q1 ? 1 : 0) + (q2 ? 1 : 0) + 1;
-              int pick = (int)((x & 0x3ff) * (unsigned long long)ncand >> 10);
-              cd = -1;
-              p = 0;
-              if (q0 && pick-- == 0) {
-                cd = DH;
-                p = q0;
-              } else if (q1 && pick-- == 0) {
-                cd = DL;
-                p = q1;
-              } else if (q2 && pick-- == 0) {
-                cd = H2L;
-                p = q2;
-              }
-            }
-          }
-          if (cd == DH) Esel = rl(e0, j);
-          else if (cd == DL) Esel = rl(e1, j);
-          else if (cd == H2L) Esel = rl(e2, j);
-          if (c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
-        }
-        if (cd >= 0 && c.use_tokens) t = t - need_fn(Esel, WRj, L, Wtot, c.eps_alg);
-        if (cd < 0) {
-          if (base_ok & bit) {
-            if (c.use_tokens) t = t + WRj;
-            cd = BASE;
-          } else {
-            cd = SPLIT;
-            is_split = true;
-          }
-        }
-        nDH += cd == DH;
-        nDL += cd == DL;
-        nH2L += cd == H2L;
-        nBASE += cd == BASE;
-        nSPLIT += cd == SPLIT;
-        if (lane == j) {
-          my_code = cd;
-          my_p = p;
-        }
       }
-      // Order-dependent sums, in pair order.
-      gest = gest + (is_fd ? fdj : 0.0);
-      Lp = Lp + (is_split ? 0.0 : ltj);
-      any_fd = any_fd || is_fd;
+      if (rule && (all_orders || a >= rl(astar, j))) {
+        const long long c1v = lane < P ? sh_c1[j][lane] : kInfCost;
+        const int64_t c0 = q0 ? rl(c0_lane, q0) : kInfCost;
+        const int64_t c1 = q1 ? rl(c1v, q1 - 1) : kInfCost;
+        const int64_t c2 = q2 ? rl(c2_lane, q2) : kInfCost;
+        const int64_t cd3 = rl(c3, j);
+        int64_t best = c0 < c1 ? c0 : c1;
+        best = c2 < best ? c2 : best;
+        best = cd3 < best ? cd3 : best;
+        if (q0 && c0 == best) {
+          cd = DH;
+          p = q0;
+          xs = 0;
+        } else if (q1 && c1 == best) {
+          cd = DL;
+          p = q1;
+          xs = 1;
+        } else if (q2 && c2 == best) {
+          cd = H2L;
+          p = q2;
+          xs = 2;
+        }
+        if (c.log_feas && c.explore > 0.0) {
+          // Exploration while logging: for a fixed pseudo-random share of
+          // the pairs, an admitted action drawn uniformly (each admitted
+          // series method at its order, or the direct path) replaces the
+          // rule's, so that the log also holds costs the rule never incurs.
+          unsigned long long x = ((unsigned long long)h << 56) ^ ((unsigned long long)Q << 28) ^
+                                 (unsigned long long)rl(Rid, j);
+          x += 0x9e3779b97f4a7c15ull;
+          x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+          x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+          x ^= x >> 31;
+          if ((double)(x >> 11) * 0x1.0p-53 < c.explore) {
+            const int ncand = (q0 ? 1 : 0) + (q1 ? 1 : 0) + (q2 ? 1 : 0) + 1;
+            int pick = (int)((x & 0x3ff) * (unsigned long long)ncand >> 10);
+            cd = -1;
+            p = 0;
+            if (q0 && pick-- == 0) {
+              cd = DH;
+              p = q0;
+              xs = 0;
+            } else if (q1 && pick-- == 0) {
+              cd = DL;
+              p = q1;
+              xs = 1;
+            } else if (q2 && pick-- == 0) {
+              cd = H2L;
+              p = q2;
+              xs = 2;
+            }
+          }
+        }
+        if (c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
+      }
+      if (cd >= 0) {
+        const double Esel = rl(pmv, xs * P + p - 1);
+        if (c.use_tokens) t = t - need_fn(Esel, WRj, L, Wtot, c.eps_alg);
+      } else if (base_ok & (1ull << j)) {
+        if (c.use_tokens) t = t + WRj;
+        cd = BASE;
+      } else {
+        cd = SPLIT;
+      }
+      nDH += cd == DH;
+      nDL += cd == DL;
+      nH2L += cd == H2L;
+      nBASE += cd == BASE;
+      nSPLIT += cd == SPLIT;
+      if (lane == j) {
+        my_code = cd;
+        my_p = p;
+      }
+      Lp = Lp + (cd == SPLIT ? 0.0 : ltj);
+      ++j;
     }
     const unsigned long long bitl = 1ull << lane;
     int code;
