@@ -546,6 +546,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     f.Lp = BUF(double, p + "Lp", nseg);
     f.R = BUF(int32_t, p + "R", npair);
     f.seg = BUF(int32_t, p + "seg", npair);
+    f.first = BUF(int32_t, p + "first", nseg);
     return GS_OK;
   };
   const char* tname[4] = {"dh", "dl", "h2l", "base"};
@@ -615,6 +616,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       CHUNK_ALLOC(grow_lists(e0, g0, s0));
     }
     int level = 0, which = 0;
+    int64_t nfirst = 0;  // long segments of the current level
     std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
     std::vector<int64_t> dh_slice_begin;  // first DH slice of each traversal level
     std::vector<int32_t> tr_h, tr_Q, tr_off, tr_len, tr_R;
@@ -649,7 +651,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
         if (use_policy) DT_HIP(launch_policy_infer_pairs((int)npair, pp, pqt, prt, D, pmodel, scores, st));
         if (log_pairs) DT_HIP(launch_policy_features((int)npair, pp, pqt, prt, D, pfeat, st));
-        DT_HIP(launch_decide((int)nseg, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
+        DT_HIP(launch_decide((int)nseg, (int)nfirst, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
                              Gest, cnt, scores, pfeas, st));
         DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
         kt.stop(st, 2 + (use_policy ? 1 : 0) + (log_pairs ? 1 : 0));
@@ -724,6 +726,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       which = 1 - which;
       nseg = nseg2;
       npair = npair2;
+      nfirst = tot.v[17];
       ++level;
     }
     const double tb0 = now_ms();

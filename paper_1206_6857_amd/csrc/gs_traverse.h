@@ -34,14 +34,20 @@ struct SegCount {
                   // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags,
                   // [10] FD pairs, [11] SPLIT pairs, [12] base-case point
                   // pairs, [13] policy consultations, [14] policy fallbacks,
-                  // [15] DH slices, [16] DL slices, [17] unused
+                  // [15] DH slices, [16] DL slices, [17] next-level
+                  // segments of at least kLongSegment pairs
 };
+
+// Segments this long are listed first (FrontierLevel::first) and raise their
+// wave's issue priority: the longest token walks start before the short ones.
+constexpr int kLongSegment = 128;
 
 struct FrontierLevel {
   int32_t *h = nullptr, *Q = nullptr, *off = nullptr, *len = nullptr;
   double *T = nullptr, *Lp = nullptr;
   int32_t* R = nullptr;    // pairs
   int32_t* seg = nullptr;  // segment of each pair
+  int32_t* first = nullptr;  // the segments of at least kLongSegment pairs
 };
 
 // Node fields read by the decision kernel.
@@ -76,7 +82,8 @@ struct LevelOffsets {
 // H2L, recurse.  feas (log_feas): per pair, 0x8000 | q_DH | q_DL << 4 |
 // q_H2L << 8 (smallest admitted orders, 0 = none) where bestMethod is
 // reached, else 0.
-hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
+// n_first: entries of cur.first (every segment of at least kLongSegment pairs).
+hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
                          SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s);

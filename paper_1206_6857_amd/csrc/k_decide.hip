@@ -184,7 +184,7 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 // masks.  Every expression and its operation order is that of the
 // single-threaded formulation, so the decisions and sums are identical to it.
 template <int P>
-__global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, TreeView qt,
+__global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, FrontierLevel cur, TreeView qt,
                                                     TreeView rt, const double* __restrict__ inv2h2,
                                                     const double* __restrict__ inv4h2,
                                                     const double* __restrict__ invh, int nQ,
@@ -195,13 +195,24 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
                                                     const float4* __restrict__ scores,
                                                     int16_t* __restrict__ feas_out) {
   constexpr double kSqrt2 = 1.4142135623730951;
-  const int s = blockIdx.x;
-  if (s >= S) return;
+  // The long segments first (listed in cur.first), then the others.
+  const int b = blockIdx.x;
+  int s;
+  if (b < n_first) {
+    s = cur.first[b];
+  } else {
+    s = b - n_first;
+    if (s >= S || (n_first > 0 && cur.len[s] >= kLongSegment)) return;
+  }
   const int lane = threadIdx.x;
   const int h = cur.h[s];
   const int Q = cur.Q[s];
   const int off = cur.off[s];
   const int len = cur.len[s];
+  if (len >= 2 * kLongSegment)
+    __builtin_amdgcn_s_setprio(2);
+  else if (len >= kLongSegment)
+    __builtin_amdgcn_s_setprio(1);
   const int D = c.D;
   const double* loQ = qt.lo + (int64_t)Q * D;
   const double* hiQ = qt.hi + (int64_t)Q * D;
@@ -557,7 +568,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, FrontierLevel cur, Tr
   sc.v[14] = nfall;
   sc.v[15] = (nDH + kDHSliceEntries - 1) / kDHSliceEntries;
   sc.v[16] = (dlchunks + kDLSliceChunks - 1) / kDLSliceChunks;
-  sc.v[17] = 0;
+  sc.v[17] = nchild >= kLongSegment ? sc.v[1] : 0;
   cnt[s] = sc;
 }
 
@@ -631,6 +642,7 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
   const int nch = nsegs ? (int)(own.v[0] / nsegs) : 0;
   const int pb = ex[0];
   const int sb = ex[1];
+  if (lane < nsegs && nch >= kLongSegment) nxt.first[(int)(in.v[17] - own.v[17]) + lane] = sb + lane;
   if (lane < nsegs) {
     nxt.h[sb + lane] = h;
     nxt.Q[sb + lane] = qleaf ? Q : qleft[Q] + lane;
@@ -703,13 +715,14 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
 
 }  // namespace
 
-hipError_t launch_decide(int S, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
+hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
                          SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s) {
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \
-    hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)S), dim3(64), 0, s, S, cur, qt, rt,   \
+    hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)(S + n_first)), dim3(64), 0, s, S,     \
+                       n_first, cur, qt, rt,                                                   \
                        inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, scores, feas);    \
     break;
   switch (c.P) {
