@@ -92,6 +92,54 @@ __device__ __forceinline__ void hermite_polys(double t, double* H) {
   for (int k = 1; k + 1 < P; ++k) H[k + 1] = 2.0 * t * H[k] - 2.0 * k * H[k - 1];
 }
 
+// Position of the multi-index (A...) in the graded order (compile time).
+template <int D, int P, int... A>
+constexpr int graded_index() {
+  constexpr MultiIndex<D, P> mi{};
+  const int want[D] = {A...};
+  for (int i = 0; i < MultiIndex<D, P>::C; ++i) {
+    bool eq = true;
+    for (int d = 0; d < D; ++d) eq = eq && mi.a[i][d] == want[d];
+    if (eq) return i;
+  }
+  return -1;
+}
+
+// Nested (Horner-like) sum over the multi-indices with |a| < rem of
+// M[a] prod_d H[d][a_d], dimension by dimension: each dimension's factor
+// multiplies the sum over the dimensions after it, so a term costs one fused
+// multiply-add instead of a product over all dimensions.  A... holds the
+// indices of the dimensions before d; a runs over dimension d.
+template <int D, int P, int d, int rem, int a, int... A>
+struct DHNest {
+  static __device__ __forceinline__ double run(const double (&H)[D][P], const double* __restrict__ M) {
+    double inner;
+    if constexpr (d == D - 1) {
+      constexpr int I = graded_index<D, P, A..., a>();
+      static_assert(I >= 0, "multi-index outside the set");
+      inner = M[I];
+    } else {
+      inner = DHNest<D, P, d + 1, rem - a, 0, A..., a>::run(H, M);
+    }
+    const double v = a == 0 ? inner : H[d][a] * inner;
+    if constexpr (a + 1 < rem)
+      return v + DHNest<D, P, d, rem, a + 1, A...>::run(H, M);
+    else
+      return v;
+  }
+};
+
+// The order p of an entry (1..P) selects the compile-time truncation.
+template <int D, int P, int p = 1>
+__device__ __forceinline__ double dh_sum(int pr, const double (&H)[D][P], const double* __restrict__ M) {
+  if constexpr (p > P) {
+    return 0.0;
+  } else {
+    if (pr == p) return DHNest<D, P, 0, p, 0>::run(H, M);
+    return dh_sum<D, P, p + 1>(pr, H, M);
+  }
+}
+
 // grid.x: slices of the level (kWavesPerBlock per block), grid.y: 64-point
 // chunks of Q.
 template <int D, int P>
@@ -100,10 +148,10 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
     const int32_t* __restrict__ ent, NodeView qt, NodeView rt, const double* __restrict__ xq_perm,
     const double* __restrict__ M, const double* __restrict__ sc, int Mq, double* __restrict__ gdh,
     double* __restrict__ part) {
-  constexpr MultiIndex<D, P> mi{};
   constexpr int C = MultiIndex<D, P>::C;
   const int lane = threadIdx.x % kW;
-  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  // wave index: uniform across the wave (readfirstlane tells the compiler)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
   if (i >= ns) return;
   const int4 sl = slc[i];
   const int4 gr = grp[sl.x];
@@ -124,11 +172,9 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
   double acc = 0.0;
   for (int e = sl.y; e < sl.y + sl.z; ++e) {
     const int R = ent[e] >> 4, p = ent[e] & 15;
-    int nt = 0;
-#pragma unroll
-    for (int k = 0; k <= P; ++k)
-      if (k == p) nt = mi.nterms[k];
     const double* cR = rt.ctr + (int64_t)R * D;
+    // H[d][k] = s^k H_k(t_d): the scale s^|a| of a term splits over the
+    // dimensions
     double H[D][P];
     double tt = 0.0;
 #pragma unroll
@@ -136,19 +182,10 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
       const double t = (x[d] - cR[d]) * s;
       tt += t * t;
       hermite_polys<P>(t, H[d]);
-    }
-    const double* m = M + (int64_t)R * C;
-    double v = 0.0;
 #pragma unroll
-    for (int a = 0; a < C; ++a) {
-      if (a < nt) {
-        double term = m[a] * spow[mi.deg[a]];
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-          if (mi.a[a][d]) term *= H[d][mi.a[a][d]];
-        v += term;
-      }
+      for (int k = 1; k < P; ++k) H[d][k] *= spow[k];
     }
+    const double v = dh_sum<D, P>(p, H, M + (int64_t)R * C);
     acc += v * exp(-tt);
   }
   if (!active) return;
@@ -164,7 +201,8 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_reduce_kernel(
     const int4* __restrict__ grp, const int32_t* __restrict__ first, int g0, int ng, int slice0,
     NodeView qt, int Mq, const double* __restrict__ part, double* __restrict__ gdh) {
   const int lane = threadIdx.x % kW;
-  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  // wave index: uniform across the wave (readfirstlane tells the compiler)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
   if (i >= ng) return;
   const int4 gr = grp[g0 + i];
   if (gr.w <= kDHSliceEntries) return;
@@ -189,7 +227,8 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
   constexpr MultiIndex<D, P> mi{};
   constexpr int C = MultiIndex<D, P>::C;
   const int lane = threadIdx.x % kW;
-  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  // wave index: uniform across the wave (readfirstlane tells the compiler)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
   if (i >= ns) return;
   const int4 sl = slc[i];
   const int4 g0 = grp[sl.x];
@@ -225,10 +264,6 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
       rn = rt.count[R];
     }
     pmax = p > pmax ? p : pmax;
-    int nt = 0;
-#pragma unroll
-    for (int q = 0; q <= P; ++q)
-      if (q == p) nt = mi.nterms[q];
     if (c * kW + lane >= rn) continue;
     const int pos = rb + c * kW + lane;
     double H[D][P];
@@ -242,7 +277,7 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
     const double ew = wr_perm[pos] * exp(-tt);
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      if (a < nt) {
+      if (mi.deg[a] < p) {
         double term = ew;
 #pragma unroll
         for (int d = 0; d < D; ++d)
@@ -269,7 +304,8 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
   static constexpr MultiIndex<D, P> mi{};
   constexpr int C = MultiIndex<D, P>::C;
   const int lane = threadIdx.x % kW;
-  const int i = blockIdx.x * kWavesPerBlock + threadIdx.x / kW;
+  // wave index: uniform across the wave (readfirstlane tells the compiler)
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
   if (i >= g.n || (i > 0 && g.key[i] == g.key[i - 1])) return;
   const int4 g0 = g.grp[g.order[i]];
   const int h = g0.x, Q = g0.y;
