@@ -503,8 +503,12 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   // Bandwidths on the host.
   std::vector<double> hs(n_h);
   if (is_device_pointer(bandwidths)) {
-    GS_HIP(ctx, hipMemcpyAsync(hs.data(), bandwidths, n_h * sizeof(double), hipMemcpyDeviceToHost, st));
+    hipError_t pe = hipSuccess;
+    auto* ph = static_cast<double*>(ctx->ws.get_pinned("hs_read", n_h * sizeof(double), &pe));
+    if (!ph) GS_FAIL(ctx, GS_ENOMEM, "pinned host allocation failed");
+    GS_HIP(ctx, hipMemcpyAsync(ph, bandwidths, n_h * sizeof(double), hipMemcpyDeviceToHost, st));
     GS_HIP(ctx, hipStreamSynchronize(st));
+    std::copy(ph, ph + n_h, hs.begin());
   } else {
     std::copy(bandwidths, bandwidths + n_h, hs.begin());
   }
@@ -551,8 +555,14 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     GS_HIP(ctx, hipMemcpyAsync(in.w, weights, N * sizeof(double), hipMemcpyHostToDevice, st));
   GS_HIP(ctx, launch_check_positive(in.w, N, bad, st));
   int bad_h = 0;
-  GS_HIP(ctx, hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-  GS_HIP(ctx, hipStreamSynchronize(st));
+  {
+    hipError_t pe = hipSuccess;
+    auto* pb = static_cast<int*>(ctx->ws.get_pinned("bad_read", sizeof(int), &pe));
+    if (!pb) GS_FAIL(ctx, GS_ENOMEM, "pinned host allocation failed");
+    GS_HIP(ctx, hipMemcpyAsync(pb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    GS_HIP(ctx, hipStreamSynchronize(st));
+    bad_h = *pb;
+  }
   if (bad_h & 1) GS_FAIL(ctx, GS_EINVAL, "a coordinate is NaN or infinite");
   if (bad_h & 2) GS_FAIL(ctx, GS_EINVAL, "every weight must be finite and > 0");
   const double t_staged = now_ms();

@@ -255,10 +255,17 @@ __global__ void group_keys_kernel(int n, const int4* __restrict__ grp, int nQ,
   idx[i] = i;
 }
 
+// Host vector to device memory through a page-locked staging buffer of its
+// own (name), so that the copy is asynchronous; the buffer is not reused
+// before the call's final synchronisation.
 template <class T>
-hipError_t upload(const std::vector<T>& v, T* dst, hipStream_t s) {
+hipError_t upload(gs_ctx_base* ctx, const char* name, const std::vector<T>& v, T* dst, hipStream_t s) {
   if (v.empty()) return hipSuccess;
-  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  hipError_t e = hipSuccess;
+  void* stage = ctx->ws.get_pinned(std::string("up_") + name, v.size() * sizeof(T), &e);
+  if (!stage) return e;
+  std::memcpy(stage, v.data(), v.size() * sizeof(T));
+  return hipMemcpyAsync(dst, stage, v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
 }  // namespace
@@ -423,15 +430,15 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     int32_t* ls0 = BUF(int32_t, "ts_l2ls", hsr.l2l_start.size());
     int2* lp = BUF(int2, "ts_l2lp", hsr.l2l_pairs.size());
     double* lc = BUF(double, "ts_l2lc", hsr.l2l_coef.size());
-    DT_HIP(upload(hsr.alpha, alpha, st));
-    DT_HIP(upload(hsr.deg, deg, st));
-    DT_HIP(upload(hsr.inv_fact, invf, st));
-    DT_HIP(upload(hsr.nterms, nterms, st));
-    DT_HIP(upload(hsr.h2h_start, hs0, st));
-    DT_HIP(upload(hsr.h2h_pairs, hp, st));
-    DT_HIP(upload(hsr.l2l_start, ls0, st));
-    DT_HIP(upload(hsr.l2l_pairs, lp, st));
-    DT_HIP(upload(hsr.l2l_coef, lc, st));
+    DT_HIP(upload(ctx, "alpha", hsr.alpha, alpha, st));
+    DT_HIP(upload(ctx, "deg", hsr.deg, deg, st));
+    DT_HIP(upload(ctx, "invf", hsr.inv_fact, invf, st));
+    DT_HIP(upload(ctx, "nterms", hsr.nterms, nterms, st));
+    DT_HIP(upload(ctx, "hs0", hsr.h2h_start, hs0, st));
+    DT_HIP(upload(ctx, "hp", hsr.h2h_pairs, hp, st));
+    DT_HIP(upload(ctx, "ls0", hsr.l2l_start, ls0, st));
+    DT_HIP(upload(ctx, "lp", hsr.l2l_pairs, lp, st));
+    DT_HIP(upload(ctx, "lc", hsr.l2l_coef, lc, st));
     T.alpha = alpha;
     T.deg = deg;
     T.inv_fact = invf;
@@ -474,12 +481,12 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* d_sc = BUF(double, "h_sc", n_h);
   float* d_s2 = BUF(float, "h_s2", n_h);
   double* d_hs = BUF(double, "h_hs", n_h);
-  DT_HIP(upload(hs, d_hs, st));
-  DT_HIP(upload(h_inv2h2, d_inv2h2, st));
-  DT_HIP(upload(h_inv4h2, d_inv4h2, st));
-  DT_HIP(upload(h_invh, d_invh, st));
-  DT_HIP(upload(h_sc, d_sc, st));
-  DT_HIP(upload(h_s2, d_s2, st));
+  DT_HIP(upload(ctx, "d_hs", hs, d_hs, st));
+  DT_HIP(upload(ctx, "d_inv2h2", h_inv2h2, d_inv2h2, st));
+  DT_HIP(upload(ctx, "d_inv4h2", h_inv4h2, d_inv4h2, st));
+  DT_HIP(upload(ctx, "d_invh", h_invh, d_invh, st));
+  DT_HIP(upload(ctx, "d_sc", h_sc, d_sc, st));
+  DT_HIP(upload(ctx, "d_s2", h_s2, d_s2, st));
 
   DecideConst dc;
   std::memset(&dc, 0, sizeof(dc));
@@ -616,6 +623,12 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       CHUNK_ALLOC(grow_lists(e0, g0, s0));
     }
     int level = 0, which = 0;
+    SegCount* seg_tot = nullptr;  // page-locked: the per-level readback
+    {
+      hipError_t pe = hipSuccess;
+      seg_tot = static_cast<SegCount*>(ctx->ws.get_pinned("seg_tot", sizeof(SegCount), &pe));
+      if (!seg_tot) DT_FAIL(GS_ENOMEM, "pinned host allocation failed for the frontier counts");
+    }
     int64_t nfirst = 0;  // long segments of the current level
     std::vector<int64_t> dh_level_begin;  // first DH group of each traversal level
     std::vector<int64_t> dh_slice_begin;  // first DH slice of each traversal level
@@ -656,9 +669,9 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
         kt.stop(st, 2 + (use_policy ? 1 : 0) + (log_pairs ? 1 : 0));
       }
-      SegCount tot;
-      DT_HIP(hipMemcpyAsync(&tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
+      DT_HIP(hipMemcpyAsync(seg_tot, incl + (nseg - 1), sizeof(SegCount), hipMemcpyDeviceToHost, st));
       DT_HIP(hipStreamSynchronize(st));
+      const SegCount tot = *seg_tot;
       if (opt.keep_trace) {
         tr_h.resize(nseg);
         tr_Q.resize(nseg);
@@ -835,6 +848,11 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.slots = BUF(int4, "bf_slots", nslots);
       ba.partial = BUF(double, "bf_partial", (int64_t)nslots * 8 * ceil_div(opt.leaf_size, 64) * 64);
       ba.counters = BUF(int32_t, "bf_counters", 4);
+      {
+        hipError_t pe = hipSuccess;
+        ba.host_counters = static_cast<int32_t*>(ctx->ws.get_pinned("bf_counters", 4 * sizeof(int32_t), &pe));
+        if (!ba.host_counters) return GS_ENOMEM;
+      }
       ba.temp_bytes = std::max(base_fused_temp_bytes(ne), gsort_bytes);
       ba.temp = BUF(char, "g_sort_temp", ba.temp_bytes);
       return GS_OK;

@@ -467,10 +467,10 @@ hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t
   e = rocprim::reduce_by_key(a.temp, bytes, a.key_sorted, a.bit_sorted, (size_t)n, a.ukey, a.umask,
                              a.counters, BitOr(), rocprim::equal_to<unsigned long long>(), s);
   if (e != hipSuccess) return e;
-  int32_t nu = 0;
-  e = hipMemcpyAsync(&nu, a.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(a.host_counters, a.counters, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
+  const int32_t nu = a.host_counters[0];
   if (nu <= 0 || nu > n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(run_flags_kernel, dim3((unsigned)ceil_div(nu, 1024)), dim3(1024), 0, s, a.ukey, nu,
                      p->rbits, p->hbits, a.qt.count, a.rt.count, a.flag, a.dist_evals);
@@ -503,10 +503,10 @@ hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   p->slice_entries = S;
-  int32_t cnt[4] = {0, 0, 0, 0};
-  e = hipMemcpyAsync(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(a.host_counters, a.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
+  const int32_t* cnt = a.host_counters;
   // slices <= runs + nu / S; slots < 2 nu / S <= max_slots
   if (cnt[2] <= 0 || (int64_t)cnt[2] > base_max_slices(n) || cnt[3] < 0 || cnt[3] > p->max_slots)
     return hipErrorInvalidValue;
