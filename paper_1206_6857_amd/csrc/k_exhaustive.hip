@@ -162,14 +162,6 @@ __global__ __launch_bounds__(kThreads) void exhaustive_kernel(
   }
 }
 
-__global__ void max_weight_kernel(const double* __restrict__ w, int64_t n,
-                                  unsigned long long* __restrict__ out_bits) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // positive doubles order like their bit patterns
-  atomicMax(out_bits, (unsigned long long)__double_as_longlong(w[i]));
-}
-
 __global__ void exhaustive_reduce_kernel(const double* __restrict__ partial, int n_split,
                                          int64_t total, double* __restrict__ G) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -223,10 +215,8 @@ int exhaustive_record_stride(int D) { return ((2 * D + 1) + 3) / 4 * 4; }
 
 hipError_t launch_exhaustive_records(const double* x_aos, const double* w, int64_t n, int D,
                                      float* rec, unsigned long long* wmax_bits, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(wmax_bits, 0, sizeof(unsigned long long), s);
+  hipError_t e = launch_max_positive(w, n, wmax_bits, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(max_weight_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w, n,
-                     wmax_bits);
   hipLaunchKernelGGL(exhaustive_records_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s,
                      x_aos, w, wmax_bits, n, D, exhaustive_record_stride(D), rec);
   return hipGetLastError();

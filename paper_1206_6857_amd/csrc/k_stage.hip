@@ -66,10 +66,18 @@ __global__ void gather_kernel(const double* __restrict__ src, const int32_t* __r
   if (i < n) dst[i] = src[perm[i]];
 }
 
+// Largest of positive doubles (their bit patterns order the same way): a wave
+// maximum, then one atomic per wave.
 __global__ void max_bits_kernel(const double* __restrict__ w, int64_t n,
                                 unsigned long long* __restrict__ out_bits) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicMax(out_bits, (unsigned long long)__double_as_longlong(w[i]));
+  unsigned long long v = i < n ? (unsigned long long)__double_as_longlong(w[i]) : 0ull;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  if (threadIdx.x % 64 == 0 && v) atomicMax(out_bits, v);
 }
 
 }  // namespace

@@ -136,22 +136,41 @@ __global__ void scatter_kernel(int64_t n, int nl, int leaf_size, const int32_t* 
   out[k * n + dst] = lists[t];
 }
 
-__global__ void leaf_weights_kernel(int n_nodes, const int32_t* __restrict__ left,
-                                    const int32_t* __restrict__ begin,
-                                    const int32_t* __restrict__ count,
-                                    const int32_t* __restrict__ perm, const double* __restrict__ w,
-                                    double* __restrict__ W, double* __restrict__ wmin) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per node (leaves only): the lanes load 64 weights at a time, the
+// sum is taken in point order (one lane's value after another), the minimum
+// by a wave reduction.
+__global__ __launch_bounds__(256) void leaf_weights_kernel(int n_nodes, const int32_t* __restrict__ left,
+                                                           const int32_t* __restrict__ begin,
+                                                           const int32_t* __restrict__ count,
+                                                           const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ w,
+                                                           double* __restrict__ W,
+                                                           double* __restrict__ wmin) {
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (int)(threadIdx.x / 64));
+  const int lane = threadIdx.x % 64;
   if (i >= n_nodes || left[i] >= 0) return;
   double s = 0.0, m = INFINITY;
-  const int b = begin[i], e = begin[i] + count[i];
-  for (int j = b; j < e; ++j) {
-    const double v = w ? w[perm[j]] : 1.0;
-    s = s + v;
+  const int b = begin[i], n = count[i];
+  for (int c = 0; c < n; c += 64) {
+    const int k = n - c < 64 ? n - c : 64;
+    const double v = lane < k ? (w ? w[perm[b + c + lane]] : 1.0) : INFINITY;
     m = v < m ? v : m;
+    for (int j = 0; j < k; ++j) {
+      const long long bits = __double_as_longlong(v);
+      const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), j);
+      const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), j);
+      s = s + __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+    }
   }
-  W[i] = s;
-  wmin[i] = m;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o < m ? o : m;
+  }
+  if (lane == 0) {
+    W[i] = s;
+    wmin[i] = m;
+  }
 }
 
 __global__ void internal_weights_kernel(int lb, int le, const int32_t* __restrict__ left,
@@ -282,7 +301,7 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
   t.perm_list = lists + (int64_t)D * n;
   e = hipMemcpyAsync(t.perm, t.perm_list, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(leaf_weights_kernel, dim3((unsigned)ceil_div(le, 256)), dim3(256), 0, s, le,
+  hipLaunchKernelGGL(leaf_weights_kernel, dim3((unsigned)ceil_div(le, 4)), dim3(256), 0, s, le,
                      t.left, t.begin, t.count, t.perm, a.w, t.W, t.wmin);
   for (int lv = (int)level_begin.size() - 2; lv >= 0; --lv) {
     const int b = level_begin[lv], en = level_begin[lv + 1];
