@@ -280,6 +280,7 @@ static gs_status build_tree(gs_ctx_base* ctx, const char* pre, const double* xs,
   t.count = BUF(int32_t, P + "count", cap);
   t.left = BUF(int32_t, P + "left", cap);
   t.depth = BUF(int32_t, P + "depth", cap);
+  t.parent = BUF(int32_t, P + "parent", cap);
   t.perm = BUF(int32_t, P + "perm", n);
   t.leaf_of_pos = BUF(int32_t, P + "leafpos", n);
   t.lo = BUF(double, P + "lo", cap * D);
@@ -308,7 +309,7 @@ static gs_status build_tree(gs_ctx_base* ctx, const char* pre, const double* xs,
   a.temp = BUF(char, "tb_temp", a.temp_bytes);
   {
     hipError_t pe = hipSuccess;
-    a.host_topo = static_cast<int32_t*>(ctx->ws.get_pinned(P + "topo", 4 * cap * sizeof(int32_t), &pe));
+    a.host_topo = static_cast<int32_t*>(ctx->ws.get_pinned(P + "topo", 5 * cap * sizeof(int32_t), &pe));
     if (!a.host_topo) DT_FAIL(GS_ENOMEM, "pinned host allocation failed for the tree topology");
   }
   hipError_t e = build_tree_device(a, t, t.level_begin, st);
@@ -955,13 +956,19 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
 
   // 5. Post-pass.
   KernelTimer kpost(ctx, ctx->kernel_timing, GS_K_POST, st);
-  for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
-    DT_HIP(launch_l2l_level(T, qv, qt.level_begin[lv], qt.level_begin[lv + 1], n_h, nQ, d_sc,
-                            lco ? lco : Gest, pL, Gest, st));
-  // one workgroup per query node; internal nodes exit at once
-  DT_HIP(launch_leaf_eval(T, qv, nullptr, nQ, n_h, nQ, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh, Gest,
-                          lco ? lco : Gest, pL, G_dev, st));
-  kpost.stop(st, (int)qt.level_begin.size());
+  if (series_fast_available(D, P)) {
+    DT_HIP(launch_leaf_post_fast(D, P, qv, qt.parent, nQ, n_h, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh,
+                                 Gest, lco, pL, G_dev, st));
+    kpost.stop(st, 1);
+  } else {
+    for (size_t lv = 0; lv + 1 < qt.level_begin.size(); ++lv)
+      DT_HIP(launch_l2l_level(T, qv, qt.level_begin[lv], qt.level_begin[lv + 1], n_h, nQ, d_sc,
+                              lco ? lco : Gest, pL, Gest, st));
+    // one workgroup per query node; internal nodes exit at once
+    DT_HIP(launch_leaf_eval(T, qv, nullptr, nQ, n_h, nQ, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh, Gest,
+                            lco ? lco : Gest, pL, G_dev, st));
+    kpost.stop(st, (int)qt.level_begin.size());
+  }
   double t5 = now_ms();
   S.t_post_ms = t5 - t4;
 

@@ -91,6 +91,15 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slice
                           double* part, int32_t* part_p, hipStream_t s);
 // Size of the DL partial coefficient vectors (C(D+P-1, D)).
 int series_terms(int D, int P);
+// Post-pass in one launch (grid: query nodes x bandwidths, internal nodes
+// exit): G_out[h][qperm[q]] = gx + gdh + sum over the leaf and its ancestors
+// A (parent[], -1 at the root) of Gest_A + EVALL(lco_A, pL_A, x_q); lco may
+// be null when every pL is 0.
+hipError_t launch_leaf_post_fast(int D, int P, const NodeView& qt, const int32_t* parent, int nQ,
+                                 int n_h, int Mq, const double* sc, const double* xq_perm,
+                                 const int32_t* qperm, const double* gx, const double* gdh,
+                                 const double* Gest, const double* lco, const int32_t* pL,
+                                 double* G_out, hipStream_t s);
 
 // Base cases (DITOBase), fused over blocks of 8 bandwidths.
 int base_record_stride(int D);

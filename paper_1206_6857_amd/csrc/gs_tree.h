@@ -13,6 +13,7 @@ struct DevTree {
   int64_t capacity = 0, n_nodes = 0, n_points = 0;
   int D = 0;
   int32_t *begin = nullptr, *count = nullptr, *left = nullptr, *depth = nullptr;
+  int32_t* parent = nullptr;       // -1 at the root
   int32_t *perm = nullptr;         // [n_points] original index at each position
   int32_t *leaf_of_pos = nullptr;  // [n_points] leaf containing each position
   double *lo = nullptr, *hi = nullptr, *ctr = nullptr;
@@ -33,7 +34,7 @@ struct TreeBuildArgs {
   int32_t *flags = nullptr, *scan = nullptr;                             // [(D+1) n]
   int32_t *splitdim = nullptr;                                           // [capacity]
   double* sort_keys = nullptr;                                           // [n]
-  int32_t* host_topo = nullptr;  // pinned host memory, 4 * capacity: the node topology
+  int32_t* host_topo = nullptr;  // pinned host memory, 5 * capacity: the node topology
   void* temp = nullptr;
   size_t temp_bytes = 0;
 };

@@ -335,6 +335,52 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
   }
 }
 
+// Post-pass (Figure 8) of one query leaf and one bandwidth, without the
+// level-by-level translation: the result at a point adds, over the leaf and
+// its ancestors A, Gest_A and A's own local expansion evaluated at the point.
+// A local-to-local translation re-expands a polynomial exactly, so this is
+// the same sum as translating every expansion down to the leaf first.
+template <int D, int P>
+__global__ __launch_bounds__(kW) void leaf_post_kernel(
+    NodeView qt, const int32_t* __restrict__ parent, int nQ, int Mq, const double* __restrict__ sc,
+    const double* __restrict__ xq_perm, const int32_t* __restrict__ qperm,
+    const double* __restrict__ gx, const double* __restrict__ gdh, const double* __restrict__ Gest,
+    const double* __restrict__ lco, const int32_t* __restrict__ pL, double* __restrict__ G_out) {
+  constexpr int C = MultiIndex<D, P>::C;
+  const int Q = blockIdx.x;
+  const int h = blockIdx.y;
+  if (Q >= nQ || qt.left[Q] >= 0) return;
+  const int lane = threadIdx.x;
+  const int64_t hb = (int64_t)h * nQ;
+  double ge = 0.0;  // finite-difference sums, from the leaf up
+  for (int A = Q; A >= 0; A = parent[A]) ge += Gest[hb + A];
+  const double s = sc[h];
+  const int qb = qt.begin[Q], qn = qt.count[Q];
+  for (int base = 0; base < qn; base += kW) {
+    const bool active = base + lane < qn;
+    const int qpos = qb + base + (active ? lane : 0);
+    double x[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = xq_perm[(int64_t)qpos * D + d];
+    double v = gx[(int64_t)h * Mq + qpos] + gdh[(int64_t)h * Mq + qpos] + ge;
+    for (int A = Q; A >= 0; A = parent[A]) {
+      const int p = pL[hb + A];
+      if (p == 0) continue;
+      const double* cA = qt.ctr + (int64_t)A * D;
+      double U[D][P];  // powers of (x - c_A) s
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const double u = (x[d] - cA[d]) * s;
+        U[d][0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < P; ++k) U[d][k] = U[d][k - 1] * u;
+      }
+      v += dh_sum<D, P>(p, U, lco + (hb + A) * C);
+    }
+    if (active) G_out[(int64_t)h * Mq + qperm[qpos]] = v;
+  }
+}
+
 template <int D, int P>
 void dh_launch(const int4* slices, int ns, int slice0, const int4* grp, const int32_t* first, int g0,
                int ng, int max_q, const int32_t* ent, const NodeView& qt, const NodeView& rt,
@@ -410,5 +456,21 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slice
 }
 
 int series_terms(int D, int P) { return cbinom(D + P - 1, D); }
+
+hipError_t launch_leaf_post_fast(int D, int P, const NodeView& qt, const int32_t* parent, int nQ,
+                                 int n_h, int Mq, const double* sc, const double* xq_perm,
+                                 const int32_t* qperm, const double* gx, const double* gdh,
+                                 const double* Gest, const double* lco, const int32_t* pL,
+                                 double* G_out, hipStream_t s) {
+#define X(d, p)                                                                                  \
+  if (D == d && P == p) {                                                                        \
+    hipLaunchKernelGGL((leaf_post_kernel<d, p>), dim3((unsigned)nQ, (unsigned)n_h), dim3(kW), 0,  \
+                       s, qt, parent, nQ, Mq, sc, xq_perm, qperm, gx, gdh, Gest, lco, pL, G_out); \
+    return hipGetLastError();                                                                    \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
 
 }  // namespace gs

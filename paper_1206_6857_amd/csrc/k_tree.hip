@@ -228,9 +228,11 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
   int32_t* hc = hb + cap;
   int32_t* hl = hc + cap;
   int32_t* hd = hl + cap;
+  int32_t* hp = hd + cap;
   hb[0] = 0;
   hc[0] = (int32_t)n;
   hd[0] = 0;
+  hp[0] = -1;
   int64_t nn = 1;
   level_begin.clear();
   int lb = 0, le = 1;
@@ -247,6 +249,7 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
         hb[nn + 1] = hb[i] + (int32_t)lc;
         hc[nn + 1] = hc[i] - (int32_t)lc;
         hd[nn] = hd[nn + 1] = hd[i] + 1;
+        hp[nn] = hp[nn + 1] = i;
         nn += 2;
       } else {
         hl[i] = -1;
@@ -265,6 +268,7 @@ hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int
   if (e == hipSuccess) e = hipMemcpyAsync(t.count, hc, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(t.left, hl, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(t.depth, hd, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t.parent, hp, nn * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(a.pos_node, 0, n * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
 
