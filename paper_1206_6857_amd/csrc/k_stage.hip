@@ -1,4 +1,6 @@
 // Input staging: validation and layout conversion of caller arrays.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -66,18 +68,28 @@ __global__ void gather_kernel(const double* __restrict__ src, const int32_t* __r
   if (i < n) dst[i] = src[perm[i]];
 }
 
-// Largest of positive doubles (their bit patterns order the same way): a wave
-// maximum, then one atomic per wave.
-__global__ void max_bits_kernel(const double* __restrict__ w, int64_t n,
-                                unsigned long long* __restrict__ out_bits) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = i < n ? (unsigned long long)__double_as_longlong(w[i]) : 0ull;
+// Largest of positive doubles (their bit patterns order the same way): each
+// thread a strided share, a block maximum, then one atomic per block.
+__global__ __launch_bounds__(1024) void max_bits_kernel(const double* __restrict__ w, int64_t n,
+                                                        unsigned long long* __restrict__ out_bits) {
+  __shared__ unsigned long long part[16];
+  unsigned long long v = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(w[i]);
+    v = b > v ? b : v;
+  }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const unsigned long long o = __shfl_xor(v, off, 64);
     v = o > v ? o : v;
   }
-  if (threadIdx.x % 64 == 0 && v) atomicMax(out_bits, v);
+  if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x / 64); ++k) v = part[k] > v ? part[k] : v;
+    if (v) atomicMax(out_bits, v);
+  }
 }
 
 }  // namespace
@@ -100,8 +112,8 @@ hipError_t launch_max_positive(const double* w, int64_t n, unsigned long long* o
                                hipStream_t s) {
   hipError_t e = hipMemsetAsync(out_bits, 0, sizeof(unsigned long long), s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(max_bits_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w, n,
-                     out_bits);
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 1024), 256);
+  hipLaunchKernelGGL(max_bits_kernel, dim3((unsigned)blocks), dim3(1024), 0, s, w, n, out_bits);
   return hipGetLastError();
 }
 
