@@ -183,7 +183,9 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 // contribute, exact for these non-negative sums); counters come from the
 // masks.  Every expression and its operation order is that of the
 // single-threaded formulation, so the decisions and sums are identical to it.
-template <int P>
+// GEN: the learned policy or logging may be on; without them the walk
+// compiles to the rule alone.
+template <int P, bool GEN>
 __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, FrontierLevel cur, TreeView qt,
                                                     TreeView rt, const double* __restrict__ inv2h2,
                                                     const double* __restrict__ inv4h2,
@@ -262,8 +264,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   long long bevals = 0, dlchunks = 0;
   // When logging, every pair that reaches bestMethod needs its admitted
   // orders: no DIRECT shortcut.
-  const bool all_orders = c.log_feas != 0;
-  const bool learned = c.use_fmm && c.policy;
+  const bool all_orders = GEN && c.log_feas != 0;
+  const bool learned = GEN && c.use_fmm && c.policy;
   // Cost tables of the segment, lane k holding order k: c_DH(k) = N_Q D^(k+1),
   // c_H2L(k) = D^(2k+1) (Figure 6).
   const long long c0_lane = lane >= 1 && lane <= P ? sat_mul(NQ, c.powD[lane + 1]) : kInfCost;
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
       const double kmin = own_exp(-dmin2 * i2);
       NR = rt.count[R];
       Rid = R;
-      if (scores) {
+      if (GEN && scores) {
         // ties go to the earlier of DH, DL, H2L, recurse
         const float4 sc = scores[off + b0 + lane];
         float sb = sc.x;
@@ -417,6 +419,9 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
       m_slow |= 1ull << j;
       const double maxerr = a / Wtot;
       const double pmv = lane < 3 * P ? sh_pm[j][lane] : INFINITY;
+      // token need of every bound (independent of the token: computed beside
+      // maxerr, read back for the chosen one)
+      const double needv = need_fn(pmv, WRj, L, Wtot, c.eps_alg);
       const unsigned long long gt = __ballot(lane < 3 * P && pmv > maxerr);
       const unsigned long long fm = (1ull << P) - 1;
       const int n0 = __popcll(gt & fm), n1 = __popcll((gt >> P) & fm),
@@ -442,7 +447,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
           }
         }
       }
-      if (rule && (all_orders || a >= rl(astar, j))) {
+      // (without the policy, thr is astar and a >= astar holds here)
+      if (rule && (!GEN || all_orders || a >= rl(astar, j))) {
         const long long c1v = lane < P ? sh_c1[j][lane] : kInfCost;
         const int64_t c0 = q0 ? rl(c0_lane, q0) : kInfCost;
         const int64_t c1 = q1 ? rl(c1v, q1 - 1) : kInfCost;
@@ -464,7 +470,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
           p = q2;
           xs = 2;
         }
-        if (c.log_feas && c.explore > 0.0) {
+        if (GEN && c.log_feas && c.explore > 0.0) {
           // Exploration while logging: for a fixed pseudo-random share of
           // the pairs, an admitted action drawn uniformly (each admitted
           // series method at its order, or the direct path) replaces the
@@ -495,11 +501,10 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
             }
           }
         }
-        if (c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
+        if (GEN && c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
       }
       if (cd >= 0) {
-        const double Esel = rl(pmv, xs * P + p - 1);
-        if (c.use_tokens) t = t - need_fn(Esel, WRj, L, Wtot, c.eps_alg);
+        if (c.use_tokens) t = t - rl(needv, xs * P + p - 1);
       } else if (base_ok & (1ull << j)) {
         if (c.use_tokens) t = t + WRj;
         cd = BASE;
@@ -543,7 +548,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
     if (act) {
       code_out[off + b0 + lane] = (int8_t)code;
       p_out[off + b0 + lane] = (int8_t)((m_slow & bitl) ? my_p : 0);
-      if (feas_out) feas_out[off + b0 + lane] = (int16_t)((m_slow & bitl) ? my_feas : 0);
+      if (GEN && feas_out) feas_out[off + b0 + lane] = (int16_t)((m_slow & bitl) ? my_feas : 0);
     }
   }
   if (lane != 0) return;
@@ -719,11 +724,17 @@ hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const Tre
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
                          SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s) {
+  const bool gen = c.policy != 0 || c.log_feas != 0 || scores != nullptr || feas != nullptr;
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \
-    hipLaunchKernelGGL(decide_kernel<PP>, dim3((unsigned)(S + n_first)), dim3(64), 0, s, S,     \
-                       n_first, cur, qt, rt,                                                   \
-                       inv2h2, inv4h2, invh, nQ, c, code, porder, Gest, cnt, scores, feas);    \
+    if (gen)                                                                                   \
+      hipLaunchKernelGGL((decide_kernel<PP, true>), dim3((unsigned)(S + n_first)), dim3(64), 0, \
+                         s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code, porder, \
+                         Gest, cnt, scores, feas);                                             \
+    else                                                                                       \
+      hipLaunchKernelGGL((decide_kernel<PP, false>), dim3((unsigned)(S + n_first)), dim3(64),  \
+                         0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code,     \
+                         porder, Gest, cnt, scores, feas);                                     \
     break;
   switch (c.P) {
     GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)
