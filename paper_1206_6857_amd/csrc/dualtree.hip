@@ -642,6 +642,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       int8_t* code;
       int8_t* pord;
       SegCount *cnt, *incl;
+      double* prep;
       void* temp;
       float4* scores = nullptr;
       float* pfeat = nullptr;
@@ -652,6 +653,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         pord = BUF(int8_t, "p_ord", npair);
         cnt = BUF(SegCount, "seg_cnt", nseg);
         incl = BUF(SegCount, "seg_incl", nseg);
+        prep = BUF(double, "p_prep", 5 * npair);
         temp = BUF(char, "scan_temp", tb);
         if (use_policy) scores = BUF(float4, "p_scores", npair);
         if (log_pairs) {
@@ -666,7 +668,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         if (use_policy) DT_HIP(launch_policy_infer_pairs((int)npair, pp, pqt, prt, D, pmodel, scores, st));
         if (log_pairs) DT_HIP(launch_policy_features((int)npair, pp, pqt, prt, D, pfeat, st));
         DT_HIP(launch_decide((int)nseg, (int)nfirst, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,
-                             Gest, cnt, scores, pfeas, st));
+                             Gest, cnt, scores, pfeas, prep, (int)npair, st));
         DT_HIP(scan_counts((int)nseg, cnt, incl, temp, tb, st));
         kt.stop(st, 2 + (use_policy ? 1 : 0) + (log_pairs ? 1 : 0));
       }

@@ -83,10 +83,13 @@ struct LevelOffsets {
 // q_H2L << 8 (smallest admitted orders, 0 = none) where bestMethod is
 // reached, else 0.
 // n_first: entries of cur.first (every segment of at least kLongSegment pairs).
+// prep: scratch of 5 * npair doubles (the pair prepass), npair: the level's
+// pairs.
 hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
-                         SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s);
+                         SegCount* cnt, const float4* scores, int16_t* feas, double* prep,
+                         int npair, hipStream_t s);
 
 hipError_t scan_counts(int S, const SegCount* cnt, SegCount* incl, void* temp, size_t temp_bytes,
                        hipStream_t s);

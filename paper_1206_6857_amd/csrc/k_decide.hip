@@ -156,6 +156,35 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
   return v;
 }
 
+// Per pair of the level, all pairs at once: the token-independent values of
+// the pair that involve its nodes' boxes, in the same arithmetic as the walk
+// would form them.  prep is [5][npair]: W_R K(dmax), K(dmin), K(dmax),
+// exp(-dmin^2 / 4h^2) (the bounds' Gaussian factor), W_R.
+__global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel cur, TreeView qt,
+                                                        TreeView rt, const double* __restrict__ inv2h2,
+                                                        const double* __restrict__ inv4h2, int D,
+                                                        double* __restrict__ prep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npair) return;
+  const int sg = cur.seg[i];
+  const int h = cur.h[sg];
+  const int Q = cur.Q[sg];
+  const int R = cur.R[i];
+  double dmin2, dmax2;
+  box_dist2(qt.lo + (int64_t)Q * D, qt.hi + (int64_t)Q * D, rt.lo + (int64_t)R * D,
+            rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
+  const double i2 = inv2h2[h];
+  const double kmax = own_exp(-dmax2 * i2);
+  const double kmin = own_exp(-dmin2 * i2);
+  const double g = own_exp(-dmin2 * inv4h2[h]);
+  const double WR = rt.W[R];
+  prep[i] = WR * kmax;
+  prep[(int64_t)npair + i] = kmin;
+  prep[2 * (int64_t)npair + i] = kmax;
+  prep[3 * (int64_t)npair + i] = g;
+  prep[4 * (int64_t)npair + i] = WR;
+}
+
 // One wave per segment, 64 pairs at a time, one pair per lane.
 //
 // Every quantity of a pair that does not depend on the token is computed by
@@ -195,7 +224,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
                                                     double* __restrict__ Gest,
                                                     SegCount* __restrict__ cnt,
                                                     const float4* __restrict__ scores,
-                                                    int16_t* __restrict__ feas_out) {
+                                                    int16_t* __restrict__ feas_out,
+                                                    const double* __restrict__ prep, int npair) {
   constexpr double kSqrt2 = 1.4142135623730951;
   // The long segments first (listed in cur.first), then the others.
   const int b = blockIdx.x;
@@ -215,10 +245,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
     __builtin_amdgcn_s_setprio(2);
   else if (len >= kLongSegment)
     __builtin_amdgcn_s_setprio(1);
-  const int D = c.D;
-  const double* loQ = qt.lo + (int64_t)Q * D;
-  const double* hiQ = qt.hi + (int64_t)Q * D;
-  const double i2 = inv2h2[h], i4 = inv4h2[h], ih = invh[h];
+  const double ih = invh[h];
   const bool qleaf = qt.left[Q] < 0;
   const double Wtot = rt.W[0];  // total reference weight (the root's)
   const int64_t NQ = qt.count[Q];
@@ -228,30 +255,22 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   double* gest_at = Gest + (int64_t)h * nQ + Q;
   const double gest_in = *gest_at;
 
-  // Lower bound L over Q, summed in pair order.  The first 64 pairs' box
-  // distances and K(dmax) stay in registers for the decision pass.
+  // Lower bound L over Q, summed in pair order (each chunk's terms read one
+  // chunk ahead).
+  const double* p_lterm = prep;
+  const double* p_kmin = prep + npair;
+  const double* p_kmax = prep + 2 * (int64_t)npair;
+  const double* p_g = prep + 3 * (int64_t)npair;
+  const double* p_WR = prep + 4 * (int64_t)npair;
   double L = cur.Lp[s];
-  int R0 = 0;
-  double dmin2_0 = 0.0, dmax2_0 = 0.0, kmax_0 = 0.0, WR_0 = 0.0;
-  for (int b0 = 0; b0 < len; b0 += 64) {
-    const int n = len - b0 < 64 ? len - b0 : 64;
-    double lterm = 0.0;
-    if (lane < n) {
-      const int R = cur.R[off + b0 + lane];
-      double dmin2, dmax2;
-      box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
-      const double kmax = own_exp(-dmax2 * i2);
-      const double WR = rt.W[R];
-      lterm = WR * kmax;
-      if (b0 == 0) {
-        R0 = R;
-        dmin2_0 = dmin2;
-        dmax2_0 = dmax2;
-        kmax_0 = kmax;
-        WR_0 = WR;
-      }
+  {
+    double nx = lane < len ? p_lterm[off + lane] : 0.0;
+    for (int b0 = 0; b0 < len; b0 += 64) {
+      const int n = len - b0 < 64 ? len - b0 : 64;
+      const double lterm = nx;
+      if (b0 + 64 < len) nx = b0 + 64 + lane < len ? p_lterm[off + b0 + 64 + lane] : 0.0;
+      for (int j = 0; j < n; ++j) L = L + rl(lterm, j);
     }
-    for (int j = 0; j < n; ++j) L = L + rl(lterm, j);
   }
   if (c.mono && qt.wmin[Q] > L) L = qt.wmin[Q];
 
@@ -282,21 +301,11 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
 #pragma unroll
     for (int p = 0; p < P; ++p) pm0[p] = pm1[p] = pm2[p] = INFINITY;
     if (lane < n) {
-      int R;
-      double dmin2, dmax2, kmax;
-      if (b0 == 0) {
-        R = R0;
-        dmin2 = dmin2_0;
-        dmax2 = dmax2_0;
-        kmax = kmax_0;
-        WR = WR_0;
-      } else {
-        R = cur.R[off + b0 + lane];
-        box_dist2(loQ, hiQ, rt.lo + (int64_t)R * D, rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
-        kmax = own_exp(-dmax2 * i2);
-        WR = rt.W[R];
-      }
-      const double kmin = own_exp(-dmin2 * i2);
+      const int64_t pi = off + b0 + lane;
+      const int R = cur.R[pi];
+      WR = p_WR[pi];
+      const double kmax = p_kmax[pi];
+      const double kmin = p_kmin[pi];
       NR = rt.count[R];
       Rid = R;
       if (GEN && scores) {
@@ -308,11 +317,11 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         if (sc.w < sb) { kstar = 3; sb = sc.w; }
       }
       rleaf = rt.left[R] < 0 ? 1 : 0;
-      lterm = WR * kmax;
+      lterm = p_lterm[pi];
       fdval = 0.5 * (WR * (kmin + kmax));
       nd = need_fn(0.5 * (WR * (kmin - kmax)), WR, L, Wtot, c.eps_alg);
       if (c.use_fmm) {
-        const double g = own_exp(-dmin2 * i4);
+        const double g = p_g[pi];
         const double rR = rt.rinf[R] * ih;
         const double base_e = WR * g;
         double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY;
@@ -723,18 +732,21 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
 hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,
-                         SegCount* cnt, const float4* scores, int16_t* feas, hipStream_t s) {
+                         SegCount* cnt, const float4* scores, int16_t* feas, double* prep,
+                         int npair, hipStream_t s) {
+  hipLaunchKernelGGL(pair_prep_kernel, dim3((unsigned)ceil_div(npair, 256)), dim3(256), 0, s, npair,
+                     cur, qt, rt, inv2h2, inv4h2, c.D, prep);
   const bool gen = c.policy != 0 || c.log_feas != 0 || scores != nullptr || feas != nullptr;
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \
     if (gen)                                                                                   \
       hipLaunchKernelGGL((decide_kernel<PP, true>), dim3((unsigned)(S + n_first)), dim3(64), 0, \
                          s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code, porder, \
-                         Gest, cnt, scores, feas);                                             \
+                         Gest, cnt, scores, feas, prep, npair);                                \
     else                                                                                       \
       hipLaunchKernelGGL((decide_kernel<PP, false>), dim3((unsigned)(S + n_first)), dim3(64),  \
                          0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code,     \
-                         porder, Gest, cnt, scores, feas);                                     \
+                         porder, Gest, cnt, scores, feas, prep, npair);                        \
     break;
   switch (c.P) {
     GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)
