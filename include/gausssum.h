@@ -53,8 +53,8 @@ enum {
 /* How the series method is chosen for a node pair (Figure 6). */
 enum {
   GS_RULE = 0,        /* the paper's cost model */
-  GS_LEARNED = 1      /* the learned pair policy; every choice is still certified by
-                         the error bound, and the rule decides when it is not */
+  GS_LEARNED = 1      /* the learned pair policy: it chooses among the actions the
+                         error bound admits, so every choice is certified */
 };
 
 typedef struct gs_options {
@@ -109,7 +109,8 @@ typedef struct gs_stats {
   int64_t base_pair_evals;  /* point-pair kernel evaluations in base cases */
   int64_t frontier_peak;    /* largest frontier (pairs over all h) */
   int64_t policy_calls;     /* pairs on which the learned policy was consulted */
-  int64_t policy_fallbacks; /* of those, choices the bound rejected (rule used) */
+  int64_t policy_fallbacks; /* of those, pairs whose cheapest predicted action the
+                               bound did not admit (the cheapest admitted one taken) */
   double t_stage_ms, t_tree_ms, t_moments_ms, t_traverse_ms, t_work_ms, t_post_ms;
   double t_total_ms;        /* wall time of the last gauss_sum call */
   /* With kernel_timing = 1: device milliseconds and launch counts per kernel class,
@@ -204,10 +205,10 @@ gs_status gs_get_trace(gs_ctx* ctx, int64_t* n_records, int32_t* records);
  * paper calls rough.  With policy = GS_LEARNED a small network predicts, from
  * the pair's geometry only, the log2 cost in nanoseconds of four actions: DH,
  * DL and H2L at the smallest order their bound admits, and "recurse", the
- * cost-to-go of the direct path.  The cheapest predicted action is taken; a
- * series method only where its error bound admits an order (Lemmas 4-6, the
- * test the rule uses), otherwise the rule decides.  Theorem 2 therefore holds
- * whatever the network predicts.
+ * cost-to-go of the direct path.  The cheapest predicted of the admitted
+ * actions is taken: a series method is admitted where its error bound admits
+ * an order (Lemmas 4-6, the test the rule uses), recursion always.  Theorem 2
+ * therefore holds whatever the network predicts.
  *
  * Network: 16 features -> 64 ReLU -> 64 ReLU -> 4 outputs.  Parameter vector
  * (float, 5508): W1[64][16], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]; in
@@ -251,10 +252,11 @@ typedef struct gs_train_opts {
 void gs_default_train_opts(gs_train_opts* opts);
 
 /* Cost model of the policy's training targets (defaults: measured on one
- * MI355X).  Each logging call (log_pairs = 1) first recalibrates the model
- * from its own kernel timings (every cost whose kernels ran for at least
- * 0.2 ms), unless a model was set here: a caller's model is kept as given.
- * All fields must be >= 0. */
+ * MI355X).  Each logging call (log_pairs = 1) first recalibrates the
+ * work-type costs (dh, dl, h2l, base) from its own kernel timings, every one
+ * whose kernels ran for at least 0.05 ms; pair_ns is kept, since a logging
+ * call decides pairs at a higher cost than a plain one.  A model set here is
+ * kept as given.  All fields must be >= 0. */
 gs_status gs_policy_set_cost_model(gs_ctx* ctx, const gs_cost_model* cm);
 gs_status gs_policy_get_cost_model(gs_ctx* ctx, gs_cost_model* cm);
 

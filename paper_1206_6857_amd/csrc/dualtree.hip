@@ -763,6 +763,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     double* dh_part = nullptr;
     double* dl_part = nullptr;
     int32_t* dl_part_p = nullptr;
+    double* h2l_part = nullptr;
+    int32_t* h2l_part_p = nullptr;
     CHUNK_ALLOC(([&]() -> gs_status {
       if (fast) {
         // partial sums of the sliced DH and DL kernels
@@ -776,6 +778,10 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         if (used_slc[1]) {
           dl_part = BUF(double, "dl_part", used_slc[1] * series_terms(D, P));
           dl_part_p = BUF(int32_t, "dl_part_p", used_slc[1]);
+        }
+        if (used_grp[2]) {
+          h2l_part = BUF(double, "h2l_part", used_grp[2] * series_terms(D, P));
+          h2l_part_p = BUF(int32_t, "h2l_part_p", used_grp[2]);
         }
       }
       for (int x = 1; x < 3; ++x) {
@@ -892,8 +898,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       }
       {
         KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, st);
-        DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
-        kh.stop(st, 1);
+        if (fast) {
+          DT_HIP(launch_h2l_fast(D, P, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, h2l_part,
+                                 h2l_part_p, st));
+          kh.stop(st, sg[2].n ? 2 : 0);
+        } else {
+          DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
+          kh.stop(st, 1);
+        }
       }
       KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, st);
       int dh_launches = 0;

@@ -89,6 +89,13 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slice
                           const NodeView& qt, const NodeView& rt, const double* xr_perm,
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
                           double* part, int32_t* part_p, hipStream_t s);
+// H2L of the whole traversal: one partial coefficient vector per group (part:
+// groups * C doubles, part_p: groups orders), then per (h, Q) run of the
+// sorted groups g their sum in order into lco.
+hipError_t launch_h2l_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+                           const NodeView& qt, const NodeView& rt, const double* M, const double* sc,
+                           int nQ, double* lco, int32_t* pL, double* part, int32_t* part_p,
+                           hipStream_t s);
 // Size of the DL partial coefficient vectors (C(D+P-1, D)).
 int series_terms(int D, int P);
 // Post-pass in one launch (grid: query nodes x bandwidths, internal nodes

@@ -297,6 +297,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
     int NR = 0, rleaf = 0, Rid = 0;
     long long c3 = 0;
     int kstar = 0;  // learned policy: cheapest predicted action (3 = recurse)
+    float4 psc = make_float4(0.f, 0.f, 0.f, 0.f);  // its predicted costs
     double pm0[P], pm1[P], pm2[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) pm0[p] = pm1[p] = pm2[p] = INFINITY;
@@ -311,6 +312,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
       if (GEN && scores) {
         // ties go to the earlier of DH, DL, H2L, recurse
         const float4 sc = scores[off + b0 + lane];
+        psc = sc;
         float sb = sc.x;
         if (sc.y < sb) { kstar = 1; sb = sc.y; }
         if (sc.z < sb) { kstar = 2; sb = sc.z; }
@@ -358,15 +360,15 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         astar = all_orders ? -INFINITY : division_threshold(mstar, Wtot);
         thr = astar;
         if (learned) {
-          // the preferred series method is admitted at some order exactly
-          // when maxerr reaches its smallest bound; recursing never needs
-          // the order search
+          // some series method is admitted at some order exactly when
+          // maxerr reaches the smallest of the bounds; a preferred recursion
+          // needs no order search
           if (kstar == 3) {
             thr = INFINITY;
           } else {
-            const double mk = kstar == 0 ? pm0[P - 1] : kstar == 1 ? pm1[P - 1] : pm2[P - 1];
-            const double ak = division_threshold(mk, Wtot);
-            thr = ak < astar ? ak : astar;
+            double mk = pm0[P - 1] < pm1[P - 1] ? pm0[P - 1] : pm1[P - 1];
+            mk = pm2[P - 1] < mk ? pm2[P - 1] : mk;
+            thr = division_threshold(mk, Wtot);
           }
         }
       }
@@ -439,20 +441,31 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
       int cd = -1, p = 0, xs = 0;
       bool rule = c.use_fmm != 0;
       if (learned) {
-        // The learned policy: its cheapest predicted action, a series
-        // method only at an order its bound admits, else the rule decides.
+        // The learned policy: the cheapest predicted of the admitted actions
+        // (each series method whose bound admits an order, at its smallest
+        // such order, and recursion, always admitted); ties go to the earlier
+        // of DH, DL, H2L, recurse.  A fallback is counted when the overall
+        // cheapest prediction was not admitted.
+        rule = false;
         const int kj = rl(kstar, j);
-        if (kj == 3) {
-          rule = false;
-        } else {
-          const int qk = kj == 0 ? q0 : kj == 1 ? q1 : q2;
-          if (qk) {
-            cd = DH + kj;
-            p = qk;
-            xs = kj;
-            rule = false;
-          } else {
-            ++nfall;
+        if (kj != 3) {
+          const float sk[4] = {__int_as_float(rl(__float_as_int(psc.x), j)),
+                               __int_as_float(rl(__float_as_int(psc.y), j)),
+                               __int_as_float(rl(__float_as_int(psc.z), j)),
+                               __int_as_float(rl(__float_as_int(psc.w), j))};
+          const int qv[3] = {q0, q1, q2};
+          int best = 3;
+          float sb = sk[3];
+          for (int k = 2; k >= 0; --k)
+            if (qv[k] && sk[k] <= sb) {
+              best = k;
+              sb = sk[k];
+            }
+          if (best != kj) ++nfall;
+          if (best < 3) {
+            cd = DH + best;
+            p = qv[best];
+            xs = best;
           }
         }
       }

@@ -121,7 +121,8 @@ struct DHNest {
     } else {
       inner = DHNest<D, P, d + 1, rem - a, 0, A..., a>::run(H, M);
     }
-    const double v = a == 0 ? inner : H[d][a] * inner;
+    // (where H[d][0] is the constant 1 the compiler drops the product)
+    const double v = H[d][a] * inner;
     if constexpr (a + 1 < rem)
       return v + DHNest<D, P, d, rem, a + 1, A...>::run(H, M);
     else
@@ -295,8 +296,86 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
   if (lane == 0) part_p[i] = pmax;
 }
 
+// H2L (Lemma 1): B_b(Q) += (-1)^|b| / b! sum_{|a|<p} A_a h_{a+b}(t), t = (x_Q - x_R) s,
+// one wave per H2L group (its entries in order), lanes over b.  Per entry the
+// 1-D Hermite polynomials of orders < 2P-1 go to LDS; lane b forms
+// g_d[k] = s^k H_{k+b_d}(t_d) (k < P) and the nested sum over a of
+// M_a prod_d g_d[a_d] (M the raw moments, so A_a = M_a s^|a|), times
+// exp(-|t|^2).  part[group][b] holds the group's sum before the 1/b! scale.
+template <int D, int P>
+__global__ __launch_bounds__(kW) void h2l_fast_kernel(
+    const int4* __restrict__ grp, int ng, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
+    const double* __restrict__ M, const double* __restrict__ sc, double* __restrict__ part,
+    int32_t* __restrict__ part_p) {
+  static constexpr MultiIndex<D, P> mi{};
+  constexpr int C = MultiIndex<D, P>::C;
+  constexpr int NB = (C + kW - 1) / kW;
+  constexpr int HT = 2 * P - 1;
+  __shared__ double Ht[D][HT];
+  const int i = blockIdx.x;
+  if (i >= ng) return;
+  const int lane = threadIdx.x;
+  const int4 gr = grp[i];
+  const int h = gr.x, Q = gr.y;
+  const double s = sc[h];
+  double spow[P];
+  spow[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k < P; ++k) spow[k] = spow[k - 1] * s;
+  int bd[NB][D], bdeg[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = u * kW + lane < C ? u * kW + lane : 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) bd[u][d] = mi.a[b][d];
+    bdeg[u] = u * kW + lane < C ? mi.deg[b] : P;  // lanes past C never contribute
+  }
+  double acc[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) acc[u] = 0.0;
+  int pmax = 0;
+  const double* cQ = qt.ctr + (int64_t)Q * D;
+  for (int e = gr.z; e < gr.z + gr.w; ++e) {
+    const int R = ent[e] >> 4, p = ent[e] & 15;
+    pmax = p > pmax ? p : pmax;
+    const double* cR = rt.ctr + (int64_t)R * D;
+    double tt = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double t = (cQ[d] - cR[d]) * s;
+      tt += t * t;
+    }
+    __syncthreads();  // the previous entry's reads of Ht are done
+    if (lane < D) {
+      const double t = (cQ[lane] - cR[lane]) * s;
+      double H[HT];
+      hermite_polys<HT>(t, H);
+#pragma unroll
+      for (int k = 0; k < HT; ++k) Ht[lane][k] = H[k];
+    }
+    __syncthreads();
+    const double ex = exp(-tt);
+    const double* m = M + (int64_t)R * C;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      double g[D][P];
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < P; ++k) g[d][k] = spow[k] * Ht[d][k + bd[u][d]];
+      const double v = dh_sum<D, P>(p, g, m) * ex;
+      if (bdeg[u] < p) acc[u] += (bdeg[u] & 1) ? -v : v;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (u * kW + lane < C) part[(int64_t)i * C + u * kW + lane] = acc[u];
+  if (lane == 0) part_p[i] = pmax;
+}
+
 // Per (h, Q) run of the sorted DL groups: the slices of its groups summed in
-// order, scaled by 1/b! into lco; lanes over coefficients.
+// order, scaled by 1/b! into lco; lanes over coefficients.  first == nullptr:
+// one partial vector per group, at the group's index (H2L).
 template <int D, int P>
 __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
     SortedGroups g, const int2* __restrict__ first, const double* __restrict__ part,
@@ -314,7 +393,7 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
   for (int u = 0; u < (C + kW - 1) / kW; ++u) sum[u] = 0.0;
   int pmax = 0;
   for (int j = i; j < g.n && (j == i || g.key[j] == g.key[j - 1]); ++j) {
-    const int2 f = first[g.order[j]];
+    const int2 f = first ? first[g.order[j]] : make_int2(g.order[j], 1);
     for (int k = f.x; k < f.x + f.y; ++k) {
       const double* v = part + (int64_t)k * C;
 #pragma unroll
@@ -456,6 +535,25 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slice
 }
 
 int series_terms(int D, int P) { return cbinom(D + P - 1, D); }
+
+hipError_t launch_h2l_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+                           const NodeView& qt, const NodeView& rt, const double* M, const double* sc,
+                           int nQ, double* lco, int32_t* pL, double* part, int32_t* part_p,
+                           hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+#define X(d, p)                                                                                   \
+  if (D == d && P == p) {                                                                         \
+    hipLaunchKernelGGL((h2l_fast_kernel<d, p>), dim3((unsigned)g.n), dim3(kW), 0, s, g.grp, g.n,   \
+                       ent, qt, rt, M, sc, part, part_p);                                         \
+    hipLaunchKernelGGL((dl_reduce_kernel<d, p>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),   \
+                       dim3(kW * kWavesPerBlock), 0, s, g, (const int2*)nullptr, part, part_p, nQ, \
+                       lco, pL);                                                                  \
+    return hipGetLastError();                                                                     \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_leaf_post_fast(int D, int P, const NodeView& qt, const int32_t* parent, int nQ,
                                  int n_h, int Mq, const double* sc, const double* xq_perm,

@@ -126,14 +126,15 @@ gs_status stage_records(gs_ctx_base* ctx, const float* rec, int64_t n, const cha
 }  // namespace
 
 void policy_default_costs(PolicyState& ps) {
-  // Measured on one MI355X (D=3, 100k points, 10 bandwidths, leaf 64): the
-  // kernel time of each work type over one sweep divided by its units.  A
-  // logged call (log_pairs) replaces them by its own measurements.
-  ps.c_pair = 0.56;
-  ps.c_dh = 4.4e-3;
-  ps.c_dl = 3.2e-3;
-  ps.c_h2l = 1.8e-3;
-  ps.c_base = 3.3e-4;
+  // Measured on one MI355X (D=3, 100k points, 10 bandwidths, leaf 128): the
+  // kernel time of each work type over one sweep with the rule divided by its
+  // units (c_h2l: the H2L kernel's per-term work equals DH's).  A logged call
+  // (log_pairs) replaces the work-type costs by its own measurements.
+  ps.c_pair = 0.9;
+  ps.c_dh = 3.0e-4;
+  ps.c_dl = 3.9e-3;
+  ps.c_h2l = 3.0e-4;
+  ps.c_base = 2.65e-4;
 }
 
 gs_status policy_device_model(gs_ctx_base* ctx, PolicyDevModel* m) {
@@ -160,10 +161,12 @@ gs_status policy_device_model(gs_ctx_base* ctx, PolicyDevModel* m) {
   return GS_OK;
 }
 
-// Measured cost model: each unit cost becomes this call's kernel time of the
-// work type divided by its units (from the trace), where the type's kernels
-// ran long enough (>= 0.2 ms) for launch latency not to dominate; the other
-// unit costs are kept.
+// Measured cost model: each work type's unit cost becomes this call's kernel
+// time of the type divided by its units (from the trace), where the type's
+// kernels ran long enough (>= 0.05 ms) for launch latency not to dominate;
+// the other unit costs are kept.  The cost of deciding a pair is not taken
+// from a logged call: logging computes every pair's features and admitted
+// orders, which a call that only decides does not.
 void policy_calibrate_costs(gs_ctx_base* ctx, int D) {
   PolicyState& ps = ctx->policy;
   const HostTree& rt = ctx->host_tree[0];
@@ -184,8 +187,8 @@ void policy_calibrate_costs(gs_ctx_base* ctx, int D) {
   const gs_stats& S = ctx->stats;
   const double ms[5] = {S.k_ms[GS_K_DECIDE], S.k_ms[GS_K_DH], S.k_ms[GS_K_DL], S.k_ms[GS_K_H2L], S.k_ms[GS_K_BASE]};
   double* c[5] = {&ps.c_pair, &ps.c_dh, &ps.c_dl, &ps.c_h2l, &ps.c_base};
-  for (int k = 0; k < 5; ++k)
-    if (u[k] > 0.0 && ms[k] >= 0.2) *c[k] = ms[k] * 1e6 / u[k];
+  for (int k = 1; k < 5; ++k)
+    if (u[k] > 0.0 && ms[k] >= 0.05) *c[k] = ms[k] * 1e6 / u[k];
 }
 
 // Records of the last logged traversal, from ctx->trace and the per-row

@@ -37,6 +37,12 @@ CASES = [
     ("d2_leaf64_ragged", 2, 1001, None, [0.02, 0.2], 64, "dito"),
     ("d2_plimit5_generic", 2, 1200, None, [0.03, 0.1, 0.3], 32, "dito", 5),
     ("d4_table", 4, 1000, None, [0.05, 0.2, 1.0], 32, "dito"),
+    # one series method at a time (bestMethod restricted by fmm_mask), so that
+    # each expansion kernel carries every series prune of the run
+    ("d2_h2l_only", 2, 1500, None, [0.03, 0.1, 0.3, 1.0], 32, "dito", 0, 4),
+    ("d3_h2l_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 4),
+    ("d3_dl_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 2),
+    ("d3_dh_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 1),
 ]
 
 
@@ -49,13 +55,19 @@ def _inputs(D, N, M, seed):
 def test_dualtree_parity(case):
     name, D, N, M, hs, leaf, method = case[:7]
     plimit = case[7] if len(case) > 7 else 0
+    mask = case[8] if len(case) > 8 else 7
     banner("dualtree", name)
     r, w, q = _inputs(D, N, M, 70 + D)
     hs = np.array(hs)
     c = ctx()
-    G = c.gauss_sum(q, r, w, hs, 0.01, method=method, leaf_size=leaf, keep_trace=1, plimit=plimit)
+    G = c.gauss_sum(q, r, w, hs, 0.01, method=method, leaf_size=leaf, keep_trace=1, plimit=plimit,
+                    fmm_mask=mask)
     ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, method=method, trace=True,
-                      plimit=plimit or None)
+                      plimit=plimit or None, fmm_mask=mask)
+    if mask != 7:
+        # the restricted method carries the series prunes of the run
+        code = {1: 1, 2: 2, 4: 3}[mask]
+        assert ref.counts[:, code].sum() > 20, ref.counts.sum(axis=0)
 
     # tree, bit-exact
     for which, t in ((0, ref.rtree), (1, ref.qtree)):
