@@ -80,6 +80,32 @@ def need(E, W_R, L, W, eps_alg):
     return (W * E) / (eps_alg * L) - W_R
 
 
+def sphere_rect_dist2(loQ, hiQ, loR, hiR, cQ, cR, radQ, radR):
+    """(dmin^2, dmax^2) from both the bounding boxes and the bounding balls
+    about the box centres (radius rad = max |x - c|_2): with
+    dc = |c_Q - c_R|_2, every point pair is at least dc - rad_Q - rad_R and at
+    most dc + rad_Q + rad_R apart, so the tighter of each pair of bounds
+    holds.  Fixed operation order (squares summed in d, sqrt, then
+    ((dc - rad_Q) - rad_R) and ((dc + rad_Q) + rad_R)) for bit-exact
+    reproduction."""
+    smin, smax = box_dist2(loQ, hiQ, loR, hiR)
+    d2 = 0.0
+    for d in range(len(cQ)):
+        diff = cQ[d] - cR[d]
+        d2 = d2 + diff * diff
+    dc = math.sqrt(d2)
+    gap = (dc - radQ) - radR
+    if gap > 0.0:
+        g2 = gap * gap
+        if g2 > smin:
+            smin = g2
+    far = (dc + radQ) + radR
+    f2 = far * far
+    if f2 < smax:
+        smax = f2
+    return smin, smax
+
+
 def box_dist2(loQ, hiQ, loR, hiR):
     """(dmin^2, dmax^2) between two boxes, summed over d in order (section 5:
     the distance bounds come from the bounding boxes)."""

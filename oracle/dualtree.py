@@ -59,7 +59,7 @@ import math
 
 import numpy as np
 
-from .bounds import best_method, box_dist2, e_fd, feasible_orders, need
+from .bounds import best_method, box_dist2, e_fd, feasible_orders, need, sphere_rect_dist2
 from .exp64 import exp64
 from .kdtree import attach_moments, build_kdtree
 from .multiindex import num_terms, plimit_for
@@ -69,6 +69,7 @@ FD, DH, DL, H2L, BASE, SPLIT = 0, 1, 2, 3, 4, 5
 CODE = {"DH": DH, "DL": DL, "H2L": H2L}
 NAME = {DH: "DH", DL: "DL", H2L: "H2L"}
 METHODS = ("dito", "dfdo", "dfd")
+NODE_BOUNDS = ("box", "sphere_rect")
 
 
 class Result:
@@ -81,7 +82,7 @@ class CertificationError(AssertionError):
 
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
              method="dito", mono=None, trace=False, fmm_mask=7, replay=None,
-             record_feasible=False):
+             record_feasible=False, node_bounds="box"):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
     decision trace: a list of (h_index, level, Q, R, code, p) tuples.
 
@@ -94,7 +95,10 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     when, and only when, its bookkeeping matches.
     record_feasible: keep {(h_index, level, Q, R): {method: p}} of the
     smallest admitted order of every series method wherever bestMethod is
-    reached (res.feasible)."""
+    reached (res.feasible).
+    node_bounds: "box" (section 5: distances between bounding boxes) or
+    "sphere_rect" (the tighter of the box and the bounding-ball bounds,
+    bounds.sphere_rect_dist2)."""
     xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
     if mono is None:
         mono = xq is xr
@@ -103,6 +107,8 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     hs = np.atleast_1d(np.asarray(hs, dtype=np.float64))
     if method not in METHODS:
         raise ValueError(method)
+    if node_bounds not in NODE_BOUNDS:
+        raise ValueError(node_bounds)
     D = xr.shape[1]
     P = plimit if plimit else plimit_for(D)
     rt = build_kdtree(xr, w, leaf_size)
@@ -116,6 +122,7 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.trace = [] if trace else None
     res.counts = np.zeros((len(hs), 6), dtype=np.int64)
     res.fmm_mask = fmm_mask
+    res.node_bounds = node_bounds
     res.replay = replay
     res.feasible = {} if record_feasible else None
     for k, h in enumerate(hs):
@@ -146,7 +153,11 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
             geo = []
             L = Lp
             for R in Rs:
-                dmin2, dmax2 = box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])
+                if res.node_bounds == "box":
+                    dmin2, dmax2 = box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])
+                else:
+                    dmin2, dmax2 = sphere_rect_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R], qt.ctr[Q],
+                                                     rt.ctr[R], qt.rad[Q], rt.rad[R])
                 kmax = exp64(-dmax2 * inv_2h2)
                 geo.append((dmin2, kmax))
                 L = L + float(rt.W[R]) * kmax

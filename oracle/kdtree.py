@@ -29,6 +29,8 @@ Pinned by tests/test_oracle_tree.py: brute-force box/radius/weight checks,
 leaf-aligned split property, permutation invariance of the tree geometry.
 """
 
+import math
+
 import numpy as np
 
 from .multiindex import num_terms
@@ -88,6 +90,7 @@ def build_kdtree(x, w, leaf_size):
     t.hi = np.empty((nn, D))
     t.ctr = np.empty((nn, D))
     t.rinf = np.empty(nn)
+    t.rad = np.empty(nn)
     t.W = np.empty(nn)
     t.wmin = np.empty(nn)
     for i in range(nn):
@@ -97,6 +100,12 @@ def build_kdtree(x, w, leaf_size):
         t.hi[i] = xs.max(axis=0)
         t.ctr[i] = 0.5 * (t.lo[i] + t.hi[i])
         t.rinf[i] = float(np.max(np.abs(xs - t.ctr[i])))
+        # Euclidean radius about the box centre: squares summed in d order
+        s2 = np.zeros(len(pts))
+        for d in range(D):
+            diff = xs[:, d] - t.ctr[i, d]
+            s2 = s2 + diff * diff
+        t.rad[i] = math.sqrt(float(np.max(s2)))
         t.wmin[i] = float(np.min(w[pts]))
     for i in range(nn - 1, -1, -1):
         if t.left[i] < 0:

@@ -118,6 +118,44 @@ def test_box_distance_bounds_brute_force(D):
         assert math.sqrt(d2.min()) - math.sqrt(dmin2) <= np.linalg.norm(cell) + 1e-12
 
 
+@pytest.mark.parametrize("D", [2, 3, 8])
+def test_sphere_rect_bounds_brute_force(D):
+    """On node pairs of a real tree: the sphere-rectangle bounds enclose the
+    true closest and farthest point pairs (brute force over the points), and
+    are never looser than the box bounds."""
+    from oracle.kdtree import build_kdtree
+    from paper_1206_6857_amd.datagen import mixture
+    x, w, _ = mixture((45, D), 700, D, 3, (0.02, 0.2))
+    t = build_kdtree(x, w, 24)
+    rng = np.random.default_rng(46 + D)
+    tighter_min = tighter_max = 0
+    for _ in range(60):
+        a, b = rng.integers(0, t.n_nodes, 2)
+        pa, pb = x[t.perm[t.begin[a]:t.end[a]]], x[t.perm[t.begin[b]:t.end[b]]]
+        d2 = ((pa[:, None, :] - pb[None, :, :]) ** 2).sum(-1)
+        smin, smax = B.sphere_rect_dist2(t.lo[a], t.hi[a], t.lo[b], t.hi[b], t.ctr[a], t.ctr[b],
+                                         t.rad[a], t.rad[b])
+        bmin, bmax = B.box_dist2(t.lo[a], t.hi[a], t.lo[b], t.hi[b])
+        assert d2.min() >= smin * (1 - 1e-12) - 1e-15
+        assert d2.max() <= smax * (1 + 1e-12)
+        assert smin >= bmin and smax <= bmax
+        tighter_min += smin > bmin
+        tighter_max += smax < bmax
+    assert tighter_max > 0   # the ball bound is not always the box bound
+
+
+def test_node_radius_is_the_largest_distance_to_the_centre():
+    from oracle.kdtree import build_kdtree
+    from paper_1206_6857_amd.datagen import mixture
+    x, w, _ = mixture((47, 3), 500, 3, 3, (0.02, 0.2))
+    t = build_kdtree(x, w, 16)
+    for i in range(t.n_nodes):
+        xs = x[t.perm[t.begin[i]:t.end[i]]]
+        want = max(math.sqrt(math.fsum((v - c) ** 2 for v, c in zip(row, t.ctr[i]))) for row in xs)
+        assert abs(t.rad[i] - want) <= 1e-15 * max(1.0, want)
+        assert t.rad[i] <= math.sqrt(3) * t.rinf[i] * (1 + 1e-15) and t.rad[i] >= t.rinf[i]
+
+
 def test_best_method_orders_and_ties():
     # Figure 6: first minimum in the order DH, DL, H2L, DIRECT
     name, p, E = B.best_method(2, 8, 1e9, 1.0, 1.0, 0.1, 0.1, 2, 2)

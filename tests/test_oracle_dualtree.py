@@ -28,6 +28,19 @@ def test_theorem2_monochromatic(D, n, method):
     assert np.all(rel <= 0.01), rel
 
 
+@pytest.mark.parametrize("D,n", [(2, 1200), (3, 1200), (8, 800)])
+def test_theorem2_sphere_rect_bounds(D, n):
+    """Theorem 2 with the sphere-rectangle node bounds, which never resolve
+    fewer pairs than the box bounds' traversal of the same input."""
+    x, w, _ = mixture((13, D), n, D, 4, (0.02, 0.1), weights=(0.5, 1.5))
+    hs = [0.01, 0.05, 0.2, 1.0]
+    res = DT.dualtree(x, x, w, hs, 0.01, leaf_size=32, node_bounds="sphere_rect")
+    rel = _max_rel(res.G, x, x, w, hs)
+    assert np.all(rel <= 0.01), rel
+    box = DT.dualtree(x, x, w, hs, 0.01, leaf_size=32)
+    assert res.counts.sum() <= box.counts.sum()
+
+
 @pytest.mark.parametrize("D", [2, 3])
 def test_theorem2_bichromatic(D):
     r, w, q = mixture((12, D), 1500, D, 4, (0.02, 0.1), weights=(0.5, 1.5), m_queries=700)
