@@ -215,6 +215,17 @@ def main():
     result["pairs"] = {k: int(pc[:, i].sum()) for i, k in enumerate(["FD", "DH", "DL", "H2L", "BASE", "SPLIT"])}
     result["base_pair_evals_frac"] = base_evals / args.steps / pair_evals
 
+    if method_used == "dualtree":
+        # Sphere-rectangle node bounds (tighter node-pair distances), same
+        # workload and leaf size.
+        t_sr, _, _, ev_sr, st_sr = run("dualtree", args.steps, args.warmup, leaf_size=leaf, autotune=0,
+                                       node_bounds="sphere_rect")
+        pc_sr = ctx.pair_counts(n_h)
+        result["sphere_rect_bounds"] = {
+            "ms_per_step": t_sr * 1e3, "value": pair_evals / t_sr, "speedup_vs_box": t_dt / t_sr,
+            "pairs_decided": int(pc_sr.sum()), "pairs_decided_box": int(pc.sum()),
+            "base_pair_evals_frac": int(ev_sr[0]) / args.steps / pair_evals}
+
     if not args.no_learned and method_used == "dualtree":
         # The learned pair policy, trained on another draw of the same
         # workload (logging and training are parameter selection, not timed).

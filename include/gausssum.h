@@ -96,8 +96,13 @@ typedef struct gs_options {
                                each once per workload signature (dimension, sizes, the
                                bandwidth range, eps, method options); the choice is
                                cached in the context.  Ignored with keep_trace. */
-  int32_t reserved2;
+  int32_t node_bounds;      /* GS_BOUNDS_BOX (default): node-pair distance bounds from
+                               the bounding boxes (section 5); GS_BOUNDS_SPHERE_RECT:
+                               the tighter of those and the bounds from the nodes'
+                               bounding balls about the box centres */
 } gs_options;
+
+enum { GS_BOUNDS_BOX = 0, GS_BOUNDS_SPHERE_RECT = 1 };
 
 typedef struct gs_stats {
   int32_t struct_size;      /* set by the caller to sizeof(gs_stats) */
@@ -185,11 +190,12 @@ const char* gs_last_error(gs_ctx* ctx);
  *   perm[n_points]   original point index at each tree position
  *   begin/count/left[n_nodes]  point range and left child (-1 for a leaf; the
  *                    right child is left+1); nodes are numbered breadth first
- *   lo/hi/ctr[n_nodes][D], rinf/W/wmin[n_nodes] as defined in the tree builder */
+ *   lo/hi/ctr[n_nodes][D], rinf/W/wmin[n_nodes] as defined in the tree builder
+ *   rad[n_nodes]     Euclidean radius about ctr (computed when the call used
+ *                    node_bounds = GS_BOUNDS_SPHERE_RECT, else 0) */
 gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_points,
-                      int32_t* perm, int32_t* begin, int32_t* count, int32_t* left,
-                      double* lo, double* hi, double* ctr, double* rinf, double* W,
-                      double* wmin);
+                      int32_t* perm, int32_t* begin, int32_t* count, int32_t* left, double* lo,
+                      double* hi, double* ctr, double* rinf, double* W, double* wmin, double* rad);
 
 /* Decision trace of the last call made with keep_trace = 1: one record per
  * decided node pair, int32 [n][6] = (bandwidth index, level, Q node, R node,

@@ -90,7 +90,7 @@ class Context:
         method ('dualtree', 'exhaustive', 'dfd', 'dfdo'), policy ('rule',
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
         keep_trace, log_pairs, log_explore, blocking, fmm_mask, kernel_timing,
-        h_chunk, max_frontier."""
+        h_chunk, max_frontier, node_bounds ('box', 'sphere_rect')."""
         lib = _lib.load()
         same = queries is refs
         r = _Arr(refs)
@@ -118,6 +118,8 @@ class Context:
                 v = _lib.METHODS[v] if isinstance(v, str) else int(v)
             elif k == "policy":
                 v = _lib.POLICIES[v] if isinstance(v, str) else int(v)
+            elif k == "node_bounds":
+                v = _lib.NODE_BOUNDS[v] if isinstance(v, str) else int(v)
             if not hasattr(opt, k):
                 raise TypeError("unknown option %r" % k)
             setattr(opt, k, v)
@@ -144,13 +146,13 @@ class Context:
         """Tree arrays of the last call made with keep_trace=1 (gs_get_tree)."""
         lib = _lib.load()
         nn, npnt = ctypes.c_int64(), ctypes.c_int64()
-        self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt), *([None] * 10)))
+        self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt), *([None] * 11)))
         n, p = nn.value, npnt.value
         t = {"perm": np.zeros(p, np.int32), "begin": np.zeros(n, np.int32),
              "count": np.zeros(n, np.int32), "left": np.zeros(n, np.int32),
              "lo": np.zeros((n, D)), "hi": np.zeros((n, D)), "ctr": np.zeros((n, D)),
-             "rinf": np.zeros(n), "W": np.zeros(n), "wmin": np.zeros(n)}
-        order = ["perm", "begin", "count", "left", "lo", "hi", "ctr", "rinf", "W", "wmin"]
+             "rinf": np.zeros(n), "W": np.zeros(n), "wmin": np.zeros(n), "rad": np.zeros(n)}
+        order = ["perm", "begin", "count", "left", "lo", "hi", "ctr", "rinf", "W", "wmin", "rad"]
         self._check(lib.gs_get_tree(self._h, which, ctypes.byref(nn), ctypes.byref(npnt),
                                     *[t[k].ctypes.data for k in order]))
         return t

@@ -16,6 +16,8 @@ GS_RULE, GS_LEARNED = 0, 1
 METHODS = {"dualtree": GS_DUALTREE, "dito": GS_DUALTREE, "exhaustive": GS_EXHAUSTIVE,
            "dfd": GS_DFD, "dfdo": GS_DFDO}
 POLICIES = {"rule": GS_RULE, "learned": GS_LEARNED}
+GS_BOUNDS_BOX, GS_BOUNDS_SPHERE_RECT = 0, 1
+NODE_BOUNDS = {"box": GS_BOUNDS_BOX, "sphere_rect": GS_BOUNDS_SPHERE_RECT}
 STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_EDEVICE",
                 -4: "GS_EOVERFLOW", -5: "GS_EINTERNAL"}
 
@@ -42,7 +44,7 @@ class GsOptions(ctypes.Structure):
                 ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
                 ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
                 ("log_explore", ctypes.c_double), ("autotune", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("node_bounds", ctypes.c_int32)]
 
 
 class GsCostModel(ctypes.Structure):
@@ -108,7 +110,7 @@ def load():
     lib.gs_get_pair_counts.restype = i32
     lib.gs_last_error.argtypes = [P]
     lib.gs_last_error.restype = ctypes.c_char_p
-    lib.gs_get_tree.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)] + [P] * 10
+    lib.gs_get_tree.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)] + [P] * 11
     lib.gs_get_tree.restype = i32
     lib.gs_get_trace.argtypes = [P, ctypes.POINTER(i64), P]
     lib.gs_get_trace.restype = i32

@@ -275,7 +275,7 @@ gs_status gs_get_pair_counts(gs_ctx* ctx, int64_t* counts) {
 
 gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_points,
                       int32_t* perm, int32_t* begin, int32_t* count, int32_t* left, double* lo,
-                      double* hi, double* ctr, double* rinf, double* W, double* wmin) {
+                      double* hi, double* ctr, double* rinf, double* W, double* wmin, double* rad) {
   if (!ctx || which < 0 || which > 1) return GS_EINVAL;
   const HostTree& t = ctx->host_tree[which];
   if (!t.valid) GS_FAIL(ctx, GS_EINVAL, "no tree kept: call gauss_sum with keep_trace = 1 first");
@@ -294,6 +294,12 @@ gs_status gs_get_tree(gs_ctx* ctx, int32_t which, int64_t* n_nodes, int64_t* n_p
   cp(rinf, t.rinf);
   cp(W, t.W);
   cp(wmin, t.wmin);
+  if (rad) {
+    if (t.rad.size() == (size_t)t.n_nodes)
+      cp(rad, t.rad);
+    else
+      std::fill(rad, rad + t.n_nodes, 0.0);
+  }
   return GS_OK;
 }
 
@@ -452,8 +458,8 @@ static std::string autotune_key(const gs_options& o, int D, bool mono, int64_t M
     hmax = std::max(hmax, h);
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d/%ld/%ld/%zu/%ld/%ld/%ld", o.method, o.policy, o.plimit,
-                o.fmm_mask, D, mono ? 1 : 0, std::lround(2.0 * std::log2((double)M)),
+  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d/%d/%ld/%ld/%zu/%ld/%ld/%ld", o.method, o.policy,
+                o.plimit, o.fmm_mask, o.node_bounds, D, mono ? 1 : 0, std::lround(2.0 * std::log2((double)M)),
                 std::lround(2.0 * std::log2((double)N)), hs.size(), std::lround(4.0 * std::log10(hmin)),
                 std::lround(4.0 * std::log10(hmax)), std::lround(8.0 * std::log10(eps)));
   return buf;
@@ -482,6 +488,8 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     GS_FAIL(ctx, GS_EINVAL, "eps must be in (0, 1)");
   if (opt.leaf_size < 1 || opt.leaf_size > 1024) GS_FAIL(ctx, GS_EINVAL, "leaf_size must be in [1, 1024]");
   if (opt.h_chunk < 0) GS_FAIL(ctx, GS_EINVAL, "h_chunk must be >= 0");
+  if (opt.node_bounds != GS_BOUNDS_BOX && opt.node_bounds != GS_BOUNDS_SPHERE_RECT)
+    GS_FAIL(ctx, GS_EINVAL, "node_bounds must be GS_BOUNDS_BOX or GS_BOUNDS_SPHERE_RECT");
   if (opt.max_frontier < 0) GS_FAIL(ctx, GS_EINVAL, "max_frontier must be >= 0");
   if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");

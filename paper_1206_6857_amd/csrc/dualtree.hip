@@ -287,6 +287,7 @@ static gs_status build_tree(gs_ctx_base* ctx, const char* pre, const double* xs,
   t.hi = BUF(double, P + "hi", cap * D);
   t.ctr = BUF(double, P + "ctr", cap * D);
   t.rinf = BUF(double, P + "rinf", cap);
+  t.rad = BUF(double, P + "rad", cap);
   t.W = BUF(double, P + "W", cap);
   t.wmin = BUF(double, P + "wmin", cap);
   TreeBuildArgs a;
@@ -333,6 +334,7 @@ static gs_status keep_tree(gs_ctx_base* ctx, const DevTree& t, int D, HostTree& 
   h.hi.resize(nn * D);
   h.ctr.resize(nn * D);
   h.rinf.resize(nn);
+  h.rad.resize(nn);
   h.W.resize(nn);
   h.wmin.resize(nn);
   auto cp = [&](auto& v, const auto* src) {
@@ -346,6 +348,7 @@ static gs_status keep_tree(gs_ctx_base* ctx, const DevTree& t, int D, HostTree& 
   DT_HIP(cp(h.hi, t.hi));
   DT_HIP(cp(h.ctr, t.ctr));
   DT_HIP(cp(h.rinf, t.rinf));
+  DT_HIP(cp(h.rad, t.rad));
   DT_HIP(cp(h.W, t.W));
   DT_HIP(cp(h.wmin, t.wmin));
   DT_HIP(hipStreamSynchronize(st));
@@ -407,6 +410,10 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   if (!in.mono) {
     xq_perm = BUF(double, "xq_perm", Mq * D);
     DT_HIP(launch_gather_rows(in.q_aos, qt.perm, Mq, D, xq_perm, st));
+  }
+  if (opt.node_bounds == 1) {
+    DT_HIP(launch_node_radius(rt, rt.n_nodes, xr_perm, D, st));
+    if (!in.mono) DT_HIP(launch_node_radius(qt, qt.n_nodes, xq_perm, D, st));
   }
   unsigned long long* wmax_bits = BUF(unsigned long long, "wmax_bits", 1);
   DT_HIP(launch_max_positive(in.w, N, wmax_bits, st));
@@ -502,6 +509,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   const bool log_pairs = use_fmm && opt.log_pairs;
   dc.policy = use_policy ? 1 : 0;
   dc.log_feas = log_pairs ? 1 : 0;
+  dc.node_bounds = opt.node_bounds;
   dc.explore = opt.log_explore;
   PolicyDevModel pmodel;
   if (use_policy) {
@@ -542,8 +550,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   bool rec_ready = false;
   BaseRecordsArgs ra;
 
-  TreeView qtv{qt.lo, qt.hi, qt.rinf, qt.W, qt.wmin, qt.count, qt.left};
-  TreeView rtv{rt.lo, rt.hi, rt.rinf, rt.W, rt.wmin, rt.count, rt.left};
+  TreeView qtv{qt.lo, qt.hi, qt.rinf, qt.W, qt.wmin, qt.count, qt.left, qt.ctr, qt.rad};
+  TreeView rtv{rt.lo, rt.hi, rt.rinf, rt.W, rt.wmin, rt.count, rt.left, rt.ctr, rt.rad};
   auto level_bufs = [&](int which, int64_t nseg, int64_t npair, FrontierLevel& f) -> gs_status {
     const std::string p = which ? "f1_" : "f0_";
     f.h = BUF(int32_t, p + "h", nseg);

@@ -33,7 +33,7 @@ struct HostTree {
   bool valid = false;
   int64_t n_nodes = 0, n_points = 0;
   std::vector<int32_t> perm, begin, count, left;
-  std::vector<double> lo, hi, ctr, rinf, W, wmin;
+  std::vector<double> lo, hi, ctr, rinf, W, wmin, rad;
 };
 
 // A recorded pair of timing events not yet read (see KernelTimer).

@@ -20,6 +20,7 @@ struct DecideConst {
   int fmm_mask = 7;  // allowed series methods: bit 0 DH, bit 1 DL, bit 2 H2L
   int policy = 0;    // 1: choose by the scores of the learned policy
   int log_feas = 0;  // 1: record the admitted orders where bestMethod is reached
+  int node_bounds = 0;  // 0: box distances; 1: the tighter of box and ball distances
   double explore = 0.0;  // logging: probability of taking the direct path
                          // instead of the rule's series choice
   double eps_alg = 0.0;
@@ -54,6 +55,7 @@ struct FrontierLevel {
 struct TreeView {
   const double *lo, *hi, *rinf, *W, *wmin;
   const int32_t *count, *left;
+  const double *ctr = nullptr, *rad = nullptr;  // for the sphere-rectangle bounds
 };
 
 // Work list entries: (R << 4) | p; groups: {h, Q, first entry, entries}.

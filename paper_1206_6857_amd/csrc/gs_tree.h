@@ -18,6 +18,7 @@ struct DevTree {
   int32_t *leaf_of_pos = nullptr;  // [n_points] leaf containing each position
   double *lo = nullptr, *hi = nullptr, *ctr = nullptr;
   double *rinf = nullptr, *W = nullptr, *wmin = nullptr;
+  double* rad = nullptr;           // Euclidean radius about ctr (sphere-rectangle bounds)
   const int32_t* perm_list = nullptr;
   std::vector<int> level_begin;    // host: first node of each level, then n_nodes
   std::vector<int> level_max;      // host: most points in a node of each level
@@ -44,6 +45,11 @@ int64_t tree_node_capacity(int64_t n, int leaf_size);
 // leaves), so the topology -- begin, count, left, depth of every node and the
 // level boundaries -- is computed on the host; the device only sorts points.
 size_t tree_sort_temp_bytes(int64_t n, int D);
+// rad[i] = sqrt(max over node i's points of sum_d (x_d - ctr_d)^2), the
+// squares summed in d order; x_perm: [n_points][D] in tree order.
+hipError_t launch_node_radius(const DevTree& t, int64_t n_nodes, const double* x_perm, int D,
+                              hipStream_t s);
+
 hipError_t build_tree_device(const TreeBuildArgs& a, DevTree& t, std::vector<int>& level_begin,
                              hipStream_t s);
 

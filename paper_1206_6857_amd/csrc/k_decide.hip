@@ -163,7 +163,7 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 __global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel cur, TreeView qt,
                                                         TreeView rt, const double* __restrict__ inv2h2,
                                                         const double* __restrict__ inv4h2, int D,
-                                                        double* __restrict__ prep) {
+                                                        int node_bounds, double* __restrict__ prep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npair) return;
   const int sg = cur.seg[i];
@@ -173,6 +173,27 @@ __global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel
   double dmin2, dmax2;
   box_dist2(qt.lo + (int64_t)Q * D, qt.hi + (int64_t)Q * D, rt.lo + (int64_t)R * D,
             rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
+  if (node_bounds) {
+    // the bounding balls about the box centres: every point pair is between
+    // dc - rad_Q - rad_R and dc + rad_Q + rad_R apart; keep the tighter bounds
+    const double* cQ = qt.ctr + (int64_t)Q * D;
+    const double* cR = rt.ctr + (int64_t)R * D;
+    double d2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double diff = cQ[d] - cR[d];
+      d2 = d2 + diff * diff;
+    }
+    const double dc = sqrt(d2);
+    const double rq = qt.rad[Q], rr = rt.rad[R];
+    const double gap = (dc - rq) - rr;
+    if (gap > 0.0) {
+      const double g2 = gap * gap;
+      if (g2 > dmin2) dmin2 = g2;
+    }
+    const double far = (dc + rq) + rr;
+    const double f2 = far * far;
+    if (f2 < dmax2) dmax2 = f2;
+  }
   const double i2 = inv2h2[h];
   const double kmax = own_exp(-dmax2 * i2);
   const double kmin = own_exp(-dmin2 * i2);
@@ -748,7 +769,7 @@ hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const Tre
                          SegCount* cnt, const float4* scores, int16_t* feas, double* prep,
                          int npair, hipStream_t s) {
   hipLaunchKernelGGL(pair_prep_kernel, dim3((unsigned)ceil_div(npair, 256)), dim3(256), 0, s, npair,
-                     cur, qt, rt, inv2h2, inv4h2, c.D, prep);
+                     cur, qt, rt, inv2h2, inv4h2, c.D, c.node_bounds, prep);
   const bool gen = c.policy != 0 || c.log_feas != 0 || scores != nullptr || feas != nullptr;
 #define GS_DECIDE(PP)                                                                           \
   case PP:                                                                                     \

@@ -183,7 +183,49 @@ __global__ void internal_weights_kernel(int lb, int le, const int32_t* __restric
   wmin[i] = wmin[l] < wmin[l + 1] ? wmin[l] : wmin[l + 1];
 }
 
+// One block per node: the largest squared distance of the node's points to
+// its box centre (squares summed in d order), then its square root.
+__global__ __launch_bounds__(256) void node_radius_kernel(const int32_t* __restrict__ begin,
+                                                          const int32_t* __restrict__ count,
+                                                          const double* __restrict__ ctr,
+                                                          const double* __restrict__ x, int D,
+                                                          double* __restrict__ rad) {
+  __shared__ double part[4];
+  const int i = blockIdx.x;
+  const int64_t b = begin[i], c = count[i];
+  const double* ci = ctr + (int64_t)i * D;
+  double m = 0.0;
+  for (int64_t k = threadIdx.x; k < c; k += blockDim.x) {
+    const double* xp = x + (b + k) * D;
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double diff = xp[d] - ci[d];
+      s = s + diff * diff;
+    }
+    m = s > m ? s : m;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = part[w] > m ? part[w] : m;
+    rad[i] = sqrt(m);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_node_radius(const DevTree& t, int64_t n_nodes, const double* x_perm, int D,
+                              hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(node_radius_kernel, dim3((unsigned)n_nodes), dim3(256), 0, s, t.begin, t.count,
+                     t.ctr, x_perm, D, t.rad);
+  return hipGetLastError();
+}
 
 int64_t tree_node_capacity(int64_t n, int leaf_size) {
   int64_t min_leaf = (leaf_size + 1) / 2;

@@ -97,6 +97,37 @@ def test_dualtree_parity(case):
     assert (np.abs(G - exact) / exact).max() <= 0.01
 
 
+SPHERE_CASES = [
+    # (name, D, N, M, hs, leaf)
+    ("d2", 2, 1500, None, [0.01, 0.05, 0.2, 1.0], 32),
+    ("d3", 3, 1500, None, [0.01, 0.05, 0.2, 1.0], 32),
+    ("d8_bi", 8, 900, 400, [0.05, 0.3, 2.0], 32),
+]
+
+
+@pytest.mark.parametrize("case", SPHERE_CASES, ids=[c[0] for c in SPHERE_CASES])
+def test_dualtree_sphere_rect_parity(case):
+    """Sphere-rectangle node bounds: node radii and the decision trace
+    bit-exact with the oracle's, values within rounding of it, Theorem 2."""
+    name, D, N, M, hs, leaf = case
+    banner("dualtree sphere_rect", name)
+    r, w, q = _inputs(D, N, M, 90 + D)
+    hs = np.array(hs)
+    c = ctx()
+    G = c.gauss_sum(q, r, w, hs, 0.01, leaf_size=leaf, keep_trace=1, node_bounds="sphere_rect")
+    ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, trace=True, node_bounds="sphere_rect")
+    for which, t in ((0, ref.rtree), (1, ref.qtree)):
+        gt = c.get_tree(which, D)
+        assert np.array_equal(gt["rad"], t.rad)
+    got = c.get_trace().astype(np.int64)
+    want = np.array(ref.trace, dtype=np.int64).reshape(-1, 6)
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    assert np.array_equal(key(got), key(want))
+    exact = gauss_sum_exhaustive(q, r, w, hs)
+    assert (np.abs(G - ref.G) / exact).max() <= TOL_ROUND
+    assert (np.abs(G - exact) / exact).max() <= 0.01
+
+
 def test_dualtree_torch_device_and_repeat():
     import torch
     banner("dualtree torch repeat")
