@@ -864,7 +864,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       const int nslots = base_partial_slots(opt.leaf_size);
       ba.slots = BUF(int4, "bf_slots", nslots);
       ba.partial = BUF(double, "bf_partial", (int64_t)nslots * 8 * ceil_div(opt.leaf_size, 64) * 64);
-      ba.counters = BUF(int32_t, "bf_counters", 4);
+      ba.counters = BUF(int32_t, "bf_counters", 8);
       {
         hipError_t pe = hipSuccess;
         ba.host_counters = static_cast<int32_t*>(ctx->ws.get_pinned("bf_counters", 4 * sizeof(int32_t), &pe));

@@ -159,7 +159,7 @@ struct BaseFusedArgs {
   int4* slices = nullptr;    // base_max_slices(n_entries)
   int4* slots = nullptr;     // base_partial_slots(max_leaf)
   double* partial = nullptr; // base_partial_slots(max_leaf) * 8 * round_up(max_leaf, 64)
-  int32_t* counters = nullptr;  // 4: unique entries, runs, slices, partial slots used
+  int32_t* counters = nullptr;  // 8: unique entries, runs, slices, partial slots used, slice queue
   int32_t* host_counters = nullptr;  // 4, page-locked host memory: the plan's readbacks
   void* temp = nullptr;
   size_t temp_bytes = 0;

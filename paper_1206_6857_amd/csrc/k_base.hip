@@ -44,6 +44,11 @@ namespace {
 constexpr int kW = 64;
 constexpr int kHB = 8;   // bandwidths per block
 constexpr int kPad = 4;  // records per leaf are padded to a multiple of this
+constexpr int kResidentWaves = 6 * 4 * 256;  // base_fused_kernel: 6 waves per SIMD
+constexpr int kBaseWaves = 4;                 // waves per workgroup of base_fused_kernel
+constexpr int kReduceThreads = 256;           // base_reduce_kernel
+constexpr uint64_t kAgeStep = 30000;          // 300 us of the 100 MHz real-time clock
+constexpr int kEntryCost = 256;               // issue slots of an entry's set-up (box distance, mask)
 
 __global__ void pad_counts_kernel(const int32_t* __restrict__ left, const int32_t* __restrict__ count,
                                   int n_nodes, int32_t* __restrict__ padded) {
@@ -163,6 +168,29 @@ __global__ void slices_kernel(const int32_t* __restrict__ run_start, const int32
   }
 }
 
+// Estimated issue cost of each slice, as a descending sort key (capped to
+// 16 bits), and the identity order: per entry, its padded reference count
+// times (2 D + 4 per bandwidth of its mask) plus a fixed per-entry overhead.
+// Units are then taken heaviest first, so that the units still running when
+// the queue runs dry are light ones.
+__global__ void slice_cost_kernel(const int4* __restrict__ slices, int n_slices,
+                                  const unsigned long long* __restrict__ ukey,
+                                  const uint8_t* __restrict__ umask, int rbits, const int32_t* __restrict__ rcount,
+                                  int D, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_slices) return;
+  const int4 sd = slices[i];
+  const unsigned long long rmask = (1ull << rbits) - 1;
+  uint64_t c = 0;
+  for (int e = sd.y; e < sd.z; ++e) {
+    const int rnp = (rcount[(int)(ukey[e] & rmask)] + kPad - 1) / kPad * kPad;
+    c += (uint64_t)rnp * (uint64_t)(2 * D + 4 * __builtin_popcount(umask[e])) + kEntryCost;
+  }
+  c >>= 4;
+  key[i] = (uint32_t)(c < 65535 ? c : 65535);
+  idx[i] = i;
+}
+
 // Sixteen floats read by one scalar load when the address is wave-uniform.
 typedef float f16v __attribute__((ext_vector_type(16), aligned(16)));
 
@@ -227,31 +255,54 @@ __device__ __forceinline__ void sweep_leaf(const float* __restrict__ rec, int rs
   }
 }
 
+// Persistent waves (six per SIMD: four already keep the VALU busy; the
+// register budget allows eight) take work units from a queue counter until
+// none is left, heaviest slices first (slice_cost_kernel): unit u is query batch
+// u % QB (64 queries) of slice u / QB, QB = qmax / 64.  There are several
+// units per wave, so a SIMD whose units were light takes more of them and
+// all finish together; the two batches of a slice are taken back to back and
+// read the same reference leaves.  The reference records (a few MB) stay in
+// every XCD's L2, so the order in which units meet XCDs does not matter.
+//
+// The instruction arbiter serves the oldest wave of a SIMD first, so without
+// help the youngest waves hold their first unit for most of the sweep and
+// finish it alone at the end.  A wave therefore raises its priority by one
+// step for every kAgeStep of real time (100 MHz clock) that its current unit
+// has taken, and drops back to 0 when it takes the next unit: a starved unit
+// catches up instead of becoming the tail.  Workgroups hold kBaseWaves
+// independent waves (no LDS, no barrier).
 template <int DT>
-__global__ __launch_bounds__(kW) void base_fused_kernel(
-    const int4* __restrict__ slices, int n_slices,
+__global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu(8))) void base_fused_kernel(
+    const int4* __restrict__ slices, const int32_t* __restrict__ order, int n_slices,
     const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey,
     const uint8_t* __restrict__ umask, int rbits, int hbits, int hc0, int hc1, NodeView qt, NodeView rt,
     const int32_t* __restrict__ rec_off, const double* __restrict__ xq_perm, const float* __restrict__ rec,
     int Drt, int rs_rt, const float* __restrict__ s2, const unsigned long long* __restrict__ wmax_bits,
-    int Mq, int qmax, double* __restrict__ partial, double* __restrict__ gx) {
+    int Mq, int qmax, double* __restrict__ partial, double* __restrict__ gx,
+    int32_t* __restrict__ queue) {
   constexpr int DC = DT > 0 ? DT : kMaxD;
   const int D = DT > 0 ? DT : Drt;
   const int rs = DT > 0 ? (DT + 4) / 4 * 4 : rs_rt;
-  // Consecutive slices (neighbouring query leaves, which share reference
-  // leaves) go to the same XCD: workgroups are dealt to the 8 XCDs
-  // round-robin, so block b takes slice (b % 8) * per + b / 8.
-  const int per = (n_slices + 7) / 8;
-  const int sl = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (sl >= n_slices) return;
-  const int4 sd = slices[sl];
+  const int QB = qmax / kW;
+  const int n_units = n_slices * QB;
+  const int lane = threadIdx.x & (kW - 1);
+  for (;;) {
+  int grab = 0;
+  if (lane == 0) grab = atomicAdd(queue, 1);
+  const int u = __builtin_amdgcn_readfirstlane(grab);
+  if (u >= n_units) break;
+  __builtin_amdgcn_s_setprio(0);
+  const uint64_t t_unit = __builtin_amdgcn_s_memrealtime();
+  int prio = 0;
+  const int si = u / QB;
+  const int base = (u - si * QB) * kW;
+  const int4 sd = slices[order[si]];
   const unsigned long long k0 = ukey[run_start[sd.x]];
   const int Q = (int)(k0 >> (hbits + rbits));
   const int h0 = (int)((k0 >> rbits) & ((1ull << hbits) - 1)) * kHB;
   const unsigned long long rmask = (1ull << rbits) - 1;
   const int qb = qt.begin[Q], qn = qt.count[Q];
-  const int lane = threadIdx.x;
-  for (int base = 0; base < qn; base += kW) {
+  if (base < qn) {
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
     double xq[DC];
@@ -262,6 +313,15 @@ __global__ __launch_bounds__(kW) void base_fused_kernel(
 #pragma unroll
     for (int k = 0; k < kHB; ++k) acc[k] = 0.0;
     for (int e = sd.y; e < sd.z; ++e) {
+      if (prio < 3) {
+        const uint64_t age = __builtin_amdgcn_s_memrealtime() - t_unit;
+        if (age > (uint64_t)(prio + 1) * kAgeStep) {
+          ++prio;
+          if (prio == 1) __builtin_amdgcn_s_setprio(1);
+          else if (prio == 2) __builtin_amdgcn_s_setprio(2);
+          else __builtin_amdgcn_s_setprio(3);
+        }
+      }
       const int R = (int)(ukey[e] & rmask);
       const unsigned m = umask[e];
       const double* cR = rt.ctr + (int64_t)R * D;
@@ -335,11 +395,13 @@ __global__ __launch_bounds__(kW) void base_fused_kernel(
       }
     }
   }
+  }  // next slice
 }
 
 // Runs of several slices: gx = sum of the slices' partials in slice order.
-// One workgroup per partial slot; only a run's first slot does the work.
-__global__ __launch_bounds__(kW) void base_reduce_kernel(
+// One workgroup per partial slot; only a run's first slot does the work, one
+// thread per (bandwidth, query) of the run's query leaf.
+__global__ __launch_bounds__(kReduceThreads) void base_reduce_kernel(
     const int4* __restrict__ slots, int n_slots,
     const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey, int rbits, int hbits,
     int hc0, int hc1, NodeView qt, const unsigned long long* __restrict__ wmax_bits, int Mq, int qmax,
@@ -354,14 +416,14 @@ __global__ __launch_bounds__(kW) void base_reduce_kernel(
   const int h0 = (int)((k0 >> rbits) & ((1ull << hbits) - 1)) * kHB;
   const int qb = qt.begin[Q], qn = qt.count[Q];
   const double wscale = __longlong_as_double((long long)*wmax_bits);
-  for (int q = threadIdx.x; q < qn; q += kW) {
-#pragma unroll
-    for (int k = 0; k < kHB; ++k) {
-      if (h0 + k < hc0 || h0 + k >= hc1) continue;
-      double v = 0.0;
-      for (int j = 0; j < ns && sl + j < n_slots; ++j) v += partial[((int64_t)(sl + j) * kHB + k) * qmax + q];
-      gx[(int64_t)(h0 + k) * Mq + qb + q] = v * wscale;
-    }
+  const int nj = min(ns, n_slots - sl);
+  for (int i = threadIdx.x; i < kHB * qn; i += kReduceThreads) {
+    const int k = i / qn, q = i - k * qn;
+    if (h0 + k < hc0 || h0 + k >= hc1) continue;
+    const double* pp = partial + ((int64_t)sl * kHB + k) * qmax + q;
+    double v = 0.0;
+    for (int j = 0; j < nj; ++j) v += pp[(int64_t)j * kHB * qmax];
+    gx[(int64_t)(h0 + k) * Mq + qb + q] = v * wscale;
   }
 }
 
@@ -373,11 +435,14 @@ int bits_for(int64_t n) {
 
 template <int DT>
 void launch_fused_t(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s) {
-  const int nb = (p.n_slices + 7) / 8 * 8;
-  hipLaunchKernelGGL((base_fused_kernel<DT>), dim3((unsigned)nb), dim3(kW), 0, s, a.slices, p.n_slices,
+  const int64_t waves = std::min<int64_t>((int64_t)p.n_slices * (p.qmax / kW), kResidentWaves);
+  const int nb = (int)ceil_div(waves, kBaseWaves);
+  (void)hipMemsetAsync(a.counters + 4, 0, sizeof(int32_t), s);
+  hipLaunchKernelGGL((base_fused_kernel<DT>), dim3((unsigned)nb), dim3(kW * kBaseWaves), 0, s, a.slices, a.mpos,
+                     p.n_slices,
                      a.run_start, a.ukey, a.umask, p.rbits, p.hbits, a.hc0, a.hc1, a.qt,
                      a.rt, a.rec_off, a.xq_perm, a.rec, a.D, base_record_stride(a.D), a.s2, a.wmax_bits,
-                     a.Mq, p.qmax, a.partial, a.gx);
+                     a.Mq, p.qmax, a.partial, a.gx, a.counters + 4);
 }
 
 }  // namespace
@@ -422,18 +487,22 @@ size_t base_fused_temp_bytes(int64_t n) {
                                rocprim::equal_to<unsigned long long>());
   (void)rocprim::exclusive_scan((void*)nullptr, b3, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
                                 (size_t)n, rocprim::plus<int32_t>());
-  return std::max(b1, std::max(b2, b3));
+  size_t b4 = 0;
+  (void)rocprim::radix_sort_pairs_desc((void*)nullptr, b4, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                       (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0, 16);
+  return std::max(std::max(b1, b2), std::max(b3, b4));
 }
 
-// Partial-sum slots of one call: 2 * 16384 * 64 / qmax, so the partials take
-// 2 * 16384 * 64 * 8 doubles (128 MiB) whatever the leaf size.
+// Partial-sum slots of one call: 4 * 16384 * 64 / qmax, so the partials take
+// 4 * 16384 * 64 * 8 doubles (256 MiB) whatever the leaf size.
 int base_partial_slots(int max_leaf) {
   const int qmax = (int)ceil_div(std::max(1, max_leaf), kW) * kW;
-  return 2 * 16384 * kW / qmax;
+  return 4 * 16384 * kW / qmax;
 }
 
-// Entries per slice: about base_partial_slots / 2 slices in all (16 per SIMD
-// at leaf sizes <= 64), at least 8 entries each.  A run of len > S entries
+// Entries per slice: about base_partial_slots / 2 slices in all, at least 8
+// entries each; with a slice's query batches that is 32768 work units, four
+// per resident wave, whatever the leaf size.  A run of len > S entries
 // has ceil(len / S) < 2 len / S slices, so the runs of several slices hold
 // fewer than 2 n_unique / S <= base_partial_slots slices.
 int base_slice_entries(int64_t n_unique, int max_leaf) {
@@ -507,11 +576,25 @@ hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   const int32_t* cnt = a.host_counters;
-  // slices <= runs + nu / S; slots < 2 nu / S <= max_slots
-  if (cnt[2] <= 0 || (int64_t)cnt[2] > base_max_slices(n) || cnt[3] < 0 || cnt[3] > p->max_slots)
+  // slices <= nu (a slice holds at least one entry); slots < 2 nu / S <= max_slots
+  if (cnt[2] <= 0 || cnt[2] > nu || cnt[3] < 0 || cnt[3] > p->max_slots)
     return hipErrorInvalidValue;
+  // work units (slice, query batch) are counted in int32
+  if ((int64_t)cnt[2] * (p->qmax / kW) > INT32_MAX - kResidentWaves) return hipErrorInvalidValue;
   p->n_slices = cnt[2];
   p->n_slots = cnt[3];
+  // Slice order, heaviest first, into mpos (slices <= unique entries, so the
+  // entry-sized scratch arrays hold it; flag, pos and mflag are free now).
+  uint32_t* ckey = reinterpret_cast<uint32_t*>(a.flag);
+  uint32_t* ckey_sorted = reinterpret_cast<uint32_t*>(a.mflag);
+  hipLaunchKernelGGL(slice_cost_kernel, dim3((unsigned)ceil_div(p->n_slices, 256)), dim3(256), 0, s, a.slices,
+                     p->n_slices, a.ukey, a.umask, p->rbits, a.rt.count, a.D, ckey, a.pos);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bytes = a.temp_bytes;
+  e = rocprim::radix_sort_pairs_desc(a.temp, bytes, ckey, ckey_sorted, a.pos, a.mpos, (size_t)p->n_slices, 0, 16,
+                                     s);
+  if (e != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -530,7 +613,7 @@ hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hip
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p.n_slots == 0) return hipSuccess;
-  hipLaunchKernelGGL(base_reduce_kernel, dim3((unsigned)p.n_slots), dim3(kW), 0, s, a.slots, p.n_slots,
+  hipLaunchKernelGGL(base_reduce_kernel, dim3((unsigned)p.n_slots), dim3(kReduceThreads), 0, s, a.slots, p.n_slots,
                      a.run_start, a.ukey, p.rbits, p.hbits, a.hc0, a.hc1, a.qt, a.wmax_bits,
                      a.Mq, p.qmax, a.partial, a.gx);
   return hipGetLastError();
