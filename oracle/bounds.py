@@ -23,6 +23,39 @@ Pinned by tests/test_oracle_bounds.py: on random node pairs the true
 truncation error of each method (computed with the series of `series`) never
 exceeds the bound, and the bound is not vacuous (the worst ratio is within a
 modest factor of 1).
+
+O(p^D) expansions (DFTO).  The paper takes their bounds from an earlier paper
+that is not available here, so the bounds below are derived afresh, from
+Cramer's inequality |h_n(t)| <= K 2^{n/2} sqrt(n!) e^{-t^2/2} (K = 1.0864... in
+its classical statement, used rounded up to KC = 1.09; the inequality already
+holds with K = 1) and from the product form of the tensor sets:
+the truncated D-dimensional series is the product of D one-dimensional
+truncated series.
+
+  One dimension, far field (DH): e^{-(t-s)^2} = sum_n s^n/n! h_n(t).  With
+  rho = sqrt2 |s| = |x_r - x_R|/h <= r_R, the kept part is at most
+  K e^{-t^2/2} a_p(rho) and the dropped part at most K e^{-t^2/2} b_p(rho):
+    a_p(rho) = sum_{n<p} rho^n / sqrt(n!),
+    b_p(rho) = rho^p / (sqrt(p!) (1 - rho/sqrt(p+1)))   (rho < sqrt(p+1); else inf)
+  since n!/p! >= (p+1)^{n-p} bounds the tail by a geometric series.
+  Local (DL) is the same with the roles of query and reference exchanged
+  (rho = |x_q - x_Q|/h <= r_Q).
+  H2L: e^{-(T+u-s)^2} = sum_{m,n} s^m (-u)^n/(m! n!) h_{m+n}(T); with
+  (m+n)! <= 2^{m+n} m! n!, every term is at most
+  K e^{-T^2/2} rho_R^m rho_Q^n / sqrt(m! n!), rho = sqrt2 r, so the kept part
+  (m, n < p) is at most K e^{-T^2/2} a_p(rho_R) a_p(rho_Q) and the dropped part
+  at most K e^{-T^2/2} (b_p(rho_R)(a_p(rho_Q) + b_p(rho_Q)) + a_p(rho_R) b_p(rho_Q)).
+
+  D dimensions: with f_d the exact factors and S_d their truncations,
+  prod f_d - prod S_d = sum_k (prod_{d<k} S_d)(f_k - S_k)(prod_{d>k} f_d), and
+  |f_d| <= 1.  Every factor of every term keeps a Gaussian factor of at
+  least e^{-gap_d^2/4h^2} (gap_d = the gap between the two boxes along d), whose
+  product is g = e^{-dmin^2/4h^2} with dmin the box distance.  Hence, with
+  a_1D and b_1D the kept and dropped bounds above without their Gaussian
+  factor,
+    E_T = W_R g (KC b_1D) sum_{k<D} (KC a_1D)^k.
+  The ball bounds of sphere-rectangle mode do not split by dimension, so these
+  bounds use the box distance.
 """
 
 import math
@@ -62,6 +95,64 @@ def e_h2l(W_R, g, D, p, r_Q, r_R):
     itail = 1.0 if sq <= 1.0 else powi(sq, p - 1)
     second = (powi(SQRT2 * r_R, p) * float(math.comb(D + p - 1, D))) * itail
     return ((W_R * g) * bound_const(D, p)) * (powi(r_Q, p) + second)
+
+
+KC = 1.09  # Cramer's classical constant 1.086435..., rounded up
+
+
+def _inv_sqrt_fact(n):
+    return 1.0 / math.sqrt(float(math.factorial(n)))
+
+
+def _inv_sqrt_next(p):
+    return 1.0 / math.sqrt(float(p + 1))
+
+
+def tensor_parts(rho, p):
+    """(a_p(rho), b_p(rho)) of the O(p^D) bounds: the one-dimensional kept and
+    dropped parts, a = sum_{n<p} rho^n/sqrt(n!) left to right, and
+    b = (rho^p/sqrt(p!)) / (1 - rho/sqrt(p+1)), inf when rho/sqrt(p+1) >= 1."""
+    a = 0.0
+    pw = 1.0
+    for n in range(p):
+        a = a + pw * _inv_sqrt_fact(n)
+        pw = pw * rho
+    q = rho * _inv_sqrt_next(p)
+    b = (pw * _inv_sqrt_fact(p)) / (1.0 - q) if q < 1.0 else math.inf
+    return a, b
+
+
+def _geometric(x, D):
+    """sum_{k<D} x^k, left to right."""
+    v = 0.0
+    pw = 1.0
+    for _ in range(D):
+        v = v + pw
+        pw = pw * x
+    return v
+
+
+def e_dh_tensor(W_R, g, D, p, r_R):
+    """O(p^D) far-field bound (module docstring)."""
+    a, b = tensor_parts(r_R, p)
+    if b == math.inf:
+        return math.inf
+    return (W_R * g) * ((KC * b) * _geometric(KC * a, D))
+
+
+def e_dl_tensor(W_R, g, D, p, r_Q):
+    """O(p^D) local bound (module docstring)."""
+    return e_dh_tensor(W_R, g, D, p, r_Q)
+
+
+def e_h2l_tensor(W_R, g, D, p, r_Q, r_R):
+    """O(p^D) H2L bound (module docstring)."""
+    aR, bR = tensor_parts(SQRT2 * r_R, p)
+    aQ, bQ = tensor_parts(SQRT2 * r_Q, p)
+    if bR == math.inf or bQ == math.inf:
+        return math.inf
+    tail = bR * (aQ + bQ) + aR * bQ
+    return (W_R * g) * ((KC * tail) * _geometric(KC * (aR * aQ), D))
 
 
 def e_fd(W_R, kmin, kmax):
@@ -142,15 +233,37 @@ def _pow_int(D, e):
     return v
 
 
-def feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask=7):
+def term_cost(D, p, family="graded"):
+    """Per-point cost of an order-p expansion in Figure 6's model: D^{p+1}
+    (graded, C(D+p-1,D) ~ D^p terms of D factors) or D p^D (tensor)."""
+    if family == "tensor":
+        return _sat_mul(D, _pow_int(p, D))
+    return _pow_int(D, p + 1)
+
+
+def h2l_cost(D, p, family="graded"):
+    """Cost of one order-p H2L translation: D^{2p+1} or D p^{2D}."""
+    if family == "tensor":
+        return _sat_mul(D, _pow_int(p, 2 * D))
+    return _pow_int(D, 2 * p + 1)
+
+
+def feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask=7, family="graded"):
     """Figure 6, first half: for each series method, the smallest order
     p <= plimit whose bound meets maxerr.  Returns {name: (p, E)} for the
     methods that have one; `mask` restricts the candidates (bit 0 DH, 1 DL,
-    2 H2L)."""
+    2 H2L); `family` selects the O(D^p) ("graded") or O(p^D) ("tensor")
+    bounds."""
     found = {}
-    for bit, name, fn in ((1, "DH", lambda p: e_dh(W_R, g, D, p, r_R)),
-                          (2, "DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
-                          (4, "H2L", lambda p: e_h2l(W_R, g, D, p, r_Q, r_R))):
+    if family == "tensor":
+        fns = ((1, "DH", lambda p: e_dh_tensor(W_R, g, D, p, r_R)),
+               (2, "DL", lambda p: e_dl_tensor(W_R, g, D, p, r_Q)),
+               (4, "H2L", lambda p: e_h2l_tensor(W_R, g, D, p, r_Q, r_R)))
+    else:
+        fns = ((1, "DH", lambda p: e_dh(W_R, g, D, p, r_R)),
+               (2, "DL", lambda p: e_dl(W_R, g, D, p, r_Q)),
+               (4, "H2L", lambda p: e_h2l(W_R, g, D, p, r_Q, r_R)))
+    for bit, name, fn in fns:
         if not mask & bit:
             continue
         for p in range(1, plimit + 1):
@@ -161,23 +274,24 @@ def feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask=7):
     return found
 
 
-def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7):
+def best_method(D, plimit, maxerr, W_R, g, r_Q, r_R, N_Q, N_R, mask=7, family="graded"):
     """Figure 6.  Smallest feasible order per method, cost model
-    c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1},
+    c_DH = N_Q D^{p+1}, c_DL = N_R D^{p+1}, c_H2L = D^{2p+1} (graded; the
+    tensor family uses D p^D and D p^{2D}, term_cost and h2l_cost),
     c_Direct = D N_Q N_R, first minimum in the order DH, DL, H2L, DIRECT.
     `mask` restricts the candidate methods (bit 0 DH, 1 DL, 2 H2L) for
     ablations.  Returns (name, p, E) with name in {"DH","DL","H2L","DIRECT"}."""
-    found = feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask)
+    found = feasible_orders(D, plimit, maxerr, W_R, g, r_Q, r_R, mask, family)
     costs = []
     for name in ("DH", "DL", "H2L"):
         if name in found:
             p = found[name][0]
             if name == "DH":
-                c = _sat_mul(N_Q, _pow_int(D, p + 1))
+                c = _sat_mul(N_Q, term_cost(D, p, family))
             elif name == "DL":
-                c = _sat_mul(N_R, _pow_int(D, p + 1))
+                c = _sat_mul(N_R, term_cost(D, p, family))
             else:
-                c = _pow_int(D, 2 * p + 1)
+                c = h2l_cost(D, p, family)
         else:
             c = INF_COST
         costs.append(c)

@@ -62,13 +62,13 @@ import numpy as np
 from .bounds import best_method, box_dist2, e_fd, feasible_orders, need, sphere_rect_dist2
 from .exp64 import exp64
 from .kdtree import attach_moments, build_kdtree
-from .multiindex import num_terms, plimit_for
+from .multiindex import plimit_for, plimit_tensor, set_size
 from .series import direct_local, eval_hermite, eval_local, h2l, l2l, scale_moments
 
 FD, DH, DL, H2L, BASE, SPLIT = 0, 1, 2, 3, 4, 5
 CODE = {"DH": DH, "DL": DL, "H2L": H2L}
 NAME = {DH: "DH", DL: "DL", H2L: "H2L"}
-METHODS = ("dito", "dfdo", "dfd")
+METHODS = ("dito", "dfto", "dfdo", "dfd")
 NODE_BOUNDS = ("box", "sphere_rect")
 
 
@@ -98,7 +98,11 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     reached (res.feasible).
     node_bounds: "box" (section 5: distances between bounding boxes) or
     "sphere_rect" (the tighter of the box and the bounding-ball bounds,
-    bounds.sphere_rect_dist2)."""
+    bounds.sphere_rect_dist2).
+    method: "dito" (O(D^p) expansions and tokens), "dfto" (O(p^D) expansions
+    and tokens, with the bounds of bounds.e_*_tensor; box bounds only),
+    "dfdo" (finite differences and tokens), "dfd" (finite differences, local
+    rule)."""
     xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
     if mono is None:
         mono = xq is xr
@@ -109,15 +113,18 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
         raise ValueError(method)
     if node_bounds not in NODE_BOUNDS:
         raise ValueError(node_bounds)
+    if method == "dfto" and node_bounds != "box":
+        raise ValueError("the O(p^D) bounds need box distances")
     D = xr.shape[1]
-    P = plimit if plimit else plimit_for(D)
+    family = "tensor" if method == "dfto" else "graded"
+    P = plimit if plimit else (plimit_tensor(D) if family == "tensor" else plimit_for(D))
     rt = build_kdtree(xr, w, leaf_size)
     qt = rt if mono else build_kdtree(xq, None, leaf_size)
-    if method == "dito":
-        attach_moments(rt, P)
+    if method in ("dito", "dfto"):
+        attach_moments(rt, P, family)
     eps_alg = (1.0 - eps_round_share) * eps
     res = Result()
-    res.rtree, res.qtree, res.plimit = rt, qt, P
+    res.rtree, res.qtree, res.plimit, res.family = rt, qt, P, family
     res.G = np.zeros((len(hs), xq.shape[0]))
     res.trace = [] if trace else None
     res.counts = np.zeros((len(hs), 6), dtype=np.int64)
@@ -132,14 +139,15 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
 
 def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
     D = rt.D
-    use_tokens = method in ("dito", "dfdo")
-    use_fmm = method == "dito"
+    use_tokens = method in ("dito", "dfto", "dfdo")
+    use_fmm = method in ("dito", "dfto")
+    fam = res.family
     inv_2h2 = 1.0 / (2.0 * h * h)
     inv_4h2 = 0.5 * inv_2h2
     inv_h = 1.0 / h
     Wtot = float(rt.W[0])
     nQ = qt.n_nodes
-    C = num_terms(D, P)
+    C = set_size(D, P, fam)
     Gest = np.zeros(nQ)
     lco = np.zeros((nQ, C))
     pL = np.zeros(nQ, dtype=np.int64)
@@ -182,7 +190,7 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                     rQ, rR = float(qt.rinf[Q]) * inv_h, float(rt.rinf[R]) * inv_h
                     key = (hk, level, Q, R)
                     if res.feasible is not None or res.replay is not None:
-                        found = feasible_orders(D, P, maxerr, WR, g, rQ, rR, res.fmm_mask)
+                        found = feasible_orders(D, P, maxerr, WR, g, rQ, rR, res.fmm_mask, fam)
                         if res.feasible is not None:
                             res.feasible[key] = {n: found[n][0] for n in found}
                     if res.replay is not None:
@@ -201,7 +209,7 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                     else:
                         name, p, E = best_method(D, P, maxerr, WR, g, rQ, rR,
                                                  int(qt.count[Q]), int(rt.count[R]),
-                                                 mask=res.fmm_mask)
+                                                 mask=res.fmm_mask, family=fam)
                     if name != "DIRECT":
                         if use_tokens:
                             t = t - need(E, WR, L, Wtot, eps_alg)
@@ -255,14 +263,14 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                 d2 += diff * diff
             gx[qpts] += np.exp(-d2 / (2.0 * h * h)) @ w[rpts]
         elif code == DH:
-            A = scale_moments(rt.moments[R], D, p, h)
-            gdh[qpts] += eval_hermite(A, p, rt.ctr[R], xq[qpts], h)
+            A = scale_moments(rt.moments[R], D, p, h, fam)
+            gdh[qpts] += eval_hermite(A, p, rt.ctr[R], xq[qpts], h, fam)
         elif code == DL:
-            lco[Q, :num_terms(D, p)] += direct_local(xr[rpts], w[rpts], p, qt.ctr[Q], h)
+            lco[Q, :set_size(D, p, fam)] += direct_local(xr[rpts], w[rpts], p, qt.ctr[Q], h, fam)
             pL[Q] = max(pL[Q], p)
         elif code == H2L:
-            A = scale_moments(rt.moments[R], D, p, h)
-            lco[Q, :num_terms(D, p)] += h2l(A, p, rt.ctr[R], qt.ctr[Q], h)
+            A = scale_moments(rt.moments[R], D, p, h, fam)
+            lco[Q, :set_size(D, p, fam)] += h2l(A, p, rt.ctr[R], qt.ctr[Q], h, fam)
             pL[Q] = max(pL[Q], p)
 
     # Post-pass (Figure 8), top down in breadth-first node order.
@@ -272,13 +280,13 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
             for c in (int(qt.left[Q]), int(qt.left[Q]) + 1):
                 Gest[c] = Gest[c] + Gest[Q]
                 if pL[Q] > 0:
-                    n = num_terms(D, pL[Q])
-                    lco[c, :n] += l2l(lco[Q, :n], pL[Q], qt.ctr[Q], qt.ctr[c], h)
+                    n = set_size(D, pL[Q], fam)
+                    lco[c, :n] += l2l(lco[Q, :n], pL[Q], qt.ctr[Q], qt.ctr[c], h, fam)
                     pL[c] = max(pL[c], pL[Q])
         else:
             qpts = qt.perm[qt.begin[Q]:qt.end[Q]]
             val = gx[qpts] + gdh[qpts] + Gest[Q]
             if pL[Q] > 0:
-                val = val + eval_local(lco[Q], pL[Q], qt.ctr[Q], xq[qpts], h)
+                val = val + eval_local(lco[Q], pL[Q], qt.ctr[Q], xq[qpts], h, fam)
             G[qpts] = val
     return G

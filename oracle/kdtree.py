@@ -33,7 +33,7 @@ import math
 
 import numpy as np
 
-from .multiindex import num_terms
+from .multiindex import set_size
 from .series import h2h, raw_moments
 
 
@@ -124,18 +124,20 @@ def is_leaf(t, i):
     return t.left[i] < 0
 
 
-def attach_moments(t, p):
+def attach_moments(t, p, family="graded"):
     """Raw Hermite moments of order p for every node (Figure 5): leaves from
-    their points, internal nodes by H2H of both children (Lemma 2)."""
-    C = num_terms(t.D, p)
+    their points, internal nodes by H2H of both children (Lemma 2).  family:
+    the index set of the expansions (multiindex.index_set)."""
+    C = set_size(t.D, p, family)
     M = np.zeros((t.n_nodes, C))
     for i in range(t.n_nodes - 1, -1, -1):
         if t.left[i] < 0:
             pts = t.perm[t.begin[i]:t.end[i]]
-            M[i] = raw_moments(t.x[pts], t.w[pts], t.ctr[i], p)
+            M[i] = raw_moments(t.x[pts], t.w[pts], t.ctr[i], p, family)
         else:
             l = t.left[i]
-            M[i] = h2h(M[l], t.ctr[l], t.ctr[i], t.D, p) + h2h(M[l + 1], t.ctr[l + 1], t.ctr[i], t.D, p)
+            M[i] = (h2h(M[l], t.ctr[l], t.ctr[i], t.D, p, family)
+                    + h2h(M[l + 1], t.ctr[l + 1], t.ctr[i], t.D, p, family))
     t.moments = M
     t.moment_order = p
     return M

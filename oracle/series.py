@@ -19,7 +19,11 @@ identity d/dt h_n = -h_{n+1} gives.
 Because the moments depend on h only through s^{|alpha|}, the tree stores
 h-independent "raw" moments M_alpha = sum_r w_r (x_r-x_R)^alpha/alpha! and
 scales them per bandwidth: A_alpha = M_alpha s^{|alpha|}.  H2H holds for raw
-moments with s = 1.  "Order p" means the multi-indices with |alpha| < p.
+moments with s = 1.  "Order p" means the multi-indices with |alpha| < p
+(family "graded", the O(D^p) expansions), or with alpha_d < p in every
+dimension (family "tensor", the O(p^D) expansions of the DFTO variant): every
+formula above holds for both sets, which are closed under taking smaller
+indices, and L2L re-expands a local series exactly in either.
 
 Pinned by tests/test_oracle_series.py: the generating-function identity of
 section 1 (truncation error -> 0 as p grows, exact 1-D reduction), H2H and L2L
@@ -33,7 +37,7 @@ import math
 import numpy as np
 
 from .hermite import hermite_fn_table
-from .multiindex import mi_degree, mi_factorial, multi_indices
+from .multiindex import index_set, mi_degree, mi_factorial
 
 
 def _scale(h):
@@ -65,38 +69,38 @@ def _hermite_products(t, mis):
     return out
 
 
-def raw_moments(points, w, ctr, p):
+def raw_moments(points, w, ctr, p, family="graded"):
     """M_alpha = sum_r w_r (x_r - ctr)^alpha / alpha!, |alpha| < p (Figure 5,
     buildLeaf), h-independent form of Lemma 1's A_alpha."""
     points = np.atleast_2d(np.asarray(points, dtype=np.float64))
     D = points.shape[1]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     mono = _monomials(points - np.asarray(ctr, dtype=np.float64), mis)
     w = np.asarray(w, dtype=np.float64)
     return np.array([np.sum(w * mono[:, i]) / mi_factorial(a) for i, a in enumerate(mis)])
 
 
-def scale_moments(M, D, p, h):
+def scale_moments(M, D, p, h, family="graded"):
     """A_alpha = M_alpha (2h^2)^{-|alpha|/2} for the first C(D+p-1,D) entries."""
     s = _scale(h)
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     return np.array([M[i] * s ** mi_degree(a) for i, a in enumerate(mis)])
 
 
-def hermite_moments(points, w, ctr, p, h):
+def hermite_moments(points, w, ctr, p, h, family="graded"):
     """A_alpha straight from Lemma 1's definition (used to pin scale_moments)."""
     points = np.atleast_2d(np.asarray(points, dtype=np.float64))
     D = points.shape[1]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     mono = _monomials((points - np.asarray(ctr, dtype=np.float64)) * _scale(h), mis)
     w = np.asarray(w, dtype=np.float64)
     return np.array([np.sum(w * mono[:, i]) / mi_factorial(a) for i, a in enumerate(mis)])
 
 
-def h2h(M_child, ctr_child, ctr_parent, D, p):
+def h2h(M_child, ctr_child, ctr_parent, D, p, family="graded"):
     """Lemma 2 on raw moments: M_gamma = sum_{alpha<=gamma} M'_alpha
     (x_R'-x_R)^{gamma-alpha}/(gamma-alpha)!, |gamma| < p (Figure 5, buildInternal)."""
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     shift = np.asarray(ctr_child, dtype=np.float64) - np.asarray(ctr_parent, dtype=np.float64)
     out = np.zeros(len(mis))
     for gi, g in enumerate(mis):
@@ -112,9 +116,9 @@ def h2h(M_child, ctr_child, ctr_parent, D, p):
     return out
 
 
-def h2h_scaled(A_child, ctr_child, ctr_parent, D, p, h):
+def h2h_scaled(A_child, ctr_child, ctr_parent, D, p, h, family="graded"):
     """Lemma 2 exactly as stated, on scaled moments A (pins h2h)."""
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     shift = (np.asarray(ctr_child, dtype=np.float64) - np.asarray(ctr_parent, dtype=np.float64)) * _scale(h)
     out = np.zeros(len(mis))
     for gi, g in enumerate(mis):
@@ -128,33 +132,33 @@ def h2h_scaled(A_child, ctr_child, ctr_parent, D, p, h):
     return out
 
 
-def eval_hermite(A, p, ctr_R, xq, h):
+def eval_hermite(A, p, ctr_R, xq, h, family="graded"):
     """Direct Hermite evaluation (EVALM/DIRECTM, section 6):
     sum_{|alpha|<p} A_alpha h_alpha((x_q - x_R) s) for every row of xq."""
     xq = np.atleast_2d(np.asarray(xq, dtype=np.float64))
     D = xq.shape[1]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     hv = _hermite_products((xq - np.asarray(ctr_R, dtype=np.float64)) * _scale(h), mis)
     return hv @ np.asarray(A[: len(mis)], dtype=np.float64)
 
 
-def direct_local(points, w, p, ctr_Q, h):
+def direct_local(points, w, p, ctr_Q, h, family="graded"):
     """Direct local accumulation (DIRECTL, section 6):
     B_beta = sum_r w_r/beta! h_beta((x_r - x_Q) s), |beta| < p."""
     points = np.atleast_2d(np.asarray(points, dtype=np.float64))
     D = points.shape[1]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     hv = _hermite_products((points - np.asarray(ctr_Q, dtype=np.float64)) * _scale(h), mis)
     w = np.asarray(w, dtype=np.float64)
     return np.array([np.sum(w * hv[:, i]) / mi_factorial(b) for i, b in enumerate(mis)])
 
 
-def h2l(A, p, ctr_R, ctr_Q, h):
+def h2l(A, p, ctr_R, ctr_Q, h, family="graded"):
     """Lemma 1: B_beta = (-1)^{|beta|}/beta! sum_{|alpha|<p} A_alpha
     h_{alpha+beta}((x_Q - x_R) s), for |beta| < p."""
     ctr_R = np.asarray(ctr_R, dtype=np.float64)
     D = ctr_R.shape[0]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     t = (np.asarray(ctr_Q, dtype=np.float64) - ctr_R) * _scale(h)
     tabs = [hermite_fn_table(t[d], 2 * p) for d in range(D)]
     out = np.zeros(len(mis))
@@ -169,12 +173,12 @@ def h2l(A, p, ctr_R, ctr_Q, h):
     return out
 
 
-def l2l(B, p, ctr_parent, ctr_child, h):
+def l2l(B, p, ctr_parent, ctr_child, h, family="graded"):
     """Lemma 3: C_alpha = sum_{beta>=alpha, |beta|<p} beta!/(alpha!(beta-alpha)!)
     B_beta ((x_Q - x_Q') s)^{beta-alpha}, Q the child, Q' the parent."""
     ctr_parent = np.asarray(ctr_parent, dtype=np.float64)
     D = ctr_parent.shape[0]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     u = (np.asarray(ctr_child, dtype=np.float64) - ctr_parent) * _scale(h)
     out = np.zeros(len(mis))
     for ai, a in enumerate(mis):
@@ -191,10 +195,10 @@ def l2l(B, p, ctr_parent, ctr_child, h):
     return out
 
 
-def eval_local(B, p, ctr_Q, xq, h):
+def eval_local(B, p, ctr_Q, xq, h, family="graded"):
     """Local evaluation (EVALL, section 6): sum_{|beta|<p} B_beta ((x_q-x_Q) s)^beta."""
     xq = np.atleast_2d(np.asarray(xq, dtype=np.float64))
     D = xq.shape[1]
-    mis = multi_indices(D, p)
+    mis = index_set(D, p, family)
     mono = _monomials((xq - np.asarray(ctr_Q, dtype=np.float64)) * _scale(h), mis)
     return mono @ np.asarray(B[: len(mis)], dtype=np.float64)
