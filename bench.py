@@ -10,8 +10,9 @@ bandwidth sweep with inputs already resident in device memory.
 Metric: pair-evals/s equivalent = M * N * n_h / (time per step), for the
 dual-tree path; the plain GPU exhaustive path is timed beside it.  The JSON
 line also carries the roofline of the dominant kernel (HIP-event timing of
-that kernel over the timed steps) and the CPU oracle's rate on a bounded
-sample of the same workload.
+that kernel over the timed steps), the paper's other dual-tree variants
+(DFTO, DFDO, DFD) on the same workload and leaf size, and the CPU oracle's
+rate on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -112,6 +113,8 @@ def main():
     ap.add_argument("--leaf-size", type=int, default=0,
                     help="kd-tree leaf size; 0 (default): chosen by the library's autotuner "
                          "during the warm-up steps")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the DFTO, DFDO and DFD legs")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-policy leg (trained on another draw of the workload)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -225,6 +228,20 @@ def main():
             "ms_per_step": t_sr * 1e3, "value": pair_evals / t_sr, "speedup_vs_box": t_dt / t_sr,
             "pairs_decided": int(pc_sr.sum()), "pairs_decided_box": int(pc.sum()),
             "base_pair_evals_frac": int(ev_sr[0]) / args.steps / pair_evals}
+
+    if method_used == "dualtree" and not args.no_variants:
+        # The paper's other dual-tree variants on the same workload and leaf
+        # size: O(p^D) expansions (DFTO), finite differences with tokens
+        # (DFDO) and without (DFD).
+        variants = {}
+        for m in ("dfto", "dfdo", "dfd"):
+            t_m, _, _, ev_m, _ = run(m, args.steps, 1, leaf_size=leaf, autotune=0)
+            pc_m = ctx.pair_counts(n_h)
+            variants[m] = {"ms_per_step": t_m * 1e3, "value": pair_evals / t_m, "time_vs_dito": t_m / t_dt,
+                           "pairs": {k: int(pc_m[:, i].sum())
+                                     for i, k in enumerate(["FD", "DH", "DL", "H2L", "BASE", "SPLIT"])},
+                           "base_pair_evals_frac": int(ev_m[0]) / args.steps / pair_evals}
+        result["variants"] = variants
 
     if not args.no_learned and method_used == "dualtree":
         # The learned pair policy, trained on another draw of the same

@@ -47,7 +47,16 @@ enum {
   GS_DUALTREE = 0,    /* finite difference + O(D^p) expansions + token rule (DITO) */
   GS_EXHAUSTIVE = 1,  /* all M*N terms, no tree */
   GS_DFD = 2,         /* finite difference only, local pruning rule (no tokens) */
-  GS_DFDO = 3         /* finite difference only, with the token rule of section 5 */
+  GS_DFDO = 3,        /* finite difference only, with the token rule of section 5 */
+  GS_DFTO = 4         /* finite difference + O(p^D) expansions (every alpha_d < p) +
+                         token rule.  The paper takes their error bounds from earlier
+                         work; this library derives them from Cramer's inequality and
+                         the product form of the tensor sets (per dimension a kept
+                         part K a_p and a dropped part K b_p, telescoped over the D
+                         factors, times exp(-dmin^2/4h^2) with the box distance).
+                         Default order limit: the plimit table lowered until
+                         p^D <= 286.  Needs node_bounds = GS_BOUNDS_BOX and
+                         policy = GS_RULE; no log_pairs. */
 };
 
 /* How the series method is chosen for a node pair (Figure 6). */
@@ -62,7 +71,7 @@ typedef struct gs_options {
   int32_t leaf_size;        /* max points per kd-tree leaf (default 64, 1..1024) */
   int32_t plimit;           /* max expansion order; <= 0 selects the section 6
                                table (D=2:8, 3:6, 5:4, 6:2, >6:1) */
-  int32_t method;           /* GS_DUALTREE, GS_EXHAUSTIVE, GS_DFD, GS_DFDO */
+  int32_t method;           /* GS_DUALTREE, GS_EXHAUSTIVE, GS_DFD, GS_DFDO, GS_DFTO */
   int32_t policy;           /* GS_RULE or GS_LEARNED */
   int32_t monochromatic;    /* -1: auto (queries == refs and M == N), 0: no, 1: yes */
   int32_t blocking;         /* 1 (default): return after the results are written;
@@ -322,6 +331,15 @@ gs_status gs_lscv(gs_ctx* ctx, const double* points, int64_t N, int32_t D, const
  * *n_terms = C(D+p-1, D) and, if alpha is not NULL, alpha[n_terms][D] (host
  * pointer).  GS_EINVAL unless 1 <= D <= 64 and 1 <= p <= 10. */
 gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha);
+
+/* Multi-index set of the O(p^D) expansions of GS_DFTO (section 2): every alpha
+ * with alpha_d < p in each dimension, ordered by the largest component and,
+ * for one largest component, in decreasing lexicographic order, so that the
+ * set of order p is the first p^D entries of any larger order (for D = 2,
+ * p = 2: (0,0), (1,1), (1,0), (0,1)).  Writes *n_terms = p^D and, if alpha is
+ * not NULL, alpha[n_terms][D] (host pointer).  GS_EINVAL unless 1 <= D <= 64,
+ * 1 <= p <= 10 and p^D <= 286. */
+gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha);
 
 #ifdef __cplusplus
 }

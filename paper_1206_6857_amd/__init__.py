@@ -12,7 +12,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (GS_DFD, GS_DFDO, GS_DUALTREE, GS_EXHAUSTIVE, GS_LEARNED, GS_RULE,  # noqa: F401
+from ._lib import (GS_DFD, GS_DFDO, GS_DFTO, GS_DUALTREE, GS_EXHAUSTIVE, GS_LEARNED, GS_RULE,  # noqa: F401
                    GsOptions, GsStats)
 
 
@@ -287,6 +287,18 @@ def gs_multi_indices(D, p):
         raise GaussSumError(st, "invalid D or p")
     out = np.zeros((n.value, D), dtype=np.int32)
     lib.gs_multi_indices(int(D), int(p), ctypes.byref(n), out.ctypes.data)
+    return out
+
+
+def gs_tensor_indices(D, p):
+    """Library's O(p^D) multi-index set (every alpha_d < p; host-side table; no GPU)."""
+    lib = _lib.load()
+    n = ctypes.c_int64()
+    st = lib.gs_tensor_indices(int(D), int(p), ctypes.byref(n), None)
+    if st != 0:
+        raise GaussSumError(st, "invalid D or p")
+    out = np.zeros((n.value, D), dtype=np.int32)
+    lib.gs_tensor_indices(int(D), int(p), ctypes.byref(n), out.ctypes.data)
     return out
 
 

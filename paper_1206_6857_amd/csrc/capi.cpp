@@ -313,6 +313,19 @@ gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alph
   return GS_OK;
 }
 
+gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha) {
+  if (D < 1 || D > kMaxD || p < 1 || p > kMaxPlimit || !n_terms) return GS_EINVAL;
+  double terms = 1.0;
+  for (int d = 0; d < D; ++d) terms *= p;
+  if (terms > (double)kMaxTerms) return GS_EINVAL;
+  auto mis = tensor_indices(D, p);
+  *n_terms = (int64_t)mis.size();
+  if (alpha)
+    for (size_t i = 0; i < mis.size(); ++i)
+      for (int d = 0; d < D; ++d) alpha[i * D + d] = mis[i][d];
+  return GS_OK;
+}
+
 void gs_default_train_opts(gs_train_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -483,7 +496,11 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   if (D < 1 || D > kMaxD) GS_FAIL(ctx, GS_EINVAL, "D must be in [1, 64]");
   if (M > INT32_MAX / 2 || N > INT32_MAX / 2) GS_FAIL(ctx, GS_EOVERFLOW, "M and N must be < 2^30");
   if (n_h > 4096) GS_FAIL(ctx, GS_EINVAL, "at most 4096 bandwidths per call");
-  if (opt.method < GS_DUALTREE || opt.method > GS_DFDO) GS_FAIL(ctx, GS_EINVAL, "unknown method");
+  if (opt.method < GS_DUALTREE || opt.method > GS_DFTO) GS_FAIL(ctx, GS_EINVAL, "unknown method");
+  if (opt.method == GS_DFTO && opt.node_bounds != GS_BOUNDS_BOX)
+    GS_FAIL(ctx, GS_EINVAL, "GS_DFTO's bounds need node_bounds = GS_BOUNDS_BOX");
+  if (opt.method == GS_DFTO && (opt.policy != GS_RULE || opt.log_pairs))
+    GS_FAIL(ctx, GS_EINVAL, "the learned policy and its logging serve GS_DUALTREE only");
   if (opt.method != GS_EXHAUSTIVE && !(eps > 0.0 && eps < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps must be in (0, 1)");
   if (opt.leaf_size < 1 || opt.leaf_size > 1024) GS_FAIL(ctx, GS_EINVAL, "leaf_size must be in [1, 1024]");

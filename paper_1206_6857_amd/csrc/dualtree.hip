@@ -128,6 +128,15 @@ uint64_t binom(int n, int k) {
   return c;
 }
 
+uint64_t ipow_sat(int b, int e) {
+  uint64_t v = 1;
+  for (int i = 0; i < e; ++i) {
+    if (v > UINT64_MAX / (uint64_t)b) return UINT64_MAX;
+    v *= (uint64_t)b;
+  }
+  return v;
+}
+
 uint64_t fact(int n) {
   uint64_t f = 1;
   for (int i = 2; i <= n; ++i) f *= (uint64_t)i;
@@ -169,6 +178,42 @@ std::vector<std::vector<int>> multi_indices(int D, int p) {
 
 namespace {
 
+// All alpha in {0..m}^(D - cur.size()) completing cur, decreasing
+// lexicographic order, kept when some component equals m.
+void max_block(int D, int m, bool hit, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+  if ((int)cur.size() == D) {
+    if (hit) out.push_back(cur);
+    return;
+  }
+  for (int v = m; v >= 0; --v) {
+    cur.push_back(v);
+    max_block(D, m, hit || v == m, cur, out);
+    cur.pop_back();
+  }
+}
+
+}  // namespace
+
+// The O(p^D) set of section 2 (every alpha_d < p), ordered by the largest
+// component so that order p is a prefix (its first p^D entries) of every
+// larger order.
+std::vector<std::vector<int>> tensor_indices(int D, int p) {
+  std::vector<std::vector<int>> out;
+  std::vector<int> cur;
+  for (int m = 0; m < p; ++m) max_block(D, m, false, cur, out);
+  return out;
+}
+
+// Largest order of the O(p^D) expansions: the O(D^p) limit, lowered until
+// p^D terms fit the kernels' term bound.
+int plimit_tensor(int D) {
+  int p = plimit_table(D);
+  while (p > 1 && ipow_sat(p, D) > (uint64_t)kMaxTerms) --p;
+  return p;
+}
+
+namespace {
+
 struct HostSeries {
   std::vector<int8_t> alpha;
   std::vector<int32_t> deg, nterms, h2h_start, l2l_start;
@@ -177,9 +222,9 @@ struct HostSeries {
   int C = 0;
 };
 
-HostSeries make_series_tables(int D, int P) {
+HostSeries make_series_tables(int D, int P, bool tensor) {
   HostSeries T;
-  auto mis = multi_indices(D, P);
+  auto mis = tensor ? tensor_indices(D, P) : multi_indices(D, P);
   T.C = (int)mis.size();
   std::vector<uint64_t> afact(T.C);
   for (int i = 0; i < T.C; ++i) {
@@ -194,7 +239,8 @@ HostSeries make_series_tables(int D, int P) {
     afact[i] = f;
     T.inv_fact.push_back(1.0 / (double)f);
   }
-  for (int p = 0; p <= P; ++p) T.nterms.push_back((int32_t)binom(D + p - 1, D));
+  for (int p = 0; p <= P; ++p)
+    T.nterms.push_back((int32_t)(tensor ? ipow_sat(p, D) : binom(D + p - 1, D)));
   auto index_of = [&](const std::vector<int>& a) {
     for (int i = 0; i < T.C; ++i)
       if (mis[i] == a) return i;
@@ -378,11 +424,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   const int D = in.D;
   const int64_t N = in.N, Mq = in.M;
   const int n_h = (int)hs.size();
-  const bool use_fmm = opt.method == GS_DUALTREE;
+  const bool tensor = opt.method == GS_DFTO;
+  const bool use_fmm = opt.method == GS_DUALTREE || tensor;
   const bool use_tokens = opt.method != GS_DFD;
-  int P = opt.plimit > 0 ? opt.plimit : plimit_table(D);
+  int P = opt.plimit > 0 ? opt.plimit : (tensor ? plimit_tensor(D) : plimit_table(D));
   if (P > kMaxPlimit) DT_FAIL(GS_EINVAL, "plimit must be <= 10");
   if (!use_fmm) P = 1;
+  if (tensor && ipow_sat(P, D) > (uint64_t)kMaxTerms)
+    DT_FAIL(GS_EINVAL, "plimit too large for this dimension (GS_DFTO needs p^D <= 286)");
   if ((int64_t)binom(D + P - 1, D) > kMaxTerms || D * P > 64)
     DT_FAIL(GS_EINVAL, "plimit too large for this dimension (need C(D+p-1,D) <= 286 and D*p <= 64)");
   gs_stats& S = ctx->stats;
@@ -422,7 +471,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   S.t_tree_ms = t1 - t0;
 
   // 2. Series tables and moments.
-  HostSeries hsr = make_series_tables(D, P);
+  HostSeries hsr = make_series_tables(D, P, tensor);
   const int C = hsr.C;
   SeriesTables T;
   T.D = D;
@@ -504,6 +553,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   dc.use_tokens = use_tokens ? 1 : 0;
   dc.use_fmm = use_fmm ? 1 : 0;
   dc.eps_alg = (1.0 - opt.eps_round_share) * eps;
+  dc.tensor = tensor ? 1 : 0;
   dc.fmm_mask = (opt.fmm_mask & 7) ? (opt.fmm_mask & 7) : 7;
   const bool use_policy = use_fmm && opt.policy == GS_LEARNED;
   const bool log_pairs = use_fmm && opt.log_pairs;
@@ -520,12 +570,21 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     dc.bconst[p] = bound_const(D, p);
     dc.binomD[p] = (double)binom(D + p - 1, D);
   }
+  // Cramer's classical constant 1.086435..., rounded up
+  dc.kc = 1.09;
+  for (int n = 0; n <= kMaxPlimit; ++n) {
+    dc.isf[n] = 1.0 / std::sqrt((double)fact(n));
+    dc.isq[n] = 1.0 / std::sqrt((double)(n + 1));
+  }
   {
-    int64_t v = 1;
-    for (int k = 0; k < 2 * kMaxPlimit + 2; ++k) {
-      dc.powD[k] = v;
-      int64_t nv;
-      v = __builtin_mul_overflow(v, (int64_t)D, &nv) ? INT64_MAX : nv;
+    auto sat = [](uint64_t v) { return v > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)v; };
+    auto mul = [](int64_t a, int64_t b) {
+      int64_t r;
+      return __builtin_mul_overflow(a, b, &r) ? INT64_MAX : r;
+    };
+    for (int p = 0; p <= kMaxPlimit; ++p) {
+      dc.cterm[p] = tensor ? mul(D, sat(ipow_sat(p, D))) : sat(ipow_sat(D, p + 1));
+      dc.ch2l[p] = tensor ? mul(D, sat(ipow_sat(p, 2 * D))) : sat(ipow_sat(D, 2 * p + 1));
     }
   }
 
@@ -767,7 +826,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
     size_t gsort_bytes = 0;
     BaseFusedArgs ba;
     const bool any_base = used_grp[3] > 0;
-    const bool fast = use_fmm && series_fast_available(D, P);
+    const bool fast = use_fmm && series_fast_available(D, P, tensor);
     double* dh_part = nullptr;
     double* dl_part = nullptr;
     int32_t* dl_part_p = nullptr;
@@ -784,11 +843,11 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         }
         if (dh_need) dh_part = BUF(double, "dh_part", dh_need);
         if (used_slc[1]) {
-          dl_part = BUF(double, "dl_part", used_slc[1] * series_terms(D, P));
+          dl_part = BUF(double, "dl_part", used_slc[1] * series_terms(D, P, tensor));
           dl_part_p = BUF(int32_t, "dl_part_p", used_slc[1]);
         }
         if (used_grp[2]) {
-          h2l_part = BUF(double, "h2l_part", used_grp[2] * series_terms(D, P));
+          h2l_part = BUF(double, "h2l_part", used_grp[2] * series_terms(D, P, tensor));
           h2l_part_p = BUF(int32_t, "h2l_part_p", used_grp[2]);
         }
       }
@@ -897,7 +956,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       {
         KernelTimer kd(ctx, ctx->kernel_timing, GS_K_DL, st);
         if (fast)
-          DT_HIP(launch_dl_fast(D, P, sg[1], wl.dl_slice, (int)used_slc[1], wl.dl_first, wl.dl_cpre,
+          DT_HIP(launch_dl_fast(D, P, tensor, sg[1], wl.dl_slice, (int)used_slc[1], wl.dl_first, wl.dl_cpre,
                                 wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, dl_part,
                                 dl_part_p, st));
         else
@@ -907,7 +966,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       {
         KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, st);
         if (fast) {
-          DT_HIP(launch_h2l_fast(D, P, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, h2l_part,
+          DT_HIP(launch_h2l_fast(D, P, tensor, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, h2l_part,
                                  h2l_part_p, st));
           kh.stop(st, sg[2].n ? 2 : 0);
         } else {
@@ -926,7 +985,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         const int64_t sb = dh_slice_begin[lv], se = dh_slice_begin[lv + 1];
         if (ge == gb) continue;
         if (fast) {
-          DT_HIP(launch_dh_fast(D, P, wl.dh_slice + sb, (int)(se - sb), (int)sb, wl.grp[0], wl.dh_first,
+          DT_HIP(launch_dh_fast(D, P, tensor, wl.dh_slice + sb, (int)(se - sb), (int)sb, wl.grp[0], wl.dh_first,
                                 (int)gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm, Mom, d_sc,
                                 (int)Mq, gdh, dh_part, st));
           dh_launches += se - sb > ge - gb ? 2 : 1;
@@ -978,8 +1037,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
 
   // 5. Post-pass.
   KernelTimer kpost(ctx, ctx->kernel_timing, GS_K_POST, st);
-  if (series_fast_available(D, P)) {
-    DT_HIP(launch_leaf_post_fast(D, P, qv, qt.parent, nQ, n_h, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh,
+  if (series_fast_available(D, P, tensor)) {
+    DT_HIP(launch_leaf_post_fast(D, P, tensor, qv, qt.parent, nQ, n_h, (int)Mq, d_sc, xq_perm, qt.perm, gx, gdh,
                                  Gest, lco, pL, G_dev, st));
     kpost.stop(st, 1);
   } else {

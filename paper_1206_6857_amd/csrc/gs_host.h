@@ -96,6 +96,10 @@ void flush_kernel_timers(gs_ctx_base* ctx);
 
 // Graded multi-index set with |alpha| < p (section 2), library order.
 std::vector<std::vector<int>> multi_indices(int D, int p);
+// alpha with every alpha_d < p, by largest component (O(p^D) expansions)
+std::vector<std::vector<int>> tensor_indices(int D, int p);
+// order limit of the O(p^D) expansions for dimension D
+int plimit_tensor(int D);
 
 // Learned pair policy (policy.cpp).
 void policy_default_costs(PolicyState& ps);

@@ -63,9 +63,11 @@ hipError_t launch_leaf_eval(const SeriesTables& T, const NodeView& qt, const int
                             const double* gdh, const double* Gest, const double* lco,
                             const int32_t* pL, double* G_out, hipStream_t s);
 
-// Compile-time specialisations of DH and DL for the order-limit table's
-// (D, P) pairs; launch_*_fast return hipErrorInvalidValue for other pairs.
-bool series_fast_available(int D, int P);
+// Compile-time specialisations of DH, DL, H2L and the post-pass for the
+// order-limit table's (D, P) pairs, with graded (O(D^p)) or, with tensor,
+// tensor (O(p^D)) index sets; launch_*_fast return hipErrorInvalidValue for
+// other pairs.
+bool series_fast_available(int D, int P, bool tensor);
 //
 // DH of one traversal level: slices[0..ns) {group, first entry, entries,
 // slice of the group} of its groups grp[g0..g0+ng), first[g] = the global
@@ -74,7 +76,7 @@ bool series_fast_available(int D, int P);
 // group of one slice adds into gdh directly; the slices of a longer group
 // write part[slice][chunk][64] (ns * ceil(max_q / 64) * 64 doubles), summed
 // in slice order by a second kernel.
-hipError_t launch_dh_fast(int D, int P, const int4* slices, int ns, int slice0, const int4* grp,
+hipError_t launch_dh_fast(int D, int P, bool tensor, const int4* slices, int ns, int slice0, const int4* grp,
                           const int32_t* first, int g0, int ng, int max_q, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xq_perm,
                           const double* M, const double* sc, int Mq, double* gdh, double* part,
@@ -84,7 +86,7 @@ hipError_t launch_dh_fast(int D, int P, const int4* slices, int ns, int slice0, 
 // entries), one partial coefficient vector per slice (part: ns * C doubles,
 // part_p: ns orders), then per (h, Q) run of the sorted groups g the sum over
 // its groups' slices (first[group] = {first slice, slices}) in order into lco.
-hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slices, int ns,
+hipError_t launch_dl_fast(int D, int P, bool tensor, const SortedGroups& g, const int4* slices, int ns,
                           const int2* first, const int32_t* cpre, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xr_perm,
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
@@ -92,17 +94,17 @@ hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slice
 // H2L of the whole traversal: one partial coefficient vector per group (part:
 // groups * C doubles, part_p: groups orders), then per (h, Q) run of the
 // sorted groups g their sum in order into lco.
-hipError_t launch_h2l_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+hipError_t launch_h2l_fast(int D, int P, bool tensor, const SortedGroups& g, const int32_t* ent,
                            const NodeView& qt, const NodeView& rt, const double* M, const double* sc,
                            int nQ, double* lco, int32_t* pL, double* part, int32_t* part_p,
                            hipStream_t s);
-// Size of the DL partial coefficient vectors (C(D+P-1, D)).
-int series_terms(int D, int P);
+// Size of the DL partial coefficient vectors (C(D+P-1, D), or P^D for tensor sets).
+int series_terms(int D, int P, bool tensor);
 // Post-pass in one launch (grid: query nodes x bandwidths, internal nodes
 // exit): G_out[h][qperm[q]] = gx + gdh + sum over the leaf and its ancestors
 // A (parent[], -1 at the root) of Gest_A + EVALL(lco_A, pL_A, x_q); lco may
 // be null when every pL is 0.
-hipError_t launch_leaf_post_fast(int D, int P, const NodeView& qt, const int32_t* parent, int nQ,
+hipError_t launch_leaf_post_fast(int D, int P, bool tensor, const NodeView& qt, const int32_t* parent, int nQ,
                                  int n_h, int Mq, const double* sc, const double* xq_perm,
                                  const int32_t* qperm, const double* gx, const double* gdh,
                                  const double* Gest, const double* lco, const int32_t* pL,

@@ -24,9 +24,18 @@ struct DecideConst {
   double explore = 0.0;  // logging: probability of taking the direct path
                          // instead of the rule's series choice
   double eps_alg = 0.0;
+  int tensor = 0;  // 1: O(p^D) expansions (tensor index sets) and their bounds
   double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
   double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
-  int64_t powD[2 * kMaxPlimit + 2];  // D^k, saturated at INT64_MAX (cost model)
+  // O(p^D) bounds: Cramer's constant, 1/sqrt(n!) and 1/sqrt(p+1)
+  double kc = 0.0;
+  double isf[kMaxPlimit + 1];
+  double isq[kMaxPlimit + 1];
+  // Figure 6's cost model, saturated at INT64_MAX: per-point cost of an
+  // order-p expansion (D^(p+1), or D p^D for tensor sets) and of an order-p
+  // H2L translation (D^(2p+1), or D p^(2D))
+  int64_t cterm[kMaxPlimit + 1];
+  int64_t ch2l[kMaxPlimit + 1];
 };
 
 // Counters of one frontier segment (one (bandwidth, query node) pair list).

@@ -64,6 +64,53 @@ __device__ __forceinline__ double own_exp(double x) {
   return ldexp(p, (int)k);
 }
 
+// One-dimensional parts of the O(p^D) bounds for a scaled radius rho:
+// a = sum_{n<p} rho^n / sqrt(n!) (left to right) and pw = rho^p, extended one
+// order at a time.
+struct TensorPart {
+  double rho, a = 0.0, pw = 1.0;
+  __device__ explicit TensorPart(double r) : rho(r) {}
+  __device__ __forceinline__ void extend(const DecideConst& c, int p) {
+    a = a + pw * c.isf[p - 1];
+    pw = pw * rho;
+  }
+  // b = (rho^p / sqrt(p!)) / (1 - rho / sqrt(p+1)), inf when the ratio
+  // rho / sqrt(p+1) reaches 1
+  __device__ __forceinline__ double b(const DecideConst& c, int p) const {
+    const double q = rho * c.isq[p];
+    return q < 1.0 ? (pw * c.isf[p]) / (1.0 - q) : INFINITY;
+  }
+};
+
+// sum_{k<D} x^k, left to right.
+__device__ __forceinline__ double geometric(double x, int D) {
+  double v = 0.0, pw = 1.0;
+  for (int k = 0; k < D; ++k) {
+    v = v + pw;
+    pw = pw * x;
+  }
+  return v;
+}
+
+// O(p^D) far-field or local bound: W_R g (K b) sum_{k<D} (K a)^k, the
+// product form of the tensor truncation with Cramer's inequality per factor.
+__device__ __forceinline__ double tensor_bound(const DecideConst& c, double base_e, const TensorPart& t,
+                                               int p) {
+  const double b = t.b(c, p);
+  if (b == INFINITY) return INFINITY;
+  return base_e * ((c.kc * b) * geometric(c.kc * t.a, c.D));
+}
+
+// O(p^D) H2L bound: the dropped part of the double series over (m, n) with
+// m or n >= p, rho = sqrt2 r on both sides.
+__device__ __forceinline__ double tensor_h2l_bound(const DecideConst& c, double base_e, const TensorPart& tR,
+                                                   const TensorPart& tQ, int p) {
+  const double bR = tR.b(c, p), bQ = tQ.b(c, p);
+  if (bR == INFINITY || bQ == INFINITY) return INFINITY;
+  const double tail = bR * (tQ.a + bQ) + tR.a * bQ;
+  return base_e * ((c.kc * tail) * geometric(c.kc * (tR.a * tQ.a), c.D));
+}
+
 __device__ __forceinline__ double powi(double x, int p) {
   double v = 1.0;
   for (int i = 0; i < p; ++i) v = v * x;
@@ -308,8 +355,8 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   const bool learned = GEN && c.use_fmm && c.policy;
   // Cost tables of the segment, lane k holding order k: c_DH(k) = N_Q D^(k+1),
   // c_H2L(k) = D^(2k+1) (Figure 6).
-  const long long c0_lane = lane >= 1 && lane <= P ? sat_mul(NQ, c.powD[lane + 1]) : kInfCost;
-  const long long c2_lane = lane >= 1 && lane <= P ? c.powD[2 * lane + 1] : kInfCost;
+  const long long c0_lane = lane >= 1 && lane <= P ? sat_mul(NQ, c.cterm[lane]) : kInfCost;
+  const long long c2_lane = lane >= 1 && lane <= P ? c.ch2l[lane] : kInfCost;
   __shared__ double sh_pm[64][3 * P];      // PM_DH, PM_DL, PM_H2L of each pair
   __shared__ long long sh_c1[64][P];       // c_DL(q) = N_R D^(q+1), q = 1..P
   for (int b0 = 0; b0 < len; b0 += 64) {
@@ -348,35 +395,57 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         const double rR = rt.rinf[R] * ih;
         const double base_e = WR * g;
         double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY;
+        if (c.tensor) {
+          // O(p^D) bounds: a = sum_{n<p} rho^n / sqrt(n!) grows by one term
+          // per order; b = rho^p / sqrt(p!) / (1 - rho / sqrt(p+1)).
+          TensorPart tR(rR), tQ(rQ), tR2(kSqrt2 * rR), tQ2(kSqrt2 * rQ);
 #pragma unroll
-        for (int p = 1; p <= P; ++p) {
-          const double bc = base_e * c.bconst[p];
-          const double e0 = (c.fmm_mask & 1) ? bc * powi(rR, p) : INFINITY;
-          const double e1 = (c.fmm_mask & 2) ? bc * powi(rQ, p) : INFINITY;
-          double e2 = INFINITY;
-          if (c.fmm_mask & 4) {
-            const double sq = kSqrt2 * rQ;
-            const double itail = sq <= 1.0 ? 1.0 : powi(sq, p - 1);
-            const double second = (powi(kSqrt2 * rR, p) * c.binomD[p]) * itail;
-            e2 = bc * (powi(rQ, p) + second);
+          for (int p = 1; p <= P; ++p) {
+            tR.extend(c, p);
+            tQ.extend(c, p);
+            tR2.extend(c, p);
+            tQ2.extend(c, p);
+            const double e0 = (c.fmm_mask & 1) ? tensor_bound(c, base_e, tR, p) : INFINITY;
+            const double e1 = (c.fmm_mask & 2) ? tensor_bound(c, base_e, tQ, p) : INFINITY;
+            const double e2 = (c.fmm_mask & 4) ? tensor_h2l_bound(c, base_e, tR2, tQ2, p) : INFINITY;
+            m0 = e0 < m0 ? e0 : m0;
+            m1 = e1 < m1 ? e1 : m1;
+            m2 = e2 < m2 ? e2 : m2;
+            pm0[p - 1] = m0;
+            pm1[p - 1] = m1;
+            pm2[p - 1] = m2;
           }
-          m0 = e0 < m0 ? e0 : m0;
-          m1 = e1 < m1 ? e1 : m1;
-          m2 = e2 < m2 ? e2 : m2;
-          pm0[p - 1] = m0;
-          pm1[p - 1] = m1;
-          pm2[p - 1] = m2;
+        } else {
+#pragma unroll
+          for (int p = 1; p <= P; ++p) {
+            const double bc = base_e * c.bconst[p];
+            const double e0 = (c.fmm_mask & 1) ? bc * powi(rR, p) : INFINITY;
+            const double e1 = (c.fmm_mask & 2) ? bc * powi(rQ, p) : INFINITY;
+            double e2 = INFINITY;
+            if (c.fmm_mask & 4) {
+              const double sq = kSqrt2 * rQ;
+              const double itail = sq <= 1.0 ? 1.0 : powi(sq, p - 1);
+              const double second = (powi(kSqrt2 * rR, p) * c.binomD[p]) * itail;
+              e2 = bc * (powi(rQ, p) + second);
+            }
+            m0 = e0 < m0 ? e0 : m0;
+            m1 = e1 < m1 ? e1 : m1;
+            m2 = e2 < m2 ? e2 : m2;
+            pm0[p - 1] = m0;
+            pm1[p - 1] = m1;
+            pm2[p - 1] = m2;
+          }
         }
         const int64_t cdir = sat_mul(c.D, sat_mul(NQ, (int64_t)NR));
         c3 = cdir;
         double mstar = INFINITY;
 #pragma unroll
         for (int p = 1; p <= P; ++p) {
-          const int64_t c1p = sat_mul((int64_t)NR, c.powD[p + 1]);
+          const int64_t c1p = sat_mul((int64_t)NR, c.cterm[p]);
           sh_c1[lane][p - 1] = c1p;
-          if (sat_mul(NQ, c.powD[p + 1]) <= cdir) mstar = pm0[p - 1] < mstar ? pm0[p - 1] : mstar;
+          if (sat_mul(NQ, c.cterm[p]) <= cdir) mstar = pm0[p - 1] < mstar ? pm0[p - 1] : mstar;
           if (c1p <= cdir) mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
-          if (c.powD[2 * p + 1] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
+          if (c.ch2l[p] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
         }
         astar = all_orders ? -INFINITY : division_threshold(mstar, Wtot);
         thr = astar;

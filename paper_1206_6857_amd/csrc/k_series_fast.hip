@@ -17,6 +17,11 @@
 //        slice of up to 16 chunks of 64 reference points, lanes over the
 //        points, per-lane partial coefficients reduced across the wave once
 //        per slice; then per (h, Q) run the slices summed in order)
+//
+// Every kernel also has an O(p^D) form (template flag T: tensor index sets,
+// every a_d < p, ordered by largest component).  The nested sums then give
+// each dimension the same bound p instead of the remaining degree, and the
+// tensor DL uses the product form of its coefficients (dl_tensor_kernel).
 #include "gs_series.h"
 
 namespace gs {
@@ -39,15 +44,57 @@ constexpr double cfact(int n) {
   return f;
 }
 
-// Graded multi-index set |a| < P in the library's order.
-template <int D, int P>
+constexpr int cpow(int b, int e) {
+  int v = 1;
+  for (int i = 0; i < e; ++i) v *= b;
+  return v;
+}
+
+// Multi-index set of order P in the library's order: graded (|a| < P, by
+// degree, decreasing lexicographic inside a degree) or, with T, tensor
+// (every a_d < P, by largest component, decreasing lexicographic inside).
+// ord[i] < p tells whether term i belongs to order p; deg[i] = |a|.
+template <int D, int P, bool T = false>
 struct MultiIndex {
-  static constexpr int C = cbinom(D + P - 1, D);
+  static constexpr int C = T ? cpow(P, D) : cbinom(D + P - 1, D);
   int a[C][D];
   int deg[C];
+  int ord[C];
   double invf[C];
   int nterms[P + 1];
-  constexpr MultiIndex() : a(), deg(), invf(), nterms() {
+  constexpr MultiIndex() : a(), deg(), ord(), invf(), nterms() {
+    if (T) {
+      int idx = 0;
+      for (int m = 0; m < P; ++m) {
+        const int n = cpow(m + 1, D);
+        for (int k = 0; k < n; ++k) {
+          // digits of k in base m + 1, most significant first, counted
+          // down from m: decreasing lexicographic order
+          int cur[D] = {};
+          int r = k, mx = 0, sum = 0;
+          for (int d = D - 1; d >= 0; --d) {
+            cur[d] = m - r % (m + 1);
+            r /= m + 1;
+          }
+          double f = 1.0;
+          for (int d = 0; d < D; ++d) {
+            mx = cur[d] > mx ? cur[d] : mx;
+            sum += cur[d];
+          }
+          if (mx != m) continue;
+          for (int d = 0; d < D; ++d) {
+            a[idx][d] = cur[d];
+            f *= cfact(cur[d]);
+          }
+          deg[idx] = sum;
+          ord[idx] = m;
+          invf[idx] = 1.0 / f;
+          ++idx;
+        }
+      }
+      for (int p = 0; p <= P; ++p) nterms[p] = cpow(p, D);
+      return;
+    }
     int idx = 0;
     for (int g = 0; g < P; ++g) {
       int cur[D] = {};
@@ -59,6 +106,7 @@ struct MultiIndex {
           f *= cfact(cur[d]);
         }
         deg[idx] = g;
+        ord[idx] = g;
         invf[idx] = 1.0 / f;
         ++idx;
         int i = D - 2;
@@ -92,12 +140,12 @@ __device__ __forceinline__ void hermite_polys(double t, double* H) {
   for (int k = 1; k + 1 < P; ++k) H[k + 1] = 2.0 * t * H[k] - 2.0 * k * H[k - 1];
 }
 
-// Position of the multi-index (A...) in the graded order (compile time).
-template <int D, int P, int... A>
-constexpr int graded_index() {
-  constexpr MultiIndex<D, P> mi{};
+// Position of the multi-index (A...) in the set's order (compile time).
+template <int D, int P, bool T, int... A>
+constexpr int set_index() {
+  constexpr MultiIndex<D, P, T> mi{};
   const int want[D] = {A...};
-  for (int i = 0; i < MultiIndex<D, P>::C; ++i) {
+  for (int i = 0; i < MultiIndex<D, P, T>::C; ++i) {
     bool eq = true;
     for (int d = 0; d < D; ++d) eq = eq && mi.a[i][d] == want[d];
     if (eq) return i;
@@ -105,51 +153,53 @@ constexpr int graded_index() {
   return -1;
 }
 
-// Nested (Horner-like) sum over the multi-indices with |a| < rem of
+// Nested (Horner-like) sum over the multi-indices of order p of
 // M[a] prod_d H[d][a_d], dimension by dimension: each dimension's factor
 // multiplies the sum over the dimensions after it, so a term costs one fused
 // multiply-add instead of a product over all dimensions.  A... holds the
-// indices of the dimensions before d; a runs over dimension d.
-template <int D, int P, int d, int rem, int a, int... A>
+// indices of the dimensions before d; a runs over dimension d below rem: the
+// remaining degree p - (a_0 + ... + a_{d-1}) of a graded set, or p itself in
+// every dimension of a tensor set.
+template <int D, int P, bool T, int d, int rem, int a, int... A>
 struct DHNest {
   static __device__ __forceinline__ double run(const double (&H)[D][P], const double* __restrict__ M) {
     double inner;
     if constexpr (d == D - 1) {
-      constexpr int I = graded_index<D, P, A..., a>();
+      constexpr int I = set_index<D, P, T, A..., a>();
       static_assert(I >= 0, "multi-index outside the set");
       inner = M[I];
     } else {
-      inner = DHNest<D, P, d + 1, rem - a, 0, A..., a>::run(H, M);
+      inner = DHNest<D, P, T, d + 1, T ? rem : rem - a, 0, A..., a>::run(H, M);
     }
     // (where H[d][0] is the constant 1 the compiler drops the product)
     const double v = H[d][a] * inner;
     if constexpr (a + 1 < rem)
-      return v + DHNest<D, P, d, rem, a + 1, A...>::run(H, M);
+      return v + DHNest<D, P, T, d, rem, a + 1, A...>::run(H, M);
     else
       return v;
   }
 };
 
 // The order p of an entry (1..P) selects the compile-time truncation.
-template <int D, int P, int p = 1>
+template <int D, int P, bool T, int p = 1>
 __device__ __forceinline__ double dh_sum(int pr, const double (&H)[D][P], const double* __restrict__ M) {
   if constexpr (p > P) {
     return 0.0;
   } else {
-    if (pr == p) return DHNest<D, P, 0, p, 0>::run(H, M);
-    return dh_sum<D, P, p + 1>(pr, H, M);
+    if (pr == p) return DHNest<D, P, T, 0, p, 0>::run(H, M);
+    return dh_sum<D, P, T, p + 1>(pr, H, M);
   }
 }
 
 // grid.x: slices of the level (kWavesPerBlock per block), grid.y: 64-point
 // chunks of Q.
-template <int D, int P>
+template <int D, int P, bool T>
 __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
     const int4* __restrict__ slc, int ns, const int4* __restrict__ grp,
     const int32_t* __restrict__ ent, NodeView qt, NodeView rt, const double* __restrict__ xq_perm,
     const double* __restrict__ M, const double* __restrict__ sc, int Mq, double* __restrict__ gdh,
     double* __restrict__ part) {
-  constexpr int C = MultiIndex<D, P>::C;
+  constexpr int C = MultiIndex<D, P, T>::C;
   const int lane = threadIdx.x % kW;
   // wave index: uniform across the wave (readfirstlane tells the compiler)
   const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
@@ -186,7 +236,7 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dh_fast_kernel(
 #pragma unroll
       for (int k = 1; k < P; ++k) H[d][k] *= spow[k];
     }
-    const double v = dh_sum<D, P>(p, H, M + (int64_t)R * C);
+    const double v = dh_sum<D, P, T>(p, H, M + (int64_t)R * C);
     acc += v * exp(-tt);
   }
   if (!active) return;
@@ -278,7 +328,7 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
     const double ew = wr_perm[pos] * exp(-tt);
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      if (mi.deg[a] < p) {
+      if (mi.ord[a] < p) {
         double term = ew;
 #pragma unroll
         for (int d = 0; d < D; ++d)
@@ -296,19 +346,155 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_fast_kernel(
   if (lane == 0) part_p[i] = pmax;
 }
 
+// Position of each tensor multi-index in the set's order, by its dense
+// row-major index sum_d a_d P^(D-1-d).
+template <int D, int P>
+struct TensorPos {
+  int pos[cpow(P, D)];
+  constexpr TensorPos() : pos() {
+    constexpr MultiIndex<D, P, true> mi{};
+    for (int i = 0; i < MultiIndex<D, P, true>::C; ++i) {
+      int dense = 0;
+      for (int d = 0; d < D; ++d) dense = dense * P + mi.a[i][d];
+      pos[dense] = i;
+    }
+  }
+};
+
+// DL for tensor sets.  B_b = sum_r w_r e^{-|t_r|^2} prod_d H_{b_d}(t_rd) is a
+// sum over the points of outer products, so a lane owns one combination of
+// the trailing indices (b_1..b_{D-1}) and keeps the P values of b_0: per point
+// one product over the trailing dimensions and P fused multiply-adds.  The
+// points of a chunk are staged in LDS as u[r][d][k] = H_k(t_rd), times the
+// point's w e^{-|t|^2} in dimension 0 and zero for k >= the entry's order, so
+// that the terms outside an entry's order vanish.  With fewer combinations
+// than lanes, G = 64 / NT lane groups split the points and are summed by a
+// fixed butterfly at the end.  One wave per slice (the slices of
+// dl_fast_kernel); part[slice][C] before the 1/b! scale, as dl_fast_kernel.
+template <int D, int P>
+__global__ __launch_bounds__(kW) void dl_tensor_kernel(
+    const int4* __restrict__ slc, int ns, const int4* __restrict__ grp,
+    const int32_t* __restrict__ ent, const int32_t* __restrict__ cpre, NodeView qt, NodeView rt,
+    const double* __restrict__ xr_perm, const double* __restrict__ wr_perm,
+    const double* __restrict__ sc, double* __restrict__ part, int32_t* __restrict__ part_p) {
+  static constexpr TensorPos<D, P> tp{};
+  constexpr int C = MultiIndex<D, P, true>::C;
+  constexpr int NT = cpow(P, D - 1);                          // trailing combinations
+  constexpr int G = (NT < kW && kW % NT == 0) ? kW / NT : 1;  // lane groups over points
+  constexpr int NJ = G > 1 ? 1 : (NT + kW - 1) / kW;          // combinations per lane
+  __shared__ double u[kW][D][P];
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x;
+  if (i >= ns) return;
+  const int4 sl = slc[i];
+  const int4 g0 = grp[sl.x];
+  const int h = g0.x, Q = g0.y;
+  const double s = sc[h];
+  double cQ[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) cQ[d] = qt.ctr[(int64_t)Q * D + d];
+  int lo = 0, hi = g0.w - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cpre[g0.z + mid] <= sl.y)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int e = g0.z + lo;
+  int c = sl.y - cpre[e];
+  // this lane's combinations and point group
+  const int grpi = G > 1 ? lane / NT : 0;
+  int combo[NJ], tb[NJ][D];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    combo[j] = G > 1 ? lane % NT : j * kW + lane;
+    int r = combo[j] < NT ? combo[j] : 0;
+#pragma unroll
+    for (int d = D - 1; d >= 1; --d) {
+      tb[j][d] = r % P;
+      r /= P;
+    }
+    tb[j][0] = 0;
+  }
+  double B[NJ][P];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int k = 0; k < P; ++k) B[j][k] = 0.0;
+  int pmax = 0;
+  int R = ent[e] >> 4, p = ent[e] & 15;
+  int rb = rt.begin[R], rn = rt.count[R];
+  for (int k = sl.y; k < sl.z; ++k, ++c) {
+    if (c * kW >= rn) {
+      ++e;
+      c = 0;
+      R = ent[e] >> 4;
+      p = ent[e] & 15;
+      rb = rt.begin[R];
+      rn = rt.count[R];
+    }
+    pmax = p > pmax ? p : pmax;
+    const int cnt = rn - c * kW < kW ? rn - c * kW : kW;
+    __syncthreads();  // the previous chunk's reads of u are done
+    if (lane < cnt) {
+      const int pos = rb + c * kW + lane;
+      double H[D][P];
+      double tt = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const double t = (xr_perm[(int64_t)pos * D + d] - cQ[d]) * s;
+        tt += t * t;
+        hermite_polys<P>(t, H[d]);
+      }
+      const double ew = wr_perm[pos] * exp(-tt);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int q = 0; q < P; ++q) u[lane][d][q] = q < p ? (d == 0 ? H[d][q] * ew : H[d][q]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (combo[j] >= NT) continue;
+      for (int r = grpi; r < cnt; r += G) {
+        double t = 1.0;
+#pragma unroll
+        for (int d = 1; d < D; ++d) t *= u[r][d][tb[j][d]];
+#pragma unroll
+        for (int q = 0; q < P; ++q) B[j][q] += u[r][0][q] * t;
+      }
+    }
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int off = NT; off < kW; off <<= 1)
+#pragma unroll
+      for (int q = 0; q < P; ++q) B[0][q] += __shfl_xor(B[0][q], off, kW);
+  }
+  double* out = part + (int64_t)i * C;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    if (combo[j] >= NT || grpi != 0) continue;
+#pragma unroll
+    for (int q = 0; q < P; ++q) out[tp.pos[q * NT + combo[j]]] = B[j][q];
+  }
+  if (lane == 0) part_p[i] = pmax;
+}
+
 // H2L (Lemma 1): B_b(Q) += (-1)^|b| / b! sum_{|a|<p} A_a h_{a+b}(t), t = (x_Q - x_R) s,
 // one wave per H2L group (its entries in order), lanes over b.  Per entry the
 // 1-D Hermite polynomials of orders < 2P-1 go to LDS; lane b forms
 // g_d[k] = s^k H_{k+b_d}(t_d) (k < P) and the nested sum over a of
 // M_a prod_d g_d[a_d] (M the raw moments, so A_a = M_a s^|a|), times
 // exp(-|t|^2).  part[group][b] holds the group's sum before the 1/b! scale.
-template <int D, int P>
+template <int D, int P, bool T>
 __global__ __launch_bounds__(kW) void h2l_fast_kernel(
     const int4* __restrict__ grp, int ng, const int32_t* __restrict__ ent, NodeView qt, NodeView rt,
     const double* __restrict__ M, const double* __restrict__ sc, double* __restrict__ part,
     int32_t* __restrict__ part_p) {
-  static constexpr MultiIndex<D, P> mi{};
-  constexpr int C = MultiIndex<D, P>::C;
+  static constexpr MultiIndex<D, P, T> mi{};
+  constexpr int C = MultiIndex<D, P, T>::C;
   constexpr int NB = (C + kW - 1) / kW;
   constexpr int HT = 2 * P - 1;
   __shared__ double Ht[D][HT];
@@ -322,13 +508,14 @@ __global__ __launch_bounds__(kW) void h2l_fast_kernel(
   spow[0] = 1.0;
 #pragma unroll
   for (int k = 1; k < P; ++k) spow[k] = spow[k - 1] * s;
-  int bd[NB][D], bdeg[NB];
+  int bd[NB][D], bdeg[NB], bord[NB];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int b = u * kW + lane < C ? u * kW + lane : 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) bd[u][d] = mi.a[b][d];
-    bdeg[u] = u * kW + lane < C ? mi.deg[b] : P;  // lanes past C never contribute
+    bdeg[u] = mi.deg[b];
+    bord[u] = u * kW + lane < C ? mi.ord[b] : P;  // lanes past C never contribute
   }
   double acc[NB];
 #pragma unroll
@@ -363,8 +550,8 @@ __global__ __launch_bounds__(kW) void h2l_fast_kernel(
       for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int k = 0; k < P; ++k) g[d][k] = spow[k] * Ht[d][k + bd[u][d]];
-      const double v = dh_sum<D, P>(p, g, m) * ex;
-      if (bdeg[u] < p) acc[u] += (bdeg[u] & 1) ? -v : v;
+      const double v = dh_sum<D, P, T>(p, g, m) * ex;
+      if (bord[u] < p) acc[u] += (bdeg[u] & 1) ? -v : v;
     }
   }
 #pragma unroll
@@ -376,12 +563,12 @@ __global__ __launch_bounds__(kW) void h2l_fast_kernel(
 // Per (h, Q) run of the sorted DL groups: the slices of its groups summed in
 // order, scaled by 1/b! into lco; lanes over coefficients.  first == nullptr:
 // one partial vector per group, at the group's index (H2L).
-template <int D, int P>
+template <int D, int P, bool T>
 __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
     SortedGroups g, const int2* __restrict__ first, const double* __restrict__ part,
     const int32_t* __restrict__ part_p, int nQ, double* __restrict__ lco, int32_t* __restrict__ pL) {
-  static constexpr MultiIndex<D, P> mi{};
-  constexpr int C = MultiIndex<D, P>::C;
+  static constexpr MultiIndex<D, P, T> mi{};
+  constexpr int C = MultiIndex<D, P, T>::C;
   const int lane = threadIdx.x % kW;
   // wave index: uniform across the wave (readfirstlane tells the compiler)
   const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kW);
@@ -419,13 +606,13 @@ __global__ __launch_bounds__(kW* kWavesPerBlock) void dl_reduce_kernel(
 // its ancestors A, Gest_A and A's own local expansion evaluated at the point.
 // A local-to-local translation re-expands a polynomial exactly, so this is
 // the same sum as translating every expansion down to the leaf first.
-template <int D, int P>
+template <int D, int P, bool T>
 __global__ __launch_bounds__(kW) void leaf_post_kernel(
     NodeView qt, const int32_t* __restrict__ parent, int nQ, int Mq, const double* __restrict__ sc,
     const double* __restrict__ xq_perm, const int32_t* __restrict__ qperm,
     const double* __restrict__ gx, const double* __restrict__ gdh, const double* __restrict__ Gest,
     const double* __restrict__ lco, const int32_t* __restrict__ pL, double* __restrict__ G_out) {
-  constexpr int C = MultiIndex<D, P>::C;
+  constexpr int C = MultiIndex<D, P, T>::C;
   const int Q = blockIdx.x;
   const int h = blockIdx.y;
   if (Q >= nQ || qt.left[Q] >= 0) return;
@@ -454,19 +641,19 @@ __global__ __launch_bounds__(kW) void leaf_post_kernel(
 #pragma unroll
         for (int k = 1; k < P; ++k) U[d][k] = U[d][k - 1] * u;
       }
-      v += dh_sum<D, P>(p, U, lco + (hb + A) * C);
+      v += dh_sum<D, P, T>(p, U, lco + (hb + A) * C);
     }
     if (active) G_out[(int64_t)h * Mq + qperm[qpos]] = v;
   }
 }
 
-template <int D, int P>
+template <int D, int P, bool T>
 void dh_launch(const int4* slices, int ns, int slice0, const int4* grp, const int32_t* first, int g0,
                int ng, int max_q, const int32_t* ent, const NodeView& qt, const NodeView& rt,
                const double* xq, const double* M, const double* sc, int Mq, double* gdh, double* part,
                hipStream_t s) {
   const unsigned cy = (unsigned)ceil_div(max_q, kW);
-  hipLaunchKernelGGL((dh_fast_kernel<D, P>), dim3((unsigned)ceil_div(ns, kWavesPerBlock), cy),
+  hipLaunchKernelGGL((dh_fast_kernel<D, P, T>), dim3((unsigned)ceil_div(ns, kWavesPerBlock), cy),
                      dim3(kW * kWavesPerBlock), 0, s, slices, ns, grp, ent, qt, rt, xq, M, sc, Mq, gdh,
                      part);
   if (ng > 0 && ns > ng)  // some group has more than one slice
@@ -474,97 +661,113 @@ void dh_launch(const int4* slices, int ns, int slice0, const int4* grp, const in
                        dim3(kW * kWavesPerBlock), 0, s, grp, first, g0, ng, slice0, qt, Mq, part, gdh);
 }
 
-template <int D, int P>
+template <int D, int P, bool T>
 void dl_launch(const SortedGroups& g, const int4* slices, int ns, const int2* first,
                const int32_t* cpre, const int32_t* ent, const NodeView& qt, const NodeView& rt,
                const double* xr, const double* wr, const double* sc, int nQ, double* lco, int32_t* pL,
                double* part, int32_t* part_p, hipStream_t s) {
-  hipLaunchKernelGGL((dl_fast_kernel<D, P>), dim3((unsigned)ceil_div(ns, kWavesPerBlock)),
-                     dim3(kW * kWavesPerBlock), 0, s, slices, ns, g.grp, ent, cpre, qt, rt, xr, wr, sc,
-                     part, part_p);
-  hipLaunchKernelGGL((dl_reduce_kernel<D, P>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),
+  if constexpr (T)
+    hipLaunchKernelGGL((dl_tensor_kernel<D, P>), dim3((unsigned)ns), dim3(kW), 0, s, slices, ns, g.grp,
+                       ent, cpre, qt, rt, xr, wr, sc, part, part_p);
+  else
+    hipLaunchKernelGGL((dl_fast_kernel<D, P>), dim3((unsigned)ceil_div(ns, kWavesPerBlock)),
+                       dim3(kW * kWavesPerBlock), 0, s, slices, ns, g.grp, ent, cpre, qt, rt, xr, wr, sc,
+                       part, part_p);
+  hipLaunchKernelGGL((dl_reduce_kernel<D, P, T>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),
                      dim3(kW * kWavesPerBlock), 0, s, g, first, part, part_p, nQ, lco, pL);
 }
 
-// (D, P) pairs with a compiled specialisation.
+// (D, P) pairs with a compiled specialisation: graded sets at the order
+// limits of section 6, tensor sets at the O(p^D) limits (in one dimension,
+// and at order 1, the two sets coincide and the graded kernels serve both).
 #define GS_FAST_CASES(X) \
-  X(1, 10) X(2, 8) X(3, 6) X(4, 5) X(5, 4) X(6, 2) X(7, 1) X(8, 1) X(16, 1)
+  X(1, 10, false) X(2, 8, false) X(3, 6, false) X(4, 5, false) X(5, 4, false) X(6, 2, false) \
+  X(7, 1, false) X(8, 1, false) X(16, 1, false) \
+  X(2, 8, true) X(3, 6, true) X(4, 4, true) X(5, 3, true) X(6, 2, true)
+
+// The set family a (D, P, tensor) request runs with.
+bool tensor_kernels(int D, int P, bool tensor) { return tensor && D > 1 && P > 1; }
 
 }  // namespace
 
-bool series_fast_available(int D, int P) {
-#define X(d, p) \
-  if (D == d && P == p) return true;
+bool series_fast_available(int D, int P, bool tensor) {
+  const bool t = tensor_kernels(D, P, tensor);
+#define X(d, p, tt) \
+  if (D == d && P == p && t == tt) return true;
   GS_FAST_CASES(X)
 #undef X
   return false;
 }
 
-hipError_t launch_dh_fast(int D, int P, const int4* slices, int ns, int slice0, const int4* grp,
+hipError_t launch_dh_fast(int D, int P, bool tensor, const int4* slices, int ns, int slice0, const int4* grp,
                           const int32_t* first, int g0, int ng, int max_q, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xq_perm,
                           const double* M, const double* sc, int Mq, double* gdh, double* part,
                           hipStream_t s) {
   if (ns == 0) return hipSuccess;
-#define X(d, p)                                                                                 \
-  if (D == d && P == p) {                                                                       \
-    dh_launch<d, p>(slices, ns, slice0, grp, first, g0, ng, max_q, ent, qt, rt, xq_perm, M, sc, \
-                    Mq, gdh, part, s);                                                          \
-    return hipGetLastError();                                                                   \
+  const bool t = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                                                                 \
+  if (D == d && P == p && t == tt) {                                                                \
+    dh_launch<d, p, tt>(slices, ns, slice0, grp, first, g0, ng, max_q, ent, qt, rt, xq_perm, M, sc, \
+                        Mq, gdh, part, s);                                                          \
+    return hipGetLastError();                                                                       \
   }
   GS_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_dl_fast(int D, int P, const SortedGroups& g, const int4* slices, int ns,
+hipError_t launch_dl_fast(int D, int P, bool tensor, const SortedGroups& g, const int4* slices, int ns,
                           const int2* first, const int32_t* cpre, const int32_t* ent,
                           const NodeView& qt, const NodeView& rt, const double* xr_perm,
                           const double* wr_perm, const double* sc, int nQ, double* lco, int32_t* pL,
                           double* part, int32_t* part_p, hipStream_t s) {
   if (g.n == 0 || ns == 0) return hipSuccess;
-#define X(d, p)                                                                                  \
-  if (D == d && P == p) {                                                                        \
-    dl_launch<d, p>(g, slices, ns, first, cpre, ent, qt, rt, xr_perm, wr_perm, sc, nQ, lco, pL,  \
-                    part, part_p, s);                                                            \
-    return hipGetLastError();                                                                    \
+  const bool t = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                                                                   \
+  if (D == d && P == p && t == tt) {                                                                  \
+    dl_launch<d, p, tt>(g, slices, ns, first, cpre, ent, qt, rt, xr_perm, wr_perm, sc, nQ, lco, pL,   \
+                        part, part_p, s);                                                             \
+    return hipGetLastError();                                                                         \
   }
   GS_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int series_terms(int D, int P) { return cbinom(D + P - 1, D); }
+int series_terms(int D, int P, bool tensor) { return tensor ? cpow(P, D) : cbinom(D + P - 1, D); }
 
-hipError_t launch_h2l_fast(int D, int P, const SortedGroups& g, const int32_t* ent,
+hipError_t launch_h2l_fast(int D, int P, bool tensor, const SortedGroups& g, const int32_t* ent,
                            const NodeView& qt, const NodeView& rt, const double* M, const double* sc,
                            int nQ, double* lco, int32_t* pL, double* part, int32_t* part_p,
                            hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-#define X(d, p)                                                                                   \
-  if (D == d && P == p) {                                                                         \
-    hipLaunchKernelGGL((h2l_fast_kernel<d, p>), dim3((unsigned)g.n), dim3(kW), 0, s, g.grp, g.n,   \
-                       ent, qt, rt, M, sc, part, part_p);                                         \
-    hipLaunchKernelGGL((dl_reduce_kernel<d, p>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),   \
-                       dim3(kW * kWavesPerBlock), 0, s, g, (const int2*)nullptr, part, part_p, nQ, \
-                       lco, pL);                                                                  \
-    return hipGetLastError();                                                                     \
+  const bool t = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                                                                    \
+  if (D == d && P == p && t == tt) {                                                                   \
+    hipLaunchKernelGGL((h2l_fast_kernel<d, p, tt>), dim3((unsigned)g.n), dim3(kW), 0, s, g.grp, g.n,    \
+                       ent, qt, rt, M, sc, part, part_p);                                              \
+    hipLaunchKernelGGL((dl_reduce_kernel<d, p, tt>), dim3((unsigned)ceil_div(g.n, kWavesPerBlock)),    \
+                       dim3(kW * kWavesPerBlock), 0, s, g, (const int2*)nullptr, part, part_p, nQ,     \
+                       lco, pL);                                                                       \
+    return hipGetLastError();                                                                          \
   }
   GS_FAST_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_leaf_post_fast(int D, int P, const NodeView& qt, const int32_t* parent, int nQ,
+hipError_t launch_leaf_post_fast(int D, int P, bool tensor, const NodeView& qt, const int32_t* parent, int nQ,
                                  int n_h, int Mq, const double* sc, const double* xq_perm,
                                  const int32_t* qperm, const double* gx, const double* gdh,
                                  const double* Gest, const double* lco, const int32_t* pL,
                                  double* G_out, hipStream_t s) {
-#define X(d, p)                                                                                  \
-  if (D == d && P == p) {                                                                        \
-    hipLaunchKernelGGL((leaf_post_kernel<d, p>), dim3((unsigned)nQ, (unsigned)n_h), dim3(kW), 0,  \
-                       s, qt, parent, nQ, Mq, sc, xq_perm, qperm, gx, gdh, Gest, lco, pL, G_out); \
-    return hipGetLastError();                                                                    \
+  const bool t = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                                                                  \
+  if (D == d && P == p && t == tt) {                                                                 \
+    hipLaunchKernelGGL((leaf_post_kernel<d, p, tt>), dim3((unsigned)nQ, (unsigned)n_h), dim3(kW), 0,  \
+                       s, qt, parent, nQ, Mq, sc, xq_perm, qperm, gx, gdh, Gest, lco, pL, G_out);    \
+    return hipGetLastError();                                                                        \
   }
   GS_FAST_CASES(X)
 #undef X

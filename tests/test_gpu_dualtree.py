@@ -43,6 +43,19 @@ CASES = [
     ("d3_h2l_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 4),
     ("d3_dl_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 2),
     ("d3_dh_only", 3, 1500, None, [0.05, 0.2, 1.0], 32, "dito", 0, 1),
+    # O(p^D) expansions (tensor index sets, generic kernels) and their bounds
+    ("d1_dfto", 1, 900, None, [1e-3, 1e-2, 0.05, 0.3, 2.0], 16, "dfto"),
+    ("d2_dfto", 2, 1500, None, [1e-3, 1e-2, 0.03, 0.1, 0.3, 1.0], 32, "dfto"),
+    ("d3_dfto", 3, 1500, None, [1e-3, 1e-2, 0.05, 0.2, 1.0], 32, "dfto"),
+    ("d4_dfto_256_terms", 4, 1000, None, [0.05, 0.2, 1.0], 32, "dfto"),
+    ("d5_dfto_bi_243_terms", 5, 1000, 400, [0.05, 0.3, 2.0], 32, "dfto"),
+    ("d2_dfto_h2l_only", 2, 1500, None, [0.03, 0.1, 0.3, 1.0], 32, "dfto", 0, 4),
+    ("d3_dfto_h2l_only", 3, 1500, None, [0.1, 0.3, 1.0, 3.0], 32, "dfto", 0, 4),
+    ("d3_dfto_dl_only", 3, 1500, None, [0.1, 0.3, 1.0, 3.0], 32, "dfto", 0, 2),
+    ("d3_dfto_dh_only", 3, 1500, None, [0.1, 0.3, 1.0, 3.0], 32, "dfto", 0, 1),
+    ("d6_dfto_bi", 6, 900, 300, [0.1, 0.5, 3.0], 32, "dfto"),
+    # an order limit without compiled tensor kernels: the generic kernels
+    ("d3_dfto_plimit4_generic", 3, 1500, None, [1e-2, 0.05, 0.2, 1.0], 32, "dfto", 4),
 ]
 
 
@@ -229,3 +242,18 @@ def test_autotune_picks_and_caches_a_configuration():
     c.gauss_sum(r, r, w, hs * 10, 0.01, autotune=1)
     assert c.stats().autotune_trials > 0
     c.close()
+
+
+def test_dfto_rejects_unsupported_options():
+    import paper_1206_6857_amd as g
+    from paper_1206_6857_amd import _lib
+    r, w, _ = _inputs(2, 300, None, 5)
+    c = ctx()
+    for kw in (dict(node_bounds="sphere_rect"), dict(log_pairs=1)):
+        with pytest.raises(g.GaussSumError) as e:
+            c.gauss_sum(r, r, w, [0.1], 0.01, method="dfto", **kw)
+        assert e.value.status == _lib.GS_EINVAL
+    r3, w3, _ = _inputs(3, 300, None, 5)
+    with pytest.raises(g.GaussSumError) as e:
+        c.gauss_sum(r3, r3, w3, [0.1], 0.01, method="dfto", plimit=7)  # 7^3 terms > 286
+    assert e.value.status == _lib.GS_EINVAL
