@@ -70,6 +70,7 @@ CODE = {"DH": DH, "DL": DL, "H2L": H2L}
 NAME = {DH: "DH", DL: "DL", H2L: "H2L"}
 METHODS = ("dito", "dfto", "dfdo", "dfd")
 NODE_BOUNDS = ("box", "sphere_rect")
+PAIR_ORDERS = ("tree", "far_first")
 
 
 class Result:
@@ -82,7 +83,7 @@ class CertificationError(AssertionError):
 
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
              method="dito", mono=None, trace=False, fmm_mask=7, replay=None,
-             record_feasible=False, node_bounds="box"):
+             record_feasible=False, node_bounds="box", pair_order="tree"):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
     decision trace: a list of (h_index, level, Q, R, code, p) tuples.
 
@@ -99,6 +100,12 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     node_bounds: "box" (section 5: distances between bounding boxes) or
     "sphere_rect" (the tighter of the box and the bounding-ball bounds,
     bounds.sphere_rect_dist2).
+    pair_order: the order in which a query node's reference list is walked
+    (and its lower bound summed): "tree" (left to right, the order of the
+    depth-first recursion of Figure 1) or "far_first" (a best-first order in
+    the spirit of the priority-queue traversal the paper mentions: decreasing
+    dmin^2, ties by R, so that the cheap far prunings deposit their tokens
+    before the near pairs ask for them).
     method: "dito" (O(D^p) expansions and tokens), "dfto" (O(p^D) expansions
     and tokens, with the bounds of bounds.e_*_tensor; box bounds only),
     "dfdo" (finite differences and tokens), "dfd" (finite differences, local
@@ -113,6 +120,8 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
         raise ValueError(method)
     if node_bounds not in NODE_BOUNDS:
         raise ValueError(node_bounds)
+    if pair_order not in PAIR_ORDERS:
+        raise ValueError(pair_order)
     if method == "dfto" and node_bounds != "box":
         raise ValueError("the O(p^D) bounds need box distances")
     D = xr.shape[1]
@@ -130,6 +139,7 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.counts = np.zeros((len(hs), 6), dtype=np.int64)
     res.fmm_mask = fmm_mask
     res.node_bounds = node_bounds
+    res.pair_order = pair_order
     res.replay = replay
     res.feasible = {} if record_feasible else None
     for k, h in enumerate(hs):
@@ -158,14 +168,20 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
         nxt = []
         for Q, t, Lp, Rs in segs:
             qleaf = qt.left[Q] < 0
-            geo = []
-            L = Lp
+            dist = []
             for R in Rs:
                 if res.node_bounds == "box":
-                    dmin2, dmax2 = box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])
+                    dist.append(box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R]))
                 else:
-                    dmin2, dmax2 = sphere_rect_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R], qt.ctr[Q],
-                                                     rt.ctr[R], qt.rad[Q], rt.rad[R])
+                    dist.append(sphere_rect_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R], qt.ctr[Q],
+                                                  rt.ctr[R], qt.rad[Q], rt.rad[R]))
+            if res.pair_order == "far_first":
+                order = sorted(range(len(Rs)), key=lambda j: (-dist[j][0], Rs[j]))
+                Rs = [Rs[j] for j in order]
+                dist = [dist[j] for j in order]
+            geo = []
+            L = Lp
+            for R, (dmin2, dmax2) in zip(Rs, dist):
                 kmax = exp64(-dmax2 * inv_2h2)
                 geo.append((dmin2, kmax))
                 L = L + float(rt.W[R]) * kmax

@@ -41,6 +41,33 @@ def test_theorem2_sphere_rect_bounds(D, n):
     assert res.counts.sum() <= box.counts.sum()
 
 
+@pytest.mark.parametrize("D,method", [(2, "dito"), (3, "dito"), (3, "dfto")])
+def test_theorem2_far_first_pair_order(D, method):
+    """A best-first walk of each query node's reference list (decreasing
+    dmin^2) keeps Theorem 2 and covers the same work as the tree order up to
+    a few percent: the order of the walk within a level hardly matters."""
+    x, w, _ = mixture((17, D), 1500, D, 4, (0.02, 0.1), weights=(0.5, 1.5))
+    hs = [1e-3, 0.01, 0.05, 0.2, 1.0]
+    res = DT.dualtree(x, x, w, hs, 0.01, leaf_size=32, method=method, pair_order="far_first", trace=True)
+    rel = _max_rel(res.G, x, x, w, hs)
+    assert np.all(rel <= 0.01), rel
+    tree = DT.dualtree(x, x, w, hs, 0.01, leaf_size=32, method=method)
+    assert abs(res.counts[:, BASE].sum() - tree.counts[:, BASE].sum()) <= 0.1 * tree.counts[:, BASE].sum()
+    # the walk order is the stated one: within every (h, level, Q), in the
+    # order the trace records the decisions, dmin^2 does not increase and
+    # equal distances come by increasing R
+    from oracle.bounds import box_dist2
+    qt, rt = res.qtree, res.rtree
+    last = {}
+    for hk, lvl, Q, R, code, p in res.trace:
+        d2 = box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])[0]
+        key = (hk, lvl, Q)
+        if key in last:
+            pd2, pR = last[key]
+            assert d2 < pd2 or (d2 == pd2 and R > pR), (key, pd2, pR, d2, R)
+        last[key] = (d2, R)
+
+
 @pytest.mark.parametrize("D", [2, 3])
 def test_theorem2_bichromatic(D):
     r, w, q = mixture((12, D), 1500, D, 4, (0.02, 0.1), weights=(0.5, 1.5), m_queries=700)
