@@ -281,8 +281,9 @@ __global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel
 // masks.  Every expression and its operation order is that of the
 // single-threaded formulation, so the decisions and sums are identical to it.
 // GEN: the learned policy or logging may be on; without them the walk
-// compiles to the rule alone.
-template <int P, bool GEN>
+// compiles to the rule alone.  TEN: the O(p^D) bounds (tensor index sets)
+// instead of the O(D^p) ones.
+template <int P, bool GEN, bool TEN>
 __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, FrontierLevel cur, TreeView qt,
                                                     TreeView rt, const double* __restrict__ inv2h2,
                                                     const double* __restrict__ inv4h2,
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         const double rR = rt.rinf[R] * ih;
         const double base_e = WR * g;
         double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY;
-        if (c.tensor) {
+        if constexpr (TEN) {
           // O(p^D) bounds: a = sum_{n<p} rho^n / sqrt(n!) grows by one term
           // per order; b = rho^p / sqrt(p!) / (1 - rho / sqrt(p+1)).
           TensorPart tR(rR), tQ(rQ), tR2(kSqrt2 * rR), tQ2(kSqrt2 * rQ);
@@ -840,16 +841,22 @@ hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const Tre
   hipLaunchKernelGGL(pair_prep_kernel, dim3((unsigned)ceil_div(npair, 256)), dim3(256), 0, s, npair,
                      cur, qt, rt, inv2h2, inv4h2, c.D, c.node_bounds, prep);
   const bool gen = c.policy != 0 || c.log_feas != 0 || scores != nullptr || feas != nullptr;
-#define GS_DECIDE(PP)                                                                           \
-  case PP:                                                                                     \
-    if (gen)                                                                                   \
-      hipLaunchKernelGGL((decide_kernel<PP, true>), dim3((unsigned)(S + n_first)), dim3(64), 0, \
-                         s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code, porder, \
-                         Gest, cnt, scores, feas, prep, npair);                                \
-    else                                                                                       \
-      hipLaunchKernelGGL((decide_kernel<PP, false>), dim3((unsigned)(S + n_first)), dim3(64),  \
-                         0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code,     \
-                         porder, Gest, cnt, scores, feas, prep, npair);                        \
+  // the policy and its logging serve the O(D^p) path only
+  if (gen && c.tensor) return hipErrorInvalidValue;
+#define GS_DECIDE(PP)                                                                                \
+  case PP:                                                                                          \
+    if (c.tensor)                                                                                   \
+      hipLaunchKernelGGL((decide_kernel<PP, false, true>), dim3((unsigned)(S + n_first)), dim3(64), \
+                         0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code, porder,  \
+                         Gest, cnt, scores, feas, prep, npair);                                     \
+    else if (gen)                                                                                   \
+      hipLaunchKernelGGL((decide_kernel<PP, true, false>), dim3((unsigned)(S + n_first)), dim3(64), \
+                         0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code, porder,  \
+                         Gest, cnt, scores, feas, prep, npair);                                     \
+    else                                                                                            \
+      hipLaunchKernelGGL((decide_kernel<PP, false, false>), dim3((unsigned)(S + n_first)),          \
+                         dim3(64), 0, s, S, n_first, cur, qt, rt, inv2h2, inv4h2, invh, nQ, c, code,\
+                         porder, Gest, cnt, scores, feas, prep, npair);                             \
     break;
   switch (c.P) {
     GS_DECIDE(1) GS_DECIDE(2) GS_DECIDE(3) GS_DECIDE(4) GS_DECIDE(5)

@@ -257,3 +257,33 @@ def test_dfto_rejects_unsupported_options():
     with pytest.raises(g.GaussSumError) as e:
         c.gauss_sum(r3, r3, w3, [0.1], 0.01, method="dfto", plimit=7)  # 7^3 terms > 286
     assert e.value.status == _lib.GS_EINVAL
+
+
+def test_repeated_calls_alternating_inputs():
+    """Calls alternate between two inputs of the same size, so every call
+    reuses the previous call's buffers: every tree is bit-exact with the
+    oracle's tree of its own input and every result equals the first result
+    for the same input."""
+    from oracle.kdtree import build_kdtree
+    D, N, M, leaf = 3, 2500, 900, 32
+    data = [_inputs(D, N, M, 300 + k) for k in range(2)]
+    hs = np.array([0.02, 0.1, 0.5])
+    c = ctx()
+    first = {}
+    for call, k in enumerate([0, 1, 0, 1, 0, 1]):
+        banner("alternating inputs", call, k)
+        r, w, q = data[k]
+        G = c.gauss_sum(q, r, w, hs, 0.01, leaf_size=leaf, keep_trace=1)
+        for which, x, wt in ((0, r, w), (1, q, None)):
+            want = build_kdtree(x, wt, leaf)
+            gt = c.get_tree(which, D)
+            assert np.array_equal(gt["perm"], want.perm), (call, which)
+            assert np.array_equal(gt["begin"], want.begin) and np.array_equal(gt["left"], want.left)
+            for f in ("lo", "hi", "ctr", "rinf"):
+                assert np.array_equal(gt[f], getattr(want, f)), (call, which, f)
+            if which == 0:
+                assert np.array_equal(gt["W"], want.W) and np.array_equal(gt["wmin"], want.wmin)
+        if k in first:
+            assert np.array_equal(G, first[k]), call
+        else:
+            first[k] = G
