@@ -512,9 +512,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   if (use_fmm) {
     Mom = BUF(double, "moments", (int64_t)nR * C);
     KernelTimer km(ctx, ctx->kernel_timing, GS_K_MOMENTS, st);
-    DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, st));
+    if (series_fast_available(D, P, tensor))
+      DT_HIP(launch_p2m_fast(D, P, tensor, rv, nR, xr_perm, wr_perm, Mom, st));
+    else
+      DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, st));
     for (int lv = (int)rt.level_begin.size() - 2; lv >= 0; --lv)
-      DT_HIP(launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st));
+      DT_HIP(series_fast_available(D, P, tensor)
+                 ? launch_h2h_level_fast(D, P, tensor, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st)
+                 : launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st));
     km.stop(st, (int)rt.level_begin.size());
   }
   double t2 = now_ms();

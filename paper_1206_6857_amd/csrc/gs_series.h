@@ -98,6 +98,13 @@ hipError_t launch_h2l_fast(int D, int P, bool tensor, const SortedGroups& g, con
                            const NodeView& qt, const NodeView& rt, const double* M, const double* sc,
                            int nQ, double* lco, int32_t* pL, double* part, int32_t* part_p,
                            hipStream_t s);
+// H2H of the internal nodes [lb, le) of one tree level, as launch_h2h_level.
+hipError_t launch_h2h_level_fast(int D, int P, bool tensor, const NodeView& t, int lb, int le, double* M,
+                                 hipStream_t s);
+// Leaf moments (raw, h-independent) of every leaf node (internal nodes are
+// left alone; H2H fills them), as launch_p2m.
+hipError_t launch_p2m_fast(int D, int P, bool tensor, const NodeView& t, int n_nodes, const double* xperm,
+                           const double* wperm, double* M, hipStream_t s);
 // Size of the DL partial coefficient vectors (C(D+P-1, D), or P^D for tensor sets).
 int series_terms(int D, int P, bool tensor);
 // Post-pass in one launch (grid: query nodes x bandwidths, internal nodes

@@ -482,6 +482,226 @@ __global__ __launch_bounds__(kW) void dl_tensor_kernel(
   if (lane == 0) part_p[i] = pmax;
 }
 
+// Leaf moments (Figure 5, buildLeaf): M_a = sum_r w_r (x_r - x_R)^a / a!, one
+// wave per node (internal nodes exit).  Graded sets: lanes over the points,
+// per-lane partial moments reduced across the wave at the end.  Tensor sets:
+// the product form of dl_tensor_kernel with powers in place of Hermite
+// values (the moments are sums of outer products of per-dimension powers).
+template <int D, int P>
+__global__ __launch_bounds__(kW) void p2m_graded_kernel(NodeView t, int n_nodes, const double* __restrict__ xperm,
+                                                        const double* __restrict__ wperm,
+                                                        double* __restrict__ M) {
+  static constexpr MultiIndex<D, P> mi{};
+  constexpr int C = MultiIndex<D, P>::C;
+  const int node = blockIdx.x;
+  if (node >= n_nodes || t.left[node] >= 0) return;
+  const int lane = threadIdx.x;
+  const int b = t.begin[node], n = t.count[node];
+  double c[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) c[d] = t.ctr[(int64_t)node * D + d];
+  double B[C];
+#pragma unroll
+  for (int a = 0; a < C; ++a) B[a] = 0.0;
+  for (int base = 0; base < n; base += kW) {
+    if (base + lane >= n) continue;
+    const int pos = b + base + lane;
+    double U[D][P];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double u = xperm[(int64_t)pos * D + d] - c[d];
+      U[d][0] = 1.0;
+#pragma unroll
+      for (int k = 1; k < P; ++k) U[d][k] = U[d][k - 1] * u;
+    }
+    const double w = wperm[pos];
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      double term = w;
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (mi.a[a][d]) term *= U[d][mi.a[a][d]];
+      B[a] += term;
+    }
+  }
+  double* out = M + (int64_t)node * C;
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    const double v = wave_sum(B[a]);
+    if (lane == 0) out[a] = v * mi.invf[a];
+  }
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(kW) void p2m_tensor_kernel(NodeView t, int n_nodes, const double* __restrict__ xperm,
+                                                        const double* __restrict__ wperm,
+                                                        double* __restrict__ M) {
+  static constexpr MultiIndex<D, P, true> mi{};
+  static constexpr TensorPos<D, P> tp{};
+  constexpr int C = MultiIndex<D, P, true>::C;
+  constexpr int NT = cpow(P, D - 1);
+  constexpr int G = (NT < kW && kW % NT == 0) ? kW / NT : 1;
+  constexpr int NJ = G > 1 ? 1 : (NT + kW - 1) / kW;
+  __shared__ double u[kW][D][P];
+  const int node = blockIdx.x;
+  if (node >= n_nodes || t.left[node] >= 0) return;
+  const int lane = threadIdx.x;
+  const int b = t.begin[node], n = t.count[node];
+  double c[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) c[d] = t.ctr[(int64_t)node * D + d];
+  const int grpi = G > 1 ? lane / NT : 0;
+  int combo[NJ], tb[NJ][D];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    combo[j] = G > 1 ? lane % NT : j * kW + lane;
+    int r = combo[j] < NT ? combo[j] : 0;
+#pragma unroll
+    for (int d = D - 1; d >= 1; --d) {
+      tb[j][d] = r % P;
+      r /= P;
+    }
+    tb[j][0] = 0;
+  }
+  double B[NJ][P];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int k = 0; k < P; ++k) B[j][k] = 0.0;
+  for (int base = 0; base < n; base += kW) {
+    const int cnt = n - base < kW ? n - base : kW;
+    __syncthreads();  // the previous chunk's reads of u are done
+    if (lane < cnt) {
+      const int pos = b + base + lane;
+      const double w = wperm[pos];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const double x = xperm[(int64_t)pos * D + d] - c[d];
+        double v = d == 0 ? w : 1.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          u[lane][d][k] = v;
+          v *= x;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (combo[j] >= NT) continue;
+      for (int r = grpi; r < cnt; r += G) {
+        double prod = 1.0;
+#pragma unroll
+        for (int d = 1; d < D; ++d) prod *= u[r][d][tb[j][d]];
+#pragma unroll
+        for (int q = 0; q < P; ++q) B[j][q] += u[r][0][q] * prod;
+      }
+    }
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int off = NT; off < kW; off <<= 1)
+#pragma unroll
+      for (int q = 0; q < P; ++q) B[0][q] += __shfl_xor(B[0][q], off, kW);
+  }
+  double* out = M + (int64_t)node * C;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    if (combo[j] >= NT || grpi != 0) continue;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int i = tp.pos[q * NT + combo[j]];
+      out[i] = B[j][q] * mi.invf[i];
+    }
+  }
+}
+
+// Position in the set's order of every multi-index of the dense box
+// [0, P)^D (row-major), -1 outside the set.
+template <int D, int P, bool T>
+struct DensePos {
+  int pos[cpow(P, D)];
+  int dense[MultiIndex<D, P, T>::C];
+  constexpr DensePos() : pos(), dense() {
+    constexpr MultiIndex<D, P, T> mi{};
+    for (int i = 0; i < cpow(P, D); ++i) pos[i] = -1;
+    for (int i = 0; i < MultiIndex<D, P, T>::C; ++i) {
+      int x = 0;
+      for (int d = 0; d < D; ++d) x = x * P + mi.a[i][d];
+      pos[x] = i;
+      dense[i] = x;
+    }
+  }
+};
+
+// H2H (Lemma 2, raw moments) of the internal nodes [lb, le) of one level:
+// M_g = sum over both children of sum_{a<=g} M'_a prod_d u_d^{g_d-a_d}/(g_d-a_d)!,
+// u = x_child - x_node.  The translation is a product over dimensions, so it
+// is applied as D one-dimensional passes (pass d replaces index d), each term
+// costing at most P multiply-adds instead of the product over all a <= g.
+// Both index families are closed under lowering a component, so every
+// intermediate index stays in the set.  One wave per node, lanes over terms,
+// the coefficient vector in LDS between passes.
+template <int D, int P, bool T>
+__global__ __launch_bounds__(kW) void h2h_fast_kernel(NodeView t, int lb, int le, double* __restrict__ M) {
+  static constexpr MultiIndex<D, P, T> mi{};
+  static constexpr DensePos<D, P, T> dp{};
+  constexpr int C = MultiIndex<D, P, T>::C;
+  constexpr int NB = (C + kW - 1) / kW;
+  __shared__ double X[C];
+  const int node = lb + blockIdx.x;
+  if (node >= le) return;
+  const int l = t.left[node];
+  if (l < 0) return;
+  const int lane = threadIdx.x;
+  int stride[D];
+  stride[D - 1] = 1;
+#pragma unroll
+  for (int d = D - 2; d >= 0; --d) stride[d] = stride[d + 1] * P;
+  double acc[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) acc[u] = 0.0;
+  for (int ch = 0; ch < 2; ++ch) {
+    const int c = l + ch;
+    double tr[D][P];  // u_d^m / m!
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double u = t.ctr[(int64_t)c * D + d] - t.ctr[(int64_t)node * D + d];
+      tr[d][0] = 1.0;
+#pragma unroll
+      for (int m = 1; m < P; ++m) tr[d][m] = tr[d][m - 1] * u / (double)m;
+    }
+    __syncthreads();  // the previous child's reads of X are done
+    for (int i = lane; i < C; i += kW) X[i] = M[(int64_t)c * C + i];
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double y[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int i = u * kW + lane;
+        y[u] = 0.0;
+        if (i < C) {
+          const int g = mi.a[i][d];
+          const int base = dp.dense[i] - g * stride[d];
+          for (int k = 0; k <= g; ++k) y[u] += tr[d][g - k] * X[dp.pos[base + k * stride[d]]];
+        }
+      }
+      __syncthreads();  // every lane has read this pass's input
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (u * kW + lane < C) X[u * kW + lane] = y[u];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (u * kW + lane < C) acc[u] += X[u * kW + lane];
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (u * kW + lane < C) M[(int64_t)node * C + u * kW + lane] = acc[u];
+}
+
 // H2L (Lemma 1): B_b(Q) += (-1)^|b| / b! sum_{|a|<p} A_a h_{a+b}(t), t = (x_Q - x_R) s,
 // one wave per H2L group (its entries in order), lanes over b.  Per entry the
 // 1-D Hermite polynomials of orders < 2P-1 go to LDS; lane b forms
@@ -677,6 +897,22 @@ void dl_launch(const SortedGroups& g, const int4* slices, int ns, const int2* fi
                      dim3(kW * kWavesPerBlock), 0, s, g, first, part, part_p, nQ, lco, pL);
 }
 
+template <int D, int P, bool T>
+void h2h_launch(const NodeView& t, int lb, int le, double* M, hipStream_t s) {
+  hipLaunchKernelGGL((h2h_fast_kernel<D, P, T>), dim3((unsigned)(le - lb)), dim3(kW), 0, s, t, lb, le, M);
+}
+
+template <int D, int P, bool T>
+void p2m_launch(const NodeView& t, int n_nodes, const double* xperm, const double* wperm, double* M,
+                hipStream_t s) {
+  if constexpr (T)
+    hipLaunchKernelGGL((p2m_tensor_kernel<D, P>), dim3((unsigned)n_nodes), dim3(kW), 0, s, t, n_nodes, xperm,
+                       wperm, M);
+  else
+    hipLaunchKernelGGL((p2m_graded_kernel<D, P>), dim3((unsigned)n_nodes), dim3(kW), 0, s, t, n_nodes, xperm,
+                       wperm, M);
+}
+
 // (D, P) pairs with a compiled specialisation: graded sets at the order
 // limits of section 6, tensor sets at the O(p^D) limits (in one dimension,
 // and at order 1, the two sets coincide and the graded kernels serve both).
@@ -751,6 +987,33 @@ hipError_t launch_h2l_fast(int D, int P, bool tensor, const SortedGroups& g, con
                        dim3(kW * kWavesPerBlock), 0, s, g, (const int2*)nullptr, part, part_p, nQ,     \
                        lco, pL);                                                                       \
     return hipGetLastError();                                                                          \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_h2h_level_fast(int D, int P, bool tensor, const NodeView& t, int lb, int le, double* M,
+                                 hipStream_t s) {
+  if (le <= lb) return hipSuccess;
+  const bool tk = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                   \
+  if (D == d && P == p && tk == tt) {                 \
+    h2h_launch<d, p, tt>(t, lb, le, M, s);            \
+    return hipGetLastError();                         \
+  }
+  GS_FAST_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_p2m_fast(int D, int P, bool tensor, const NodeView& t, int n_nodes, const double* xperm,
+                           const double* wperm, double* M, hipStream_t s) {
+  const bool tk = tensor_kernels(D, P, tensor);
+#define X(d, p, tt)                                                       \
+  if (D == d && P == p && tk == tt) {                                     \
+    p2m_launch<d, p, tt>(t, n_nodes, xperm, wperm, M, s);                 \
+    return hipGetLastError();                                             \
   }
   GS_FAST_CASES(X)
 #undef X
