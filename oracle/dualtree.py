@@ -71,6 +71,7 @@ NAME = {DH: "DH", DL: "DL", H2L: "H2L"}
 METHODS = ("dito", "dfto", "dfdo", "dfd")
 NODE_BOUNDS = ("box", "sphere_rect")
 PAIR_ORDERS = ("tree", "far_first")
+TRAVERSALS = ("level", "depth_first")
 
 
 class Result:
@@ -83,7 +84,7 @@ class CertificationError(AssertionError):
 
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
              method="dito", mono=None, trace=False, fmm_mask=7, replay=None,
-             record_feasible=False, node_bounds="box", pair_order="tree"):
+             record_feasible=False, node_bounds="box", pair_order="tree", traversal="level"):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
     decision trace: a list of (h_index, level, Q, R, code, p) tuples.
 
@@ -106,6 +107,9 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     the spirit of the priority-queue traversal the paper mentions: decreasing
     dmin^2, ties by R, so that the cheap far prunings deposit their tokens
     before the near pairs ask for them).
+    traversal: "level" (the frontier mode above, which the library follows)
+    or "depth_first" (paper mode: the recursion of Figures 1 and 7 in its
+    printed order, _depth_first_decisions; no replay, no feasibility log).
     method: "dito" (O(D^p) expansions and tokens), "dfto" (O(p^D) expansions
     and tokens, with the bounds of bounds.e_*_tensor; box bounds only),
     "dfdo" (finite differences and tokens), "dfd" (finite differences, local
@@ -122,6 +126,10 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
         raise ValueError(node_bounds)
     if pair_order not in PAIR_ORDERS:
         raise ValueError(pair_order)
+    if traversal not in TRAVERSALS:
+        raise ValueError(traversal)
+    if traversal == "depth_first" and (replay is not None or record_feasible or pair_order != "tree"):
+        raise ValueError("depth-first mode keeps the tree order and records no feasibility or replay")
     if method == "dfto" and node_bounds != "box":
         raise ValueError("the O(p^D) bounds need box distances")
     D = xr.shape[1]
@@ -140,6 +148,7 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.fmm_mask = fmm_mask
     res.node_bounds = node_bounds
     res.pair_order = pair_order
+    res.traversal = traversal
     res.replay = replay
     res.feasible = {} if record_feasible else None
     for k, h in enumerate(hs):
@@ -164,6 +173,9 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
     work = []  # (code, Q, R, p) in emission order
     segs = [(0, 0.0, 0.0, [0])]
     level = 0
+    if res.traversal == "depth_first":
+        work = _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest)
+        segs = []
     while segs:
         nxt = []
         for Q, t, Lp, Rs in segs:
@@ -264,6 +276,13 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
         segs = nxt
         level += 1
 
+    return _execute(h, qt, rt, xq, D, fam, work, Gest, lco, pL)
+
+
+def _execute(h, qt, rt, xq, D, fam, work, Gest, lco, pL):
+    """Runs the recorded work (base cases, DH, DL, H2L), then the post-pass of
+    Figure 8; returns G~ for every query in input order."""
+    nQ = qt.n_nodes
     # Execute the recorded work.
     M = xq.shape[0]
     gx = np.zeros(M)
@@ -306,3 +325,128 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                 val = val + eval_local(lco[Q], pL[Q], qt.ctr[Q], xq[qpts], h, fam)
             G[qpts] = val
     return G
+
+
+def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
+    """Paper mode: the node pairs in the depth-first order of Figure 1 (for a
+    pair that is neither approximated nor a base case: (Q.l,R.l), (Q.l,R.r),
+    (Q.r,R.l), (Q.r,R.r), or the two pairs of the internal node when the other
+    is a leaf), each decided as in Figure 7.  Returns the work list; fills
+    Gest and the trace like the frontier mode.
+
+    Readings (Figure 7 leaves the bookkeeping open):
+      * each query node has its own token slot Q.W_T; a node's slot starts as
+        a copy of its parent's slot when the recursion first reaches it, and
+        only decisions at Q change it afterwards (no flow back to the parent);
+      * G_Q^min is the sum of W_R K(dmax) over the reference nodes resolved at
+        Q or an ancestor and over the pairs still pending (on the recursion
+        stack) at Q or an ancestor, each with the query node it was formed
+        with, in a fixed order; reference nodes resolved only at descendants
+        of Q are left out, so the bound is valid for every point of Q (looser
+        than it could be, never above G);
+      * monochromatic self bound, tokens, maxerr, costs and ties as in the
+        frontier mode.
+    The trace's level field holds the recursion depth of the pair."""
+    D = rt.D
+    use_tokens = method in ("dito", "dfto", "dfdo")
+    use_fmm = method in ("dito", "dfto")
+    fam = res.family
+    inv_2h2 = 1.0 / (2.0 * h * h)
+    inv_4h2 = 0.5 * inv_2h2
+    inv_h = 1.0 / h
+    Wtot = float(rt.W[0])
+    parent = {}
+    for Q in range(qt.n_nodes):
+        if qt.left[Q] >= 0:
+            parent[int(qt.left[Q])] = Q
+            parent[int(qt.left[Q]) + 1] = Q
+
+    def ancestors(Q):
+        out = [Q]
+        while out[-1] in parent:
+            out.append(parent[out[-1]])
+        return out[::-1]  # root first
+
+    def dist2(Q, R):
+        if res.node_bounds == "box":
+            return box_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R])
+        return sphere_rect_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R], qt.ctr[Q], rt.ctr[R], qt.rad[Q],
+                                 rt.rad[R])
+
+    T = {0: 0.0}
+    resolved = {}   # Q -> list of W_R K(dmax) of pairs resolved at Q, in order
+    pending = {}    # Q -> {R: W_R K(dmax)} of pairs on the stack
+    work = []
+
+    def push(Q, R, depth, stack):
+        dmin2, dmax2 = dist2(Q, R)
+        pending.setdefault(Q, {})[R] = float(rt.W[R]) * exp64(-dmax2 * inv_2h2)
+        stack.append((Q, R, depth, dmin2, dmax2))
+
+    stack = []
+    push(0, 0, 0, stack)
+    while stack:
+        Q, R, depth, dmin2, dmax2 = stack.pop()
+        L = 0.0
+        for A in ancestors(Q):
+            for v in resolved.get(A, ()):
+                L = L + v
+            for R2 in sorted(pending.get(A, {})):
+                L = L + pending[A][R2]
+        if mono and float(qt.wmin[Q]) > L:
+            L = float(qt.wmin[Q])
+        bound = pending[Q].pop(R)
+        t = T[Q]
+        WR = float(rt.W[R])
+        kmax = exp64(-dmax2 * inv_2h2)
+        kmin = exp64(-dmin2 * inv_2h2)
+        nd = need(e_fd(WR, kmin, kmax), WR, L, Wtot, eps_alg)
+        code, p = None, 0
+        if nd <= (t if use_tokens else 0.0):
+            if use_tokens:
+                t = t - nd
+            Gest[Q] = Gest[Q] + 0.5 * (WR * (kmin + kmax))
+            code = FD
+        elif use_fmm:
+            tt = t if use_tokens else 0.0
+            maxerr = ((eps_alg * (WR + tt)) * L) / Wtot
+            g = exp64(-dmin2 * inv_4h2)
+            rQ, rR = float(qt.rinf[Q]) * inv_h, float(rt.rinf[R]) * inv_h
+            name, p, E = best_method(D, P, maxerr, WR, g, rQ, rR, int(qt.count[Q]), int(rt.count[R]),
+                                     mask=res.fmm_mask, family=fam)
+            if name != "DIRECT":
+                if use_tokens:
+                    t = t - need(E, WR, L, Wtot, eps_alg)
+                code = CODE[name]
+            else:
+                p = 0
+        qleaf, rleaf = qt.left[Q] < 0, rt.left[R] < 0
+        if code is None:
+            if qleaf and rleaf:
+                if use_tokens:
+                    t = t + WR
+                code = BASE
+            else:
+                code = SPLIT
+        T[Q] = t
+        res.counts[hk, code] += 1
+        if res.trace is not None:
+            res.trace.append((hk, depth, Q, R, code, p))
+        if code != SPLIT:
+            resolved.setdefault(Q, []).append(bound)
+            if code != FD:
+                work.append((code, Q, R, p))
+            continue
+        if qleaf:
+            kids = [(Q, int(rt.left[R])), (Q, int(rt.left[R]) + 1)]
+        elif rleaf:
+            kids = [(int(qt.left[Q]), R), (int(qt.left[Q]) + 1, R)]
+        else:
+            ql, rl = int(qt.left[Q]), int(rt.left[R])
+            kids = [(ql, rl), (ql, rl + 1), (ql + 1, rl), (ql + 1, rl + 1)]
+        for Qc, _ in kids:
+            if Qc not in T:
+                T[Qc] = t
+        for Qc, Rc in reversed(kids):
+            push(Qc, Rc, depth + 1, stack)
+    return work

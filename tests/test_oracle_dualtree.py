@@ -68,6 +68,37 @@ def test_theorem2_far_first_pair_order(D, method):
         last[key] = (d2, R)
 
 
+@pytest.mark.parametrize("D,method,M", [(1, "dito", None), (2, "dito", None), (3, "dito", None),
+                                         (2, "dfto", None), (3, "dfdo", None), (2, "dito", 600)])
+def test_theorem2_depth_first_paper_mode(D, method, M):
+    """Paper mode (the recursion of Figures 1 and 7 in its printed order)
+    keeps Theorem 2 and resolves every (query, reference) point pair exactly
+    once."""
+    r, w, q = mixture((19, D), 1500, D, 4, (0.02, 0.1), weights=(0.5, 1.5), m_queries=M)
+    q = r if M is None else q
+    # (far queries of the bichromatic case underflow at h = 1e-3: G = 0 there)
+    hs = [1e-3, 0.01, 0.05, 0.2, 1.0] if M is None else [0.01, 0.05, 0.2, 1.0]
+    res = DT.dualtree(q, r, w, hs, 0.01, leaf_size=32, method=method, traversal="depth_first", trace=True)
+    rel = _max_rel(res.G, q, r, w, hs)
+    assert np.all(rel <= 0.01), rel
+    qt, rt = res.qtree, res.rtree
+    for k in range(len(hs)):
+        cover = np.zeros((q.shape[0], r.shape[0]), dtype=np.int64)
+        for hk, depth, Q, R, code, p in res.trace:
+            if hk == k and code != SPLIT:
+                cover[np.ix_(qt.perm[qt.begin[Q]:qt.end[Q]], rt.perm[rt.begin[R]:rt.end[R]])] += 1
+        assert np.all(cover == 1), k
+
+
+def test_depth_first_rejects_frontier_only_options():
+    x, w, _ = mixture((3, 2), 200, 2, 2, 0.1)
+    for kw in (dict(record_feasible=True), dict(pair_order="far_first"), dict(replay={})):
+        with pytest.raises(ValueError):
+            DT.dualtree(x, x, w, [0.1], 0.01, traversal="depth_first", **kw)
+    with pytest.raises(ValueError):
+        DT.dualtree(x, x, w, [0.1], 0.01, traversal="breadth")
+
+
 @pytest.mark.parametrize("D", [2, 3])
 def test_theorem2_bichromatic(D):
     r, w, q = mixture((12, D), 1500, D, 4, (0.02, 0.1), weights=(0.5, 1.5), m_queries=700)
