@@ -82,8 +82,10 @@ typedef struct gs_options {
   int32_t log_pairs;        /* 1: record policy-training features and costs */
   int32_t fmm_mask;         /* series methods bestMethod may choose (Figure 6): bit 0
                                DH, bit 1 DL, bit 2 H2L; 0 or 7 allows all (ablations) */
-  int32_t kernel_timing;    /* 1: time kernel classes with HIP events on the context's
-                               stream (gs_stats.k_ms / k_launches) */
+  int32_t kernel_timing;    /* 1: time every kernel class with HIP events on the stream
+                               it runs on (gs_stats.k_ms / k_launches); 2: time only
+                               the base-case tiles (GS_K_BASE) and the exhaustive
+                               tiles (one event pair per call); 0: none */
   int32_t h_chunk;          /* most bandwidths traversed together (0: all); the
                                library halves it by itself when a frontier outgrows
                                2^30 pairs or device memory.  Results do not depend
@@ -127,7 +129,8 @@ typedef struct gs_stats {
                                bound did not admit (the cheapest admitted one taken) */
   double t_stage_ms, t_tree_ms, t_moments_ms, t_traverse_ms, t_work_ms, t_post_ms;
   double t_total_ms;        /* wall time of the last gauss_sum call */
-  /* With kernel_timing = 1: device milliseconds and launch counts per kernel class,
+  /* With kernel_timing (1: all classes, 2: GS_K_BASE and GS_K_EXHAUSTIVE only): device
+   * milliseconds and launch counts per kernel class,
    * indexed by GS_K_*. */
   double k_ms[12];
   int64_t k_launches[12];

@@ -97,7 +97,7 @@ static hipEvent_t pooled_event(gs_ctx_base* ctx) {
 }
 
 KernelTimer::KernelTimer(gs_ctx_base* c, bool enabled, int k, hipStream_t s) : ctx(c), cls(k) {
-  if (!enabled) return;
+  if (!enabled || !((c->timing_mask >> k) & 1u)) return;
   a = pooled_event(ctx);
   b = pooled_event(ctx);
   if (!a || !b) return;
@@ -224,6 +224,17 @@ gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream) {
     }
     ctx->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+    if (ctx->side) hipStreamDestroy(ctx->side);
+    if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GS_EDEVICE;
+  }
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
   policy_default_costs(ctx->policy);
   *out = ctx;
@@ -237,6 +248,10 @@ gs_status gs_destroy(gs_ctx* ctx) {
   flush_kernel_timers(ctx);
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   ctx->ev_pool.clear();
+  hipStreamSynchronize(ctx->side);
+  hipStreamDestroy(ctx->side);
+  hipEventDestroy(ctx->fork_ev);
+  hipEventDestroy(ctx->join_ev);
   ctx->ws.release_all();
   if (ctx->own_stream) hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -505,6 +520,7 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     GS_FAIL(ctx, GS_EINVAL, "eps must be in (0, 1)");
   if (opt.leaf_size < 1 || opt.leaf_size > 1024) GS_FAIL(ctx, GS_EINVAL, "leaf_size must be in [1, 1024]");
   if (opt.h_chunk < 0) GS_FAIL(ctx, GS_EINVAL, "h_chunk must be >= 0");
+  if (opt.kernel_timing < 0 || opt.kernel_timing > 2) GS_FAIL(ctx, GS_EINVAL, "kernel_timing must be 0, 1 or 2");
   if (opt.node_bounds != GS_BOUNDS_BOX && opt.node_bounds != GS_BOUNDS_SPHERE_RECT)
     GS_FAIL(ctx, GS_EINVAL, "node_bounds must be GS_BOUNDS_BOX or GS_BOUNDS_SPHERE_RECT");
   if (opt.max_frontier < 0) GS_FAIL(ctx, GS_EINVAL, "max_frontier must be >= 0");
@@ -613,6 +629,9 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     ctx->policy.log_keys.clear();
     ctx->host_tree[0].valid = ctx->host_tree[1].valid = false;
     ctx->kernel_timing = o.kernel_timing != 0;
+    ctx->timing_mask = o.kernel_timing == 1   ? ~0u
+                       : o.kernel_timing == 2 ? (1u << GS_K_BASE) | (1u << GS_K_EXHAUSTIVE)
+                                              : 0u;
     if (o.method == GS_EXHAUSTIVE) {
       float* rec = WS(float, "ex_rec", N * exhaustive_record_stride(D));
       unsigned long long* wb = WS(unsigned long long, "wmax_bits", 1);

@@ -956,30 +956,51 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       DT_HIP(rocprim::radix_sort_pairs(ba.temp, bytes, gkey[x], const_cast<unsigned long long*>(sg[x].key),
                                        gidx[x], const_cast<int32_t*>(sg[x].order), (unsigned)n, 0, 64, st));
     }
+    // The expansions write gdh, lco and pL only, the base cases gx only: the
+    // expansions go to the side stream and overlap the base-case plan (whose
+    // readbacks wait for the main stream alone) and tiles.  The side stream
+    // is joined back when the chunk returns.  Pair logging keeps one stream:
+    // its cost model is calibrated from the kernels' own times.
+    struct SideJoin {
+      hipStream_t st = nullptr, ss = nullptr;
+      hipEvent_t ev = nullptr;
+      ~SideJoin() {
+        if (ss != st && (hipEventRecord(ev, ss) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess))
+          (void)hipGetLastError();
+      }
+    } join;
+    join.st = join.ss = st;
+    hipStream_t ss = st;
+    if (use_fmm && !log_pairs && ctx->side) {
+      DT_HIP(hipEventRecord(ctx->fork_ev, st));
+      DT_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+      ss = join.ss = ctx->side;
+      join.ev = ctx->join_ev;
+    }
     if (use_fmm) {
-      KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, st);
+      KernelTimer kt(ctx, ctx->kernel_timing, GS_K_SERIES, ss);
       {
-        KernelTimer kd(ctx, ctx->kernel_timing, GS_K_DL, st);
+        KernelTimer kd(ctx, ctx->kernel_timing, GS_K_DL, ss);
         if (fast)
           DT_HIP(launch_dl_fast(D, P, tensor, sg[1], wl.dl_slice, (int)used_slc[1], wl.dl_first, wl.dl_cpre,
                                 wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, dl_part,
-                                dl_part_p, st));
+                                dl_part_p, ss));
         else
-          DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, st));
-        kd.stop(st, fast ? 2 : 1);
+          DT_HIP(launch_dl(T, sg[1], wl.ent[1], qv, rv, xr_perm, wr_perm, d_sc, nQ, lco, pL, ss));
+        kd.stop(ss, fast ? 2 : 1);
       }
       {
-        KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, st);
+        KernelTimer kh(ctx, ctx->kernel_timing, GS_K_H2L, ss);
         if (fast) {
           DT_HIP(launch_h2l_fast(D, P, tensor, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, h2l_part,
-                                 h2l_part_p, st));
-          kh.stop(st, sg[2].n ? 2 : 0);
+                                 h2l_part_p, ss));
+          kh.stop(ss, sg[2].n ? 2 : 0);
         } else {
-          DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, st));
-          kh.stop(st, 1);
+          DT_HIP(launch_h2l(T, sg[2], wl.ent[2], qv, rv, Mom, d_sc, nQ, lco, pL, ss));
+          kh.stop(ss, 1);
         }
       }
-      KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, st);
+      KernelTimer kdh(ctx, ctx->kernel_timing, GS_K_DH, ss);
       int dh_launches = 0;
       for (size_t lv = 0; lv + 1 < dh_level_begin.size(); ++lv) {
         const int64_t gb = dh_level_begin[lv], ge = dh_level_begin[lv + 1];
@@ -992,16 +1013,16 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         if (fast) {
           DT_HIP(launch_dh_fast(D, P, tensor, wl.dh_slice + sb, (int)(se - sb), (int)sb, wl.grp[0], wl.dh_first,
                                 (int)gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm, Mom, d_sc,
-                                (int)Mq, gdh, dh_part, st));
+                                (int)Mq, gdh, dh_part, ss));
           dh_launches += se - sb > ge - gb ? 2 : 1;
         } else {
           DT_HIP(launch_dh_level(T, wl.grp[0] + gb, (int)(ge - gb), max_q, wl.ent[0], qv, rv, xq_perm,
-                                 Mom, d_sc, (int)Mq, gdh, st));
+                                 Mom, d_sc, (int)Mq, gdh, ss));
           dh_launches += 1;
         }
       }
-      kdh.stop(st, dh_launches);
-      kt.stop(st, (fast ? 3 : 2) + dh_launches);
+      kdh.stop(ss, dh_launches);
+      kt.stop(ss, (fast ? 3 : 2) + dh_launches);
     }
     if (any_base) {
       if (!rec_ready) {

@@ -46,6 +46,10 @@ struct gs_ctx_base {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // A side stream (default priority) for work that is independent of the
+  // base cases: forked from `stream` with fork_ev, joined with join_ev.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::string err;
   gs_stats stats;
   Workspace ws;
@@ -55,6 +59,7 @@ struct gs_ctx_base {
   std::vector<int16_t> trace_feas;    // [n] admitted orders (policy logging)
   HostTree host_tree[2];
   bool kernel_timing = false;
+  unsigned timing_mask = 0;  // kernel classes (bit GS_K_*) timed by KernelTimer
   PolicyState policy;
   std::map<std::string, std::pair<int, int>> tuned;  // autotuner: signature -> (method, leaf)
   std::vector<hipEvent_t> ev_pool;                    // reusable timing events

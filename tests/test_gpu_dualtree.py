@@ -287,3 +287,25 @@ def test_repeated_calls_alternating_inputs():
             assert np.array_equal(G, first[k]), call
         else:
             first[k] = G
+
+
+def test_kernel_timing_modes():
+    """kernel_timing=1 times every kernel class, 2 only the base-case tiles
+    (the exhaustive tiles on that path), 0 none; other values are rejected."""
+    import paper_1206_6857_amd as g
+    from paper_1206_6857_amd import _lib
+    r, w, _ = _inputs(3, 4000, None, 9)
+    c = ctx()
+    hs = [0.01, 0.1, 1.0]
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, kernel_timing=1)
+    st = c.stats()
+    assert st.k_ms[_lib.K_BASE] > 0 and st.k_ms[_lib.K_DECIDE] > 0 and st.k_ms[_lib.K_TREE] > 0
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, kernel_timing=2)
+    st = c.stats()
+    assert st.k_ms[_lib.K_BASE] > 0 and st.k_launches[_lib.K_BASE] == 1
+    assert st.k_ms[_lib.K_DECIDE] == 0 and st.k_ms[_lib.K_TREE] == 0 and st.k_ms[_lib.K_SERIES] == 0
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32)
+    assert c.stats().k_ms[_lib.K_BASE] == 0
+    with pytest.raises(g.GaussSumError) as e:
+        c.gauss_sum(r, r, w, hs, 0.01, kernel_timing=3)
+    assert e.value.status == _lib.GS_EINVAL
