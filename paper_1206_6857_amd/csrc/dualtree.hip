@@ -511,16 +511,25 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* Mom = nullptr;
   if (use_fmm) {
     Mom = BUF(double, "moments", (int64_t)nR * C);
-    KernelTimer km(ctx, ctx->kernel_timing, GS_K_MOMENTS, st);
+    // Only the expansions read the moments, and they run on the side stream
+    // (below), so the moments go there too, beside the traversal; each
+    // bandwidth chunk joins the side stream back before it returns.
+    hipStream_t sm = st;
+    if (!opt.log_pairs && ctx->side) {
+      DT_HIP(hipEventRecord(ctx->fork_ev, st));
+      DT_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+      sm = ctx->side;
+    }
+    KernelTimer km(ctx, ctx->kernel_timing, GS_K_MOMENTS, sm);
     if (series_fast_available(D, P, tensor))
-      DT_HIP(launch_p2m_fast(D, P, tensor, rv, nR, xr_perm, wr_perm, Mom, st));
+      DT_HIP(launch_p2m_fast(D, P, tensor, rv, nR, xr_perm, wr_perm, Mom, sm));
     else
-      DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, st));
+      DT_HIP(launch_p2m(T, rv, nR, xr_perm, wr_perm, Mom, sm));
     for (int lv = (int)rt.level_begin.size() - 2; lv >= 0; --lv)
       DT_HIP(series_fast_available(D, P, tensor)
-                 ? launch_h2h_level_fast(D, P, tensor, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st)
-                 : launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, st));
-    km.stop(st, (int)rt.level_begin.size());
+                 ? launch_h2h_level_fast(D, P, tensor, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, sm)
+                 : launch_h2h_level(T, rv, rt.level_begin[lv], rt.level_begin[lv + 1], Mom, sm));
+    km.stop(sm, (int)rt.level_begin.size());
   }
   double t2 = now_ms();
   S.t_moments_ms = t2 - t1;
