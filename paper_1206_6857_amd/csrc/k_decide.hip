@@ -359,7 +359,6 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   const long long c0_lane = lane >= 1 && lane <= P ? sat_mul(NQ, c.cterm[lane]) : kInfCost;
   const long long c2_lane = lane >= 1 && lane <= P ? c.ch2l[lane] : kInfCost;
   __shared__ double sh_pm[64][3 * P];      // PM_DH, PM_DL, PM_H2L of each pair
-  __shared__ long long sh_c1[64][P];       // c_DL(q) = N_R D^(q+1), q = 1..P
   for (int b0 = 0; b0 < len; b0 += 64) {
     const int n = len - b0 < 64 ? len - b0 : 64;
     double lterm = 0.0, fdval = 0.0, nd = 0.0, WR = 0.0, astar = INFINITY, thr = INFINITY;
@@ -443,7 +442,6 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
 #pragma unroll
         for (int p = 1; p <= P; ++p) {
           const int64_t c1p = sat_mul((int64_t)NR, c.cterm[p]);
-          sh_c1[lane][p - 1] = c1p;
           if (sat_mul(NQ, c.cterm[p]) <= cdir) mstar = pm0[p - 1] < mstar ? pm0[p - 1] : mstar;
           if (c1p <= cdir) mstar = pm1[p - 1] < mstar ? pm1[p - 1] : mstar;
           if (c.ch2l[p] <= cdir) mstar = pm2[p - 1] < mstar ? pm2[p - 1] : mstar;
@@ -562,9 +560,9 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
       }
       // (without the policy, thr is astar and a >= astar holds here)
       if (rule && (!GEN || all_orders || a >= rl(astar, j))) {
-        const long long c1v = lane < P ? sh_c1[j][lane] : kInfCost;
+        // c_DL(q1) = N_R c_term(q1) of pair j (its N_R read from lane j)
         const int64_t c0 = q0 ? rl(c0_lane, q0) : kInfCost;
-        const int64_t c1 = q1 ? rl(c1v, q1 - 1) : kInfCost;
+        const int64_t c1 = q1 ? sat_mul((int64_t)__builtin_amdgcn_readlane(NR, j), c.cterm[q1]) : kInfCost;
         const int64_t c2 = q2 ? rl(c2_lane, q2) : kInfCost;
         const int64_t cd3 = rl(c3, j);
         int64_t best = c0 < c1 ? c0 : c1;
