@@ -59,8 +59,9 @@ def test_fullsize_d2_all_queries():
 
 
 @pytest.mark.parametrize("opts", [dict(autotune=1), dict(leaf_size=64), dict(leaf_size=128),
-                                  dict(leaf_size=256), dict(autotune=1, method="dualtree", h_chunk=3)],
-                         ids=["autotune", "leaf64", "leaf128", "leaf256", "chunked"])
+                                  dict(leaf_size=256), dict(autotune=1, method="dualtree", h_chunk=3),
+                                  dict(leaf_size=256, method="dfto"), dict(leaf_size=256, method="dfdo")],
+                         ids=["autotune", "leaf64", "leaf128", "leaf256", "chunked", "dfto", "dfdo"])
 def test_fullsize_d3_bench_workload(opts):
     _check(1, n_sample=300, **opts)
 
