@@ -25,7 +25,7 @@ void* Workspace::get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hi
   Buf& b = bufs[name];
   if (bytes == 0) bytes = 16;
   if (b.cap < bytes) {
-    if (b.p) hipFree(b.p);
+    if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     size_t cap = std::max(bytes, b.cap + b.cap / 2);
     hipError_t e = hipMalloc(&b.p, cap);
@@ -46,7 +46,7 @@ void* Workspace::get_pinned(const std::string& name, size_t bytes, hipError_t* e
   Buf& b = pinned[name];
   if (bytes == 0) bytes = 16;
   if (b.cap < bytes) {
-    if (b.p) hipHostFree(b.p);
+    if (b.p) (void)hipHostFree(b.p);
     b.p = nullptr;
     size_t cap = std::max(bytes, b.cap + b.cap / 2);
     hipError_t e = hipHostMalloc(&b.p, cap, hipHostMallocDefault);
@@ -64,10 +64,10 @@ void* Workspace::get_pinned(const std::string& name, size_t bytes, hipError_t* e
 
 void Workspace::release_all() {
   for (auto& kv : bufs)
-    if (kv.second.p) hipFree(kv.second.p);
+    if (kv.second.p) (void)hipFree(kv.second.p);
   bufs.clear();
   for (auto& kv : pinned)
-    if (kv.second.p) hipHostFree(kv.second.p);
+    if (kv.second.p) (void)hipHostFree(kv.second.p);
   pinned.clear();
 }
 
@@ -228,10 +228,10 @@ gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream) {
       hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
-    if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
-    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
-    if (ctx->side) hipStreamDestroy(ctx->side);
-    if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return GS_EDEVICE;
   }
@@ -243,17 +243,17 @@ gs_status gs_create(gs_ctx** out, int32_t device, void* hip_stream) {
 
 gs_status gs_destroy(gs_ctx* ctx) {
   if (!ctx) return GS_OK;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   flush_kernel_timers(ctx);
-  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   ctx->ev_pool.clear();
-  hipStreamSynchronize(ctx->side);
-  hipStreamDestroy(ctx->side);
-  hipEventDestroy(ctx->fork_ev);
-  hipEventDestroy(ctx->join_ev);
+  (void)hipStreamSynchronize(ctx->side);
+  (void)hipStreamDestroy(ctx->side);
+  (void)hipEventDestroy(ctx->fork_ev);
+  (void)hipEventDestroy(ctx->join_ev);
   ctx->ws.release_all();
-  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return GS_OK;
 }

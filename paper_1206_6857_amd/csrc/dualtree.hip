@@ -78,7 +78,7 @@ T* grow(gs_ctx_base* ctx, const std::string& name, size_t used, size_t need, hip
     (void)hipMemcpyAsync(np, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, s);
   if (b.p) {
     (void)hipStreamSynchronize(s);
-    hipFree(b.p);
+    (void)hipFree(b.p);
   }
   b.p = np;
   b.cap = cap;
