@@ -251,6 +251,22 @@ def main():
                            "base_pair_evals_frac": int(ev_m[0]) / args.steps / pair_evals}
         result["variants"] = variants
 
+    if method_used == "dualtree" and not args.no_variants:
+        # Bandwidth selection (least-squares cross-validation) over the
+        # workload's bandwidths: one sweep over h and sqrt(2) h plus the
+        # score reduction, inputs resident on the device.
+        for _ in range(max(1, args.warmup)):
+            ctx.lscv(rd, hd, wl.eps, leaf_size=leaf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            scores, bounds = ctx.lscv(rd, hd, wl.eps, leaf_size=leaf)
+        torch.cuda.synchronize()
+        t_cv = (time.perf_counter() - t0) / args.steps
+        k = int(np.argmin(scores))
+        result["lscv"] = {"ms_per_call": t_cv * 1e3, "bandwidths": n_h, "h_min": float(wl.bandwidths[k]),
+                          "score_bound_max": float(np.max(bounds))}
+
     if not args.no_learned and method_used == "dualtree":
         # The learned pair policy, trained on another draw of the same
         # workload (logging and training are parameter selection, not timed).
