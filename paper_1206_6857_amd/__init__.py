@@ -87,7 +87,7 @@ class Context:
     def gauss_sum(self, queries, refs, weights, bandwidths, eps, out=None, **opts):
         """G[n_h][M] = sum_r w_r exp(-|q - r|^2 / 2h^2) to relative error eps.
         queries may be the same object as refs (monochromatic).  Options:
-        method ('dualtree', 'exhaustive', 'dfd', 'dfdo'), policy ('rule',
+        method ('dualtree', 'exhaustive', 'dfd', 'dfdo', 'dfto'), policy ('rule',
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
         keep_trace, log_pairs, log_explore, blocking, fmm_mask, kernel_timing,
         h_chunk, max_frontier, node_bounds ('box', 'sphere_rect')."""
