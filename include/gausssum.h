@@ -111,6 +111,12 @@ typedef struct gs_options {
                                the bounding boxes (section 5); GS_BOUNDS_SPHERE_RECT:
                                the tighter of those and the bounds from the nodes'
                                bounding balls about the box centres */
+  int32_t debug_fail_alloc; /* error-path testing: k > 0 makes the k-th device
+                               workspace request of the call (cached or not,
+                               counted from 1 across the whole call) fail as an
+                               out-of-memory would, so the call returns GS_ENOMEM
+                               from wherever that request sits; the context stays
+                               usable.  0 (default): off */
 } gs_options;
 
 enum { GS_BOUNDS_BOX = 0, GS_BOUNDS_SPHERE_RECT = 1 };
@@ -140,6 +146,8 @@ typedef struct gs_stats {
   int32_t tuned_leaf_size;  /* leaf size the call used */
   int32_t tuned_method;     /* method the call used (the autotuner may pick GS_EXHAUSTIVE) */
   int32_t autotune_trials;  /* timed trial runs this call made (0: cached or off) */
+  int64_t workspace_requests; /* device workspace requests the call made (cached or
+                               not; the range of gs_options.debug_fail_alloc) */
 } gs_stats;
 
 /* Kernel classes of gs_stats.k_ms. */

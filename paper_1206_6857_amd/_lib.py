@@ -44,7 +44,7 @@ class GsOptions(ctypes.Structure):
                 ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
                 ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
                 ("log_explore", ctypes.c_double), ("autotune", ctypes.c_int32),
-                ("node_bounds", ctypes.c_int32)]
+                ("node_bounds", ctypes.c_int32), ("debug_fail_alloc", ctypes.c_int32)]
 
 
 class GsCostModel(ctypes.Structure):
@@ -69,7 +69,8 @@ class GsStats(ctypes.Structure):
                 ("t_total_ms", ctypes.c_double), ("k_ms", ctypes.c_double * 12),
                 ("k_launches", ctypes.c_int64 * 12), ("base_dist_evals", ctypes.c_int64),
                 ("h_chunks", ctypes.c_int32), ("tuned_leaf_size", ctypes.c_int32),
-                ("tuned_method", ctypes.c_int32), ("autotune_trials", ctypes.c_int32)]
+                ("tuned_method", ctypes.c_int32), ("autotune_trials", ctypes.c_int32),
+                ("workspace_requests", ctypes.c_int64)]
 K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS, K_DH, K_DL, K_H2L = range(10)
 
 

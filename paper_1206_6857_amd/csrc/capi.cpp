@@ -22,6 +22,10 @@ using namespace gs;
 namespace gs {
 
 void* Workspace::get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hipError_t* err) {
+  if (ctx && ctx->inject_alloc_failure()) {
+    *err = hipErrorOutOfMemory;
+    return nullptr;
+  }
   Buf& b = bufs[name];
   if (bytes == 0) bytes = 16;
   if (b.cap < bytes) {
@@ -38,7 +42,6 @@ void* Workspace::get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hi
     }
     b.cap = cap;
   }
-  (void)ctx;
   return b.p;
 }
 
@@ -174,6 +177,35 @@ static T* wsget(gs_ctx* ctx, const char* name, size_t count, gs_status* st) {
     if (!_p) return _st;                            \
     _p;                                             \
   })
+
+// Arms gs_options.debug_fail_alloc for the outermost API call and disarms it
+// when that call returns; a nested call (gs_lscv's sum) shares the count.
+struct AllocFaultScope {
+  gs_ctx* c;
+  AllocFaultScope(gs_ctx* ctx, int32_t k) : c(ctx) {
+    if (c->alloc_scope++ == 0) {
+      c->fail_alloc_at = k;
+      c->alloc_requests = 0;
+    }
+  }
+  ~AllocFaultScope() {
+    if (--c->alloc_scope == 0) c->fail_alloc_at = 0;
+  }
+};
+
+// A call that fails after it enqueued work drains both streams before it
+// returns, so that none of its kernels still reads the caller's buffers or
+// the workspace when the caller frees the one or reuses the other.
+struct DrainOnFailure {
+  gs_ctx* c;
+  bool ok = false;
+  ~DrainOnFailure() {
+    if (ok) return;
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipGetLastError();
+  }
+};
 
 static double now_ms() {
   using namespace std::chrono;
@@ -524,6 +556,7 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   if (opt.node_bounds != GS_BOUNDS_BOX && opt.node_bounds != GS_BOUNDS_SPHERE_RECT)
     GS_FAIL(ctx, GS_EINVAL, "node_bounds must be GS_BOUNDS_BOX or GS_BOUNDS_SPHERE_RECT");
   if (opt.max_frontier < 0) GS_FAIL(ctx, GS_EINVAL, "max_frontier must be >= 0");
+  if (opt.debug_fail_alloc < 0) GS_FAIL(ctx, GS_EINVAL, "debug_fail_alloc must be >= 0");
   if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");
   if (opt.policy != GS_RULE && opt.policy != GS_LEARNED) GS_FAIL(ctx, GS_EINVAL, "unknown policy");
@@ -540,6 +573,8 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   GS_HIP(ctx, hipSetDevice(ctx->device));
   const double t_start = now_ms();
   hipStream_t st = ctx->stream;
+  AllocFaultScope fault_scope(ctx, opt.debug_fail_alloc);
+  DrainOnFailure drain{ctx};
 
   // Bandwidths on the host.
   std::vector<double> hs(n_h);
@@ -702,6 +737,8 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     flush_kernel_timers(ctx);
   }
   ctx->stats.t_total_ms = now_ms() - t_start;
+  ctx->stats.workspace_requests = ctx->alloc_requests;
+  drain.ok = true;
   return GS_OK;
 }
 
@@ -721,8 +758,11 @@ gs_status gs_lscv(gs_ctx* ctx, const double* points, int64_t N, int32_t D, const
   }
   if (opt.keep_trace || opt.log_pairs) GS_FAIL(ctx, GS_EINVAL, "keep_trace and log_pairs do not apply to gs_lscv");
   opt.monochromatic = 1;
+  if (opt.debug_fail_alloc < 0) GS_FAIL(ctx, GS_EINVAL, "debug_fail_alloc must be >= 0");
   GS_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
+  AllocFaultScope fault_scope(ctx, opt.debug_fail_alloc);
+  DrainOnFailure drain{ctx};
   std::vector<double> hs(n_h);
   if (is_device_pointer(bandwidths)) {
     GS_HIP(ctx, hipMemcpyAsync(hs.data(), bandwidths, n_h * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -754,6 +794,8 @@ gs_status gs_lscv(gs_ctx* ctx, const double* points, int64_t N, int32_t D, const
   GS_HIP(ctx, hipMemcpyAsync(scores, out, n_h * sizeof(double), hipMemcpyDefault, st));
   if (bounds) GS_HIP(ctx, hipMemcpyAsync(bounds, out + n_h, n_h * sizeof(double), hipMemcpyDefault, st));
   GS_HIP(ctx, hipStreamSynchronize(st));
+  ctx->stats.workspace_requests = ctx->alloc_requests;
+  drain.ok = true;
   return GS_OK;
 }
 

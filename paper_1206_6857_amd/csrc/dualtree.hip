@@ -63,6 +63,11 @@ T* buf(gs_ctx_base* ctx, const std::string& name, size_t count, gs_status* st) {
 template <class T>
 T* grow(gs_ctx_base* ctx, const std::string& name, size_t used, size_t need, hipStream_t s,
         gs_status* st) {
+  if (ctx->inject_alloc_failure()) {
+    ctx->err = "device allocation failed while growing '" + name + "'";
+    *st = GS_ENOMEM;
+    return nullptr;
+  }
   Buf& b = ctx->ws.bufs[name];
   const size_t bytes = std::max<size_t>(need, 1) * sizeof(T);
   if (b.cap >= bytes) return static_cast<T*>(b.p);

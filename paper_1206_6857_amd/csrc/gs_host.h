@@ -63,6 +63,13 @@ struct gs_ctx_base {
   PolicyState policy;
   std::map<std::string, std::pair<int, int>> tuned;  // autotuner: signature -> (method, leaf)
   std::vector<hipEvent_t> ev_pool;                    // reusable timing events
+  // Error-path testing (gs_options.debug_fail_alloc): the device workspace
+  // request that fails (0: none), the requests of the current call so far,
+  // and the nesting depth of the API calls that armed them.
+  int64_t fail_alloc_at = 0, alloc_requests = 0;
+  int alloc_scope = 0;
+  // Counts one device workspace request; true when it is the one to fail.
+  bool inject_alloc_failure() { return ++alloc_requests == fail_alloc_at; }
   // decision counters of the last dual-tree call, being copied to pinned
   // memory; read by finish_dualtree_stats once the stream has drained
   const unsigned long long* stats_pending = nullptr;
