@@ -10,7 +10,8 @@ Theorem 2 against the FP64 exhaustive sum):
 * a dimension of zero extent (points on a plane in three dimensions);
 * one query against many references;
 * bandwidths far below and far above the point spacing (every pair a base
-  case; every pair pruned by finite difference at the root).
+  case; every pair pruned by finite difference at the root);
+* the largest dimension the library accepts (D = 64).
 """
 import numpy as np
 import pytest
@@ -60,6 +61,9 @@ def _case(name):
         r, w, _ = mixture((7, 2), 2000, 2, 4, (0.02, 0.1))
         q = np.array([[0.45, 0.55]])
         return q, r, w, np.array([0.05, 0.3, 2.0]), 32, False
+    if name == "max_dimension":
+        r, w, q = mixture((9, 64), 600, 64, 3, (0.02, 0.1), m_queries=200)
+        return q, r, w, np.array([0.3, 1.0, 4.0]), 32, False
     if name == "extreme_bandwidths":
         r, w, _ = mixture((8, 2), 1500, 2, 4, (0.02, 0.1))
         return r, r, w, np.array([1e-6, 1e4]), 32, True
@@ -67,7 +71,7 @@ def _case(name):
 
 
 CASES = ["one_ref_one_query", "one_point_mono", "all_points_equal", "coarse_lattice", "single_leaf_tree",
-         "one_point_leaves", "flat_dimension", "one_query", "extreme_bandwidths"]
+         "one_point_leaves", "flat_dimension", "one_query", "extreme_bandwidths", "max_dimension"]
 
 
 @pytest.mark.parametrize("method", ["dito", "dfto"])

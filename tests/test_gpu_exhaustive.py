@@ -22,7 +22,7 @@ TOL_MEDIAN = 1e-6
 
 @pytest.mark.parametrize("D,M,N,nh", [(1, 300, 517, 3), (2, 1000, 1000, 1), (3, 777, 2049, 10),
                                       (5, 513, 700, 17), (8, 129, 300, 4), (16, 260, 1100, 16),
-                                      (7, 33, 65, 2), (3, 1, 1, 1)])
+                                      (7, 33, 65, 2), (3, 1, 1, 1), (64, 100, 300, 3)])
 def test_exhaustive_matches_oracle(D, M, N, nh):
     banner("exhaustive", D, M, N, nh)
     r, w, q = mixture((50, D), N, D, 3, (0.02, 0.2), weights=(0.5, 1.5), m_queries=M)
