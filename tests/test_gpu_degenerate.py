@@ -11,7 +11,8 @@ Theorem 2 against the FP64 exhaustive sum):
 * one query against many references;
 * bandwidths far below and far above the point spacing (every pair a base
   case; every pair pruned by finite difference at the root);
-* the largest dimension the library accepts (D = 64).
+* the largest dimension the library accepts (D = 64);
+* the most bandwidths one call accepts (4096).
 """
 import numpy as np
 import pytest
@@ -105,3 +106,27 @@ def test_degenerate_parity(name, method):
         np.testing.assert_allclose(G, np.full((len(hs), 1), 2.0), rtol=1e-6)
     if name == "all_points_equal":
         np.testing.assert_allclose(G, np.full((len(hs), 300), w.sum()), rtol=1e-6)
+
+
+def test_most_bandwidths_per_call():
+    """4096 bandwidths in one call (the most accepted).  Bandwidths never
+    interact in the traversal, so the decisions and values of each sampled
+    bandwidth equal the oracle's run on that bandwidth alone."""
+    banner("degenerate", "4096 bandwidths")
+    r, w, _ = mixture((10, 2), 500, 2, 3, (0.02, 0.1))
+    hs = np.logspace(-3, 1, 4096)
+    c = ctx()
+    G = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, keep_trace=1)
+    assert G.shape == (4096, 500)
+    tr = c.get_trace().astype(np.int64)
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    for k in (0, 1, 7, 8, 1000, 2047, 2048, 3001, 4094, 4095):
+        ref = DT.dualtree(r, r, w, hs[k:k + 1], 0.01, leaf_size=32, trace=True)
+        want = np.array(ref.trace, dtype=np.int64).reshape(-1, 6)
+        want[:, 0] = k
+        got = tr[tr[:, 0] == k]
+        assert got.shape == want.shape, (k, got.shape, want.shape)
+        assert np.array_equal(key(got), key(want)), k
+        exact = gauss_sum_exhaustive(r, r, w, hs[k:k + 1])[0]
+        assert (np.abs(G[k] - ref.G[0]) / exact).max() <= TOL_ROUND, k
+        assert (np.abs(G[k] - exact) / exact).max() <= 0.01, k
