@@ -18,7 +18,9 @@
  *     copied to the device inside the call; a host output is written back
  *     before the call returns.
  *   - A failed call leaves outputs unspecified and the context reusable; the
- *     reason is available from gs_last_error().
+ *     reason is available from gs_last_error().  A failed gauss_sum or
+ *     gs_lscv returns only after the work it had enqueued has finished, so
+ *     the caller may free its buffers at once.
  *   - A context is not thread safe: calls on one context must not overlap.
  */
 #ifndef GAUSSSUM_H
