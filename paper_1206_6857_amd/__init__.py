@@ -28,6 +28,22 @@ def gs_default_options():
     return opt
 
 
+def _numel(a):
+    n = 1
+    for k in a.shape:
+        n *= int(k)
+    return n
+
+
+def _rows(a, width, what):
+    """Check that a marshalled array is [n][width]; returns n.  The library
+    reads and writes exactly these sizes, so a mismatch would run past the
+    caller's buffer."""
+    if len(a.shape) != 2 or a.shape[1] != width:
+        raise ValueError("%s must be [n][%d], got shape %s" % (what, width, a.shape))
+    return a.shape[0]
+
+
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
@@ -105,6 +121,10 @@ class Context:
         M, D = q.shape
         N = r.shape[0]
         n_h = int(np.prod(hb.shape)) if hb.shape else 1
+        if r.shape[1] != D:
+            raise ValueError("queries and refs must have the same dimension (%d, %d)" % (D, r.shape[1]))
+        if _numel(w) != N:
+            raise ValueError("weights must hold one value per reference point (%d, got %d)" % (N, _numel(w)))
         if out is None:
             if q.is_cuda or r.is_cuda:
                 import torch
@@ -112,6 +132,8 @@ class Context:
             else:
                 out = np.empty((n_h, M), dtype=np.float64)
         o = _Arr(out, writable=True)
+        if tuple(o.shape) != (n_h, M):
+            raise ValueError("out must have shape (%d, %d), got %s" % (n_h, M, tuple(o.shape)))
         opt = gs_default_options()
         for k, v in opts.items():
             if k == "method":
@@ -162,6 +184,8 @@ class Context:
         of the Gaussian KDE of `points` for every bandwidth."""
         lib = _lib.load()
         x = _Arr(points)
+        if len(x.shape) != 2:
+            raise ValueError("points must be 2-D [n][D]")
         hsrc = bandwidths
         if not _is_torch(hsrc):
             hsrc = np.atleast_1d(np.asarray(hsrc, dtype=np.float64))
@@ -221,12 +245,14 @@ class Context:
                                             ctypes.byref(loss)))
         else:
             rec = np.ascontiguousarray(records, dtype=np.float32)
+            _rows(rec, _lib.POLICY_RECORD, "records")
             self._check(lib.gs_policy_train_records(self._h, rec.ctypes.data, rec.shape[0],
                                                     ctypes.byref(o), ctypes.byref(loss)))
         return loss.value
 
     def policy_gradient(self, records):
         rec = np.ascontiguousarray(records, dtype=np.float32)
+        _rows(rec, _lib.POLICY_RECORD, "records")
         g = np.zeros(_lib.POLICY_PARAMS, dtype=np.float32)
         loss = ctypes.c_float()
         self._check(_lib.load().gs_policy_gradient(self._h, rec.ctypes.data, rec.shape[0], g.ctypes.data,
@@ -235,6 +261,7 @@ class Context:
 
     def policy_predict(self, features):
         f = np.ascontiguousarray(features, dtype=np.float32)
+        _rows(f, _lib.POLICY_FEATURES, "features")
         out = np.zeros((f.shape[0], 4), dtype=np.float32)
         self._check(_lib.load().gs_policy_predict(self._h, f.ctypes.data, f.shape[0], out.ctypes.data))
         return out

@@ -33,6 +33,7 @@ EXPORTED = ["gs_default_options", "gs_create", "gs_destroy", "gauss_sum", "gs_ge
 POLICY_PARAMS = 5508          # W1[64][16] b1[64] W2[64][64] b2[64] W3[4][64] b3[4]
 POLICY_PARAM_FLOATS = 5542    # + mu_x[16] sd_x[16] mu_y sd_y
 POLICY_RECORD = 24            # features[16] targets[4] masks[4]
+POLICY_FEATURES = 16          # raw features per pair
 
 
 class GsOptions(ctypes.Structure):
