@@ -70,6 +70,40 @@ def test_every_injected_failure_leaves_the_context_usable(method, device):
     assert np.array_equal(G, G0)
 
 
+def test_injected_failures_with_the_learned_policy():
+    """The learned policy's inference buffers are workspace requests too.  A
+    context of its own holds a seeded network (any parameters: the policy only
+    chooses among actions the bound admits)."""
+    import paper_1206_6857_amd as g
+    from paper_1206_6857_amd import _lib
+    banner("fault injection", "learned policy")
+    rng = np.random.default_rng(31)
+    params = np.concatenate([rng.normal(0, 0.35, _lib.POLICY_PARAMS), rng.normal(0, 1, 16),
+                             rng.uniform(0.5, 2.0, 16), [3.0, 2.5]]).astype(np.float32)
+    r, w, q, hs = _inputs(False)
+    c = g.Context(0)
+    try:
+        c.policy_set_params(params)
+        opts = dict(policy="learned", leaf_size=32)
+        G0 = c.gauss_sum(q, r, w, hs, EPS, **opts)
+        assert c.stats().policy_calls > 0
+        n = c.stats().workspace_requests
+        failed = 0
+        for k in range(1, n + 1):
+            try:
+                G = c.gauss_sum(q, r, w, hs, EPS, debug_fail_alloc=k, **opts)
+            except g.GaussSumError as e:
+                assert e.status == _lib.GS_ENOMEM, (k, str(e))
+                failed += 1
+            else:
+                assert c.stats().h_chunks > 1, k
+                assert (np.abs(G - G0) / G0).max() <= 1e-12, k
+            assert np.array_equal(c.gauss_sum(q, r, w, hs, EPS, **opts), G0), k
+        assert failed >= 1
+    finally:
+        c.close()
+
+
 def test_injected_failures_in_lscv():
     import paper_1206_6857_amd as g
     from paper_1206_6857_amd import _lib
