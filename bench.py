@@ -104,7 +104,7 @@ def cpu_baseline(wl, n_queries, seed=0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=1, help="workload index (see datagen.workload)")
     ap.add_argument("--cpu-queries", type=int, default=3000)
