@@ -354,6 +354,16 @@ gs_status gs_multi_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alph
  * 1 <= p <= 10 and p^D <= 286. */
 gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alpha);
 
+/* The FP64 operations every pruning decision is made of (the token rule of
+ * section 5 and bestMethod of Figure 6 compare bounds formed from them),
+ * evaluated on the device exactly as the decide kernels do: out[0][i] = the
+ * library's own exp(x[i]) (Cody-Waite reduction, degree-13 Taylor polynomial;
+ * 0 below -700), out[1][i] = x[i] / y[i], out[2][i] = sqrt(y[i]).  Host
+ * pointers x[n], y[n], out[3][n]; 1 <= n <= 2^24, else GS_EINVAL.  Tests
+ * compare these bits with the host's correctly rounded division and square
+ * root and with an independent exp of the same definition. */
+gs_status gs_decision_arith(gs_ctx* ctx, const double* x, const double* y, int64_t n, double* out);
+
 #ifdef __cplusplus
 }
 #endif

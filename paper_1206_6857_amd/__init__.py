@@ -295,6 +295,18 @@ class Context:
     def policy_load(self, path):
         self._check(_lib.load().gs_policy_load(self._h, str(path).encode()))
 
+    def decision_arith(self, x, y):
+        """(own exp(x), x / y, sqrt(y)) as the decide kernels compute them
+        (gs_decision_arith), for equal-length float64 arrays x, y."""
+        x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        y = np.ascontiguousarray(y, dtype=np.float64).ravel()
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same length")
+        out = np.zeros((3, x.size), dtype=np.float64)
+        self._check(_lib.load().gs_decision_arith(self._h, x.ctypes.data, y.ctypes.data, x.size,
+                                                  out.ctypes.data))
+        return out[0], out[1], out[2]
+
     def get_trace(self):
         """Decision records (h, level, Q, R, code, p) of the last keep_trace call."""
         lib = _lib.load()

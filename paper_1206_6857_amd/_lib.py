@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_EDEVICE",
 # Every function the header declares; tests check that the library exports them.
 EXPORTED = ["gs_default_options", "gs_create", "gs_destroy", "gauss_sum", "gs_get_stats",
             "gs_get_pair_counts", "gs_last_error", "gs_get_tree", "gs_get_trace",
-            "gs_multi_indices", "gs_tensor_indices", "gs_default_train_opts", "gs_policy_set_cost_model",
+            "gs_multi_indices", "gs_tensor_indices", "gs_decision_arith", "gs_default_train_opts", "gs_policy_set_cost_model",
             "gs_policy_get_cost_model", "gs_policy_get_log", "gs_policy_write_log",
             "gs_policy_train", "gs_policy_train_records", "gs_policy_gradient",
             "gs_policy_predict", "gs_policy_get_params", "gs_policy_set_params",
@@ -120,6 +120,8 @@ def load():
     lib.gs_multi_indices.restype = i32
     lib.gs_tensor_indices.argtypes = [i32, i32, ctypes.POINTER(i64), P]
     lib.gs_tensor_indices.restype = i32
+    lib.gs_decision_arith.argtypes = [P, P, P, i64, P]
+    lib.gs_decision_arith.restype = i32
     lib.gs_lscv.argtypes = [P, P, i64, i32, P, i32, f64, P, P, ctypes.POINTER(GsOptions)]
     lib.gs_lscv.restype = i32
     pf = ctypes.POINTER(ctypes.c_float)

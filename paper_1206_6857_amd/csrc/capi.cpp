@@ -373,6 +373,24 @@ gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alp
   return GS_OK;
 }
 
+gs_status gs_decision_arith(gs_ctx* ctx, const double* x, const double* y, int64_t n, double* out) {
+  if (!ctx) return GS_EINVAL;
+  ctx->err.clear();
+  if (!x || !y || !out) GS_FAIL(ctx, GS_EINVAL, "null array pointer");
+  if (n < 1 || n > (int64_t)1 << 24) GS_FAIL(ctx, GS_EINVAL, "n must be in [1, 2^24]");
+  GS_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  double* dx = WS(double, "arith_x", n);
+  double* dy = WS(double, "arith_y", n);
+  double* dout = WS(double, "arith_out", 3 * n);
+  GS_HIP(ctx, hipMemcpyAsync(dx, x, n * sizeof(double), hipMemcpyHostToDevice, st));
+  GS_HIP(ctx, hipMemcpyAsync(dy, y, n * sizeof(double), hipMemcpyHostToDevice, st));
+  GS_HIP(ctx, launch_decision_arith(dx, dy, n, dout, st));
+  GS_HIP(ctx, hipMemcpyAsync(out, dout, 3 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  GS_HIP(ctx, hipStreamSynchronize(st));
+  return GS_OK;
+}
+
 void gs_default_train_opts(gs_train_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));

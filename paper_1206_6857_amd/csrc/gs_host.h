@@ -110,6 +110,8 @@ void flush_kernel_timers(gs_ctx_base* ctx);
 std::vector<std::vector<int>> multi_indices(int D, int p);
 // alpha with every alpha_d < p, by largest component (O(p^D) expansions)
 std::vector<std::vector<int>> tensor_indices(int D, int p);
+// own_exp(x), x / y and sqrt(y) elementwise into out[3][n] (device pointers; k_decide.hip).
+hipError_t launch_decision_arith(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 // order limit of the O(p^D) expansions for dimension D
 int plimit_tensor(int D);
 

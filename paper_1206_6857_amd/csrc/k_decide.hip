@@ -823,7 +823,27 @@ __global__ __launch_bounds__(64) void emit_kernel(int S, FrontierLevel cur, Fron
   }
 }
 
+// The FP64 operations the decisions are made of, one element per thread:
+// own_exp(x), x / y and sqrt(y), in the same compilation settings as the
+// decide kernels (no contraction), so that a test can compare their bits with
+// the host's correctly rounded results.
+__global__ __launch_bounds__(256) void decision_arith_kernel(const double* __restrict__ x,
+                                                             const double* __restrict__ y, int64_t n,
+                                                             double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = own_exp(x[i]);
+  out[n + i] = x[i] / y[i];
+  out[2 * n + i] = sqrt(y[i]);
+}
+
 }  // namespace
+
+hipError_t launch_decision_arith(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(decision_arith_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
