@@ -84,7 +84,8 @@ class CertificationError(AssertionError):
 
 def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
              method="dito", mono=None, trace=False, fmm_mask=7, replay=None,
-             record_feasible=False, node_bounds="box", pair_order="tree", traversal="level"):
+             record_feasible=False, node_bounds="box", pair_order="tree", traversal="level",
+             ledger=False):
     """G~ of shape (n_h, M) in query order, plus the trees and (optionally) the
     decision trace: a list of (h_index, level, Q, R, code, p) tuples.
 
@@ -110,6 +111,13 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     traversal: "level" (the frontier mode above, which the library follows)
     or "depth_first" (paper mode: the recursion of Figures 1 and 7 in its
     printed order, _depth_first_decisions; no replay, no feasibility log).
+    ledger: keep res.ledger, one row (h_index, Q, R, code, E, L, W_R, t) per
+    resolved pair: the error bound E its resolution spends (the finite
+    difference or series bound; 0 for a base case), the lower bound L on G
+    over Q that the decision used, W_R, and the token left at Q afterwards.
+    The token rule's soundness is checked from these rows alone: per query
+    point and bandwidth, the sum over the pairs covering it of
+    W E / (eps_alg L) - W_R is at most 0 (Theorem 2's budget).
     method: "dito" (O(D^p) expansions and tokens), "dfto" (O(p^D) expansions
     and tokens, with the bounds of bounds.e_*_tensor; box bounds only),
     "dfdo" (finite differences and tokens), "dfd" (finite differences, local
@@ -151,6 +159,8 @@ def dualtree(xq, xr, w, hs, eps, leaf_size=64, plimit=None, eps_round_share=0.1,
     res.traversal = traversal
     res.replay = replay
     res.feasible = {} if record_feasible else None
+    res.ledger = [] if ledger else None
+    res.eps_alg = eps_alg
     for k, h in enumerate(hs):
         res.G[k] = _one_bandwidth(k, float(h), qt, rt, xq, mono, P, eps_alg, method, res)
     return res
@@ -204,13 +214,14 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                 WR = float(rt.W[R])
                 dmin2, kmax = geo[j]
                 kmin = exp64(-dmin2 * inv_2h2)
-                nd = need(e_fd(WR, kmin, kmax), WR, L, Wtot, eps_alg)
-                code, p = None, 0
+                efd = e_fd(WR, kmin, kmax)
+                nd = need(efd, WR, L, Wtot, eps_alg)
+                code, p, spent = None, 0, 0.0
                 if nd <= (t if use_tokens else 0.0):
                     if use_tokens:
                         t = t - nd
                     Gest[Q] = Gest[Q] + 0.5 * (WR * (kmin + kmax))
-                    code = FD
+                    code, spent = FD, efd
                 elif use_fmm:
                     tt = t if use_tokens else 0.0
                     maxerr = ((eps_alg * (WR + tt)) * L) / Wtot
@@ -241,7 +252,7 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                     if name != "DIRECT":
                         if use_tokens:
                             t = t - need(E, WR, L, Wtot, eps_alg)
-                        code = CODE[name]
+                        code, spent = CODE[name], E
                     else:
                         p = 0
                 if code is None:
@@ -254,6 +265,8 @@ def _one_bandwidth(hk, h, qt, rt, xq, mono, P, eps_alg, method, res):
                 if code == SPLIT:
                     split.append(R)
                 else:
+                    if res.ledger is not None:
+                        res.ledger.append((hk, Q, R, code, spent, L, WR, t))
                     Lp = Lp + WR * kmax
                     if code != FD:
                         work.append((code, Q, R, p))
@@ -335,9 +348,17 @@ def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
     Gest and the trace like the frontier mode.
 
     Readings (Figure 7 leaves the bookkeeping open):
-      * each query node has its own token slot Q.W_T; a node's slot starts as
-        a copy of its parent's slot when the recursion first reaches it, and
-        only decisions at Q change it afterwards (no flow back to the parent);
+      * a token is a per-query-point budget (proof of Theorem 2), and Q's slot
+        Q.W_T must be what every point of Q can still spend.  Each query node
+        keeps the sum of the token changes of its own decisions (deposits
+        positive, spendings negative); a point's remaining budget is the sum
+        of these over the nodes on its root-to-leaf path.  Q's slot is the
+        smallest of these over Q's points: the sum over Q and its ancestors,
+        plus the least that the decisions below Q have added on any path
+        (a node's value is refreshed as the minimum over its children, so a
+        spending in a child is seen by every later decision at its
+        ancestors, and a spending at an ancestor by every later decision in
+        the child).  Nothing is spent twice;
       * G_Q^min is the sum of W_R K(dmax) over the reference nodes resolved at
         Q or an ancestor and over the pairs still pending (on the recursion
         stack) at Q or an ancestor, each with the query node it was formed
@@ -373,7 +394,23 @@ def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
         return sphere_rect_dist2(qt.lo[Q], qt.hi[Q], rt.lo[R], rt.hi[R], qt.ctr[Q], rt.ctr[R], qt.rad[Q],
                                  rt.rad[R])
 
-    T = {0: 0.0}
+    own = {}        # Q -> sum of the token changes of Q's own decisions
+    below = {}      # Q -> min over Q's children c of own[c] + below[c]
+
+    def token(Q):
+        v = below.get(Q, 0.0)
+        for A in ancestors(Q):
+            v = v + own.get(A, 0.0)
+        return v
+
+    def book(Q, delta):
+        own[Q] = own.get(Q, 0.0) + delta
+        A = Q
+        while A in parent:
+            A = parent[A]
+            l = int(qt.left[A])
+            below[A] = min(own.get(l, 0.0) + below.get(l, 0.0), own.get(l + 1, 0.0) + below.get(l + 1, 0.0))
+
     resolved = {}   # Q -> list of W_R K(dmax) of pairs resolved at Q, in order
     pending = {}    # Q -> {R: W_R K(dmax)} of pairs on the stack
     work = []
@@ -396,17 +433,17 @@ def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
         if mono and float(qt.wmin[Q]) > L:
             L = float(qt.wmin[Q])
         bound = pending[Q].pop(R)
-        t = T[Q]
+        t = token(Q)
         WR = float(rt.W[R])
         kmax = exp64(-dmax2 * inv_2h2)
         kmin = exp64(-dmin2 * inv_2h2)
-        nd = need(e_fd(WR, kmin, kmax), WR, L, Wtot, eps_alg)
-        code, p = None, 0
+        efd = e_fd(WR, kmin, kmax)
+        nd = need(efd, WR, L, Wtot, eps_alg)
+        code, p, spent, delta = None, 0, 0.0, 0.0
         if nd <= (t if use_tokens else 0.0):
-            if use_tokens:
-                t = t - nd
+            delta = -nd
             Gest[Q] = Gest[Q] + 0.5 * (WR * (kmin + kmax))
-            code = FD
+            code, spent = FD, efd
         elif use_fmm:
             tt = t if use_tokens else 0.0
             maxerr = ((eps_alg * (WR + tt)) * L) / Wtot
@@ -415,24 +452,26 @@ def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
             name, p, E = best_method(D, P, maxerr, WR, g, rQ, rR, int(qt.count[Q]), int(rt.count[R]),
                                      mask=res.fmm_mask, family=fam)
             if name != "DIRECT":
-                if use_tokens:
-                    t = t - need(E, WR, L, Wtot, eps_alg)
-                code = CODE[name]
+                delta = -need(E, WR, L, Wtot, eps_alg)
+                code, spent = CODE[name], E
             else:
                 p = 0
         qleaf, rleaf = qt.left[Q] < 0, rt.left[R] < 0
         if code is None:
             if qleaf and rleaf:
-                if use_tokens:
-                    t = t + WR
+                delta = WR
                 code = BASE
             else:
                 code = SPLIT
-        T[Q] = t
+        if use_tokens and code != SPLIT:
+            book(Q, delta)
+            t = token(Q)
         res.counts[hk, code] += 1
         if res.trace is not None:
             res.trace.append((hk, depth, Q, R, code, p))
         if code != SPLIT:
+            if res.ledger is not None:
+                res.ledger.append((hk, Q, R, code, spent, L, WR, t))
             resolved.setdefault(Q, []).append(bound)
             if code != FD:
                 work.append((code, Q, R, p))
@@ -444,9 +483,6 @@ def _depth_first_decisions(hk, h, qt, rt, mono, P, eps_alg, method, res, Gest):
         else:
             ql, rl = int(qt.left[Q]), int(rt.left[R])
             kids = [(ql, rl), (ql, rl + 1), (ql + 1, rl), (ql + 1, rl + 1)]
-        for Qc, _ in kids:
-            if Qc not in T:
-                T[Qc] = t
         for Qc, Rc in reversed(kids):
             push(Qc, Rc, depth + 1, stack)
     return work

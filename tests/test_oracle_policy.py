@@ -146,3 +146,66 @@ def test_records_shapes_and_masks():
     for n, k in enumerate(keys):
         assert (Mk[n, 3] == 1.0) == (codes[k] in (DT.BASE, DT.SPLIT))
         assert Mk[n, :3].sum() == len(a.feasible[k])
+
+
+def test_forward_on_a_hand_computed_network():
+    """A sparse network whose output is worked out by hand below.  A dropped
+    bias, a missing or misplaced ReLU, or a transposed weight matrix each
+    changes at least one of the four outputs.
+
+      x = (1, -2, 0.5, 0, ...)
+      layer 1: a1_0 = 2*1 + 1*(-2) + 0.5 = 0.5   -> h1_0 = 0.5
+               a1_1 = 1*(-2) - 1        = -3    -> h1_1 = 0     (ReLU)
+               a1_2 = 4*0.5             = 2     -> h1_2 = 2
+               a1_3 = -1 (bias only)            -> h1_3 = 0
+      layer 2: a2_0 = h1_0 - h1_2 + 3   = 1.5   -> h2_0 = 1.5
+               a2_1 = 5 h1_1 + 0.25     = 0.25  -> h2_1 = 0.25
+               a2_2 = -h1_2 + 1         = -1    -> h2_2 = 0     (ReLU)
+      output:  y_0 = 2 h2_0 + 0.1              = 3.1
+               y_1 = -h2_0 + 4 h2_1            = -0.5
+               y_2 = 7 h2_2 - 0.5              = -0.5
+               y_3 = h2_0 + h2_1 + h2_2 + 1    = 2.75
+    """
+    P = {name: np.zeros(shape) for name, shape in mlp.SHAPES}
+    P["W1"][0, 0], P["W1"][0, 1], P["b1"][0] = 2.0, 1.0, 0.5
+    P["W1"][1, 1], P["b1"][1] = 1.0, -1.0
+    P["W1"][2, 2] = 4.0
+    P["b1"][3] = -1.0
+    P["W2"][0, 0], P["W2"][0, 2], P["b2"][0] = 1.0, -1.0, 3.0
+    P["W2"][1, 1], P["b2"][1] = 5.0, 0.25
+    P["W2"][2, 2], P["b2"][2] = -1.0, 1.0
+    P["W3"][0, 0], P["b3"][0] = 2.0, 0.1
+    P["W3"][1, 0], P["W3"][1, 1] = -1.0, 4.0
+    P["W3"][2, 2], P["b3"][2] = 7.0, -0.5
+    P["W3"][3, :3], P["b3"][3] = 1.0, 1.0
+    x = np.zeros((1, 16))
+    x[0, :3] = (1.0, -2.0, 0.5)
+    y, _ = mlp.forward(mlp.pack(P), x)
+    assert np.allclose(y[0], [3.1, -0.5, -0.5, 2.75], rtol=0, atol=1e-15), y
+
+
+def test_pair_features_of_a_hand_built_pair():
+    """Two boxes in D = 2 whose distances are worked out by hand:
+    Q = [0,1] x [0,2] (8 points, a leaf, rinf 1), R = [3,4] x [0,1]
+    (32 points, internal, rinf 0.5), h = 0.5.  The closest points are 2 apart
+    along the first axis (dmin = 2); the farthest are 4 apart along the first
+    and 2 along the second (dmax = sqrt(20) = 2 sqrt(5))."""
+    from types import SimpleNamespace
+
+    from oracle.policy import pair_features
+    qt = SimpleNamespace(lo=[np.array([0.0, 0.0])], hi=[np.array([1.0, 2.0])], count=[8], rinf=[1.0],
+                         left=[-1])
+    rt = SimpleNamespace(lo=[np.array([3.0, 0.0])], hi=[np.array([4.0, 1.0])], count=[32], rinf=[0.5],
+                         left=[5])
+    f = pair_features(qt, rt, 0, 0, 0.5, 2)
+    want = np.zeros(16)
+    want[:10] = [3.0,                              # log2 8
+                 5.0,                              # log2 32
+                 math.log2(5.0),                   # log2(1 + 2/0.5)
+                 math.log2(1.0 + 4.0 * math.sqrt(5.0)),  # log2(1 + 2 sqrt5 / 0.5)
+                 -1.0,                             # log2 0.5
+                 math.log2(3.0),                   # log2(1 + 1/0.5)
+                 1.0,                              # log2(1 + 0.5/0.5)
+                 1.0, 0.0,                         # Q is a leaf, R is not
+                 2.0 / 16.0]
+    assert np.allclose(f, want, rtol=0, atol=1e-14), f - want
