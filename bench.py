@@ -281,7 +281,7 @@ def main():
         result["learned_policy"] = {
             "ms_per_step": t_lp * 1e3, "value": pair_evals / t_lp, "speedup_vs_rule": t_dt / t_lp,
             "train_records": int(rec.shape[0]), "train_loss": loss, "train_s": t_train,
-            "policy_calls": int(st_lp.policy_calls), "policy_fallbacks": int(st_lp.policy_fallbacks),
+            "policy_calls": int(st_lp.policy_calls), "policy_overrides": int(st_lp.policy_overrides),
             "trained_on": tr.name + " (another draw)"}
 
     if not args.no_exhaustive:

@@ -119,6 +119,11 @@ typedef struct gs_options {
                                out-of-memory would, so the call returns GS_ENOMEM
                                from wherever that request sits; the context stays
                                usable.  0 (default): off */
+  const char* log_path;     /* with log_pairs: also write the call's training records
+                               to this file (gs_policy_write_log's format; read by
+                               gs_policy_train) before returning; NULL (default): keep
+                               them in the context only (gs_policy_get_log).  The
+                               library does not keep the pointer. */
 } gs_options;
 
 enum { GS_BOUNDS_BOX = 0, GS_BOUNDS_SPHERE_RECT = 1 };
@@ -133,8 +138,10 @@ typedef struct gs_stats {
   int64_t base_pair_evals;  /* point-pair kernel evaluations in base cases */
   int64_t frontier_peak;    /* largest frontier (pairs over all h) */
   int64_t policy_calls;     /* pairs on which the learned policy was consulted */
-  int64_t policy_fallbacks; /* of those, pairs whose cheapest predicted action the
-                               bound did not admit (the cheapest admitted one taken) */
+  int64_t policy_overrides; /* of those, pairs whose cheapest predicted action of all
+                               four the bound did not admit, so the cheapest predicted
+                               admitted one was taken.  The rule never takes over: the
+                               policy only chooses among admitted actions. */
   double t_stage_ms, t_tree_ms, t_moments_ms, t_traverse_ms, t_work_ms, t_post_ms;
   double t_total_ms;        /* wall time of the last gauss_sum call */
   /* With kernel_timing (1: all classes, 2: GS_K_BASE and GS_K_EXHAUSTIVE only): device
@@ -150,6 +157,19 @@ typedef struct gs_stats {
   int32_t autotune_trials;  /* timed trial runs this call made (0: cached or off) */
   int64_t workspace_requests; /* device workspace requests the call made (cached or
                                not; the range of gs_options.debug_fail_alloc) */
+  int64_t p_hist[3][16];    /* dual-tree calls: node pairs resolved by DH, DL and H2L
+                               (first index) at each order p (second index, 1..plimit;
+                               Figure 6's chosen orders) over all bandwidths */
+  double tokens_deposited;  /* token rule (section 5), over all bandwidths and query
+                               nodes, in weight units: the sum of the token gains of
+                               the decisions (base cases add W_R, approximations whose
+                               need W E/(eps L) - W_R is negative add -need) ... */
+  double tokens_withdrawn;  /* ... and the sum of the positive needs the approximations
+                               spent.  Summed with atomics: the last bits can differ
+                               between identical calls. */
+  double pair_evals_per_s;  /* M N n_h / t_total_ms: the call's rate in point-pair
+                               evaluations per second equivalent (section 7's measure
+                               of a whole sweep, preprocessing included) */
 } gs_stats;
 
 /* Kernel classes of gs_stats.k_ms. */

@@ -105,8 +105,9 @@ class Context:
         queries may be the same object as refs (monochromatic).  Options:
         method ('dualtree', 'exhaustive', 'dfd', 'dfdo', 'dfto'), policy ('rule',
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
-        keep_trace, log_pairs, log_explore, blocking, fmm_mask, kernel_timing,
-        h_chunk, max_frontier, node_bounds ('box', 'sphere_rect')."""
+        keep_trace, log_pairs, log_path, log_explore, blocking, fmm_mask,
+        kernel_timing, h_chunk, max_frontier, node_bounds ('box', 'sphere_rect'),
+        autotune, debug_fail_alloc."""
         lib = _lib.load()
         same = queries is refs
         r = _Arr(refs)
@@ -142,6 +143,8 @@ class Context:
                 v = _lib.POLICIES[v] if isinstance(v, str) else int(v)
             elif k == "node_bounds":
                 v = _lib.NODE_BOUNDS[v] if isinstance(v, str) else int(v)
+            elif k == "log_path" and v is not None:
+                v = str(v).encode()
             if not hasattr(opt, k):
                 raise TypeError("unknown option %r" % k)
             setattr(opt, k, v)

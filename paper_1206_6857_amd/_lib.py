@@ -45,7 +45,8 @@ class GsOptions(ctypes.Structure):
                 ("kernel_timing", ctypes.c_int32), ("h_chunk", ctypes.c_int32),
                 ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
                 ("log_explore", ctypes.c_double), ("autotune", ctypes.c_int32),
-                ("node_bounds", ctypes.c_int32), ("debug_fail_alloc", ctypes.c_int32)]
+                ("node_bounds", ctypes.c_int32), ("debug_fail_alloc", ctypes.c_int32),
+                ("log_path", ctypes.c_char_p)]
 
 
 class GsCostModel(ctypes.Structure):
@@ -63,7 +64,7 @@ class GsStats(ctypes.Structure):
                 ("levels", ctypes.c_int32), ("plimit", ctypes.c_int32),
                 ("pairs", ctypes.c_int64 * 6), ("base_pair_evals", ctypes.c_int64),
                 ("frontier_peak", ctypes.c_int64), ("policy_calls", ctypes.c_int64),
-                ("policy_fallbacks", ctypes.c_int64),
+                ("policy_overrides", ctypes.c_int64),
                 ("t_stage_ms", ctypes.c_double), ("t_tree_ms", ctypes.c_double),
                 ("t_moments_ms", ctypes.c_double), ("t_traverse_ms", ctypes.c_double),
                 ("t_work_ms", ctypes.c_double), ("t_post_ms", ctypes.c_double),
@@ -71,7 +72,9 @@ class GsStats(ctypes.Structure):
                 ("k_launches", ctypes.c_int64 * 12), ("base_dist_evals", ctypes.c_int64),
                 ("h_chunks", ctypes.c_int32), ("tuned_leaf_size", ctypes.c_int32),
                 ("tuned_method", ctypes.c_int32), ("autotune_trials", ctypes.c_int32),
-                ("workspace_requests", ctypes.c_int64)]
+                ("workspace_requests", ctypes.c_int64), ("p_hist", (ctypes.c_int64 * 16) * 3),
+                ("tokens_deposited", ctypes.c_double), ("tokens_withdrawn", ctypes.c_double),
+                ("pair_evals_per_s", ctypes.c_double)]
 K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS, K_DH, K_DL, K_H2L = range(10)
 
 

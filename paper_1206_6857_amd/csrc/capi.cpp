@@ -755,7 +755,12 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
     flush_kernel_timers(ctx);
   }
   ctx->stats.t_total_ms = now_ms() - t_start;
+  ctx->stats.pair_evals_per_s = (double)M * (double)N * (double)n_h / (ctx->stats.t_total_ms * 1e-3);
   ctx->stats.workspace_requests = ctx->alloc_requests;
+  if (opt.log_pairs && opt.log_path) {
+    s = policy_write_log(ctx, opt.log_path);
+    if (s != GS_OK) return s;
+  }
   drain.ok = true;
   return GS_OK;
 }

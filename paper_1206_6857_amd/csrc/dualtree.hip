@@ -29,6 +29,13 @@
 
 namespace gs {
 
+// Event block of a dual-tree call (after the [n_h][6] decision counts): four
+// counters, the token deposits and withdrawals (doubles), the order
+// histogram [3][16] of the DH, DL and H2L pairs.
+constexpr int kEvTok = 4;
+constexpr int kEvHist = 6;
+constexpr int kEvN = kEvHist + 3 * 16;
+
 namespace {
 
 #define DT_FAIL(code, msg) \
@@ -284,6 +291,17 @@ HostSeries make_series_tables(int D, int P, bool tensor) {
   return T;
 }
 
+// Order histogram of a work list: entries are (R << 4) | p.
+__global__ void order_hist_kernel(const int32_t* __restrict__ ent, int64_t n, unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int part[16];
+  if (threadIdx.x < 16) part[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&part[ent[i] & 15], 1u);
+  __syncthreads();
+  if (threadIdx.x < 16 && part[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)part[threadIdx.x]);
+}
+
 // Root pairs (h, root, root) of the bandwidths [h0, h0 + nh).
 __global__ void init_level0_kernel(int h0, int nh, FrontierLevel f) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,7 +437,11 @@ void finish_dualtree_stats(gs_ctx_base* ctx) {
   S.base_pair_evals = (int64_t)hc[n_h * 6];
   S.base_dist_evals = (int64_t)hc[n_h * 6 + 1];
   S.policy_calls = (int64_t)hc[n_h * 6 + 2];
-  S.policy_fallbacks = (int64_t)hc[n_h * 6 + 3];
+  S.policy_overrides = (int64_t)hc[n_h * 6 + 3];
+  std::memcpy(&S.tokens_deposited, hc + n_h * 6 + kEvTok, sizeof(double));
+  std::memcpy(&S.tokens_withdrawn, hc + n_h * 6 + kEvTok + 1, sizeof(double));
+  for (int x = 0; x < 3; ++x)
+    for (int p = 0; p < 16; ++p) S.p_hist[x][p] = (int64_t)hc[n_h * 6 + kEvHist + 16 * x + p];
   ctx->stats_pending = nullptr;
 }
 
@@ -613,17 +635,20 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   double* lco = use_fmm ? BUF(double, "lco", (int64_t)n_h * nQ * C) : nullptr;
   double* gx = BUF(double, "gx", (int64_t)n_h * Mq);
   double* gdh = BUF(double, "gdh", (int64_t)n_h * Mq);
-  // [n_h][6] decisions per type, then four event counters of the call: base
-  // point-pair evaluations, base distance evaluations, policy consultations,
-  // policy fallbacks; then their copy taken at the start of each chunk.
-  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 8);
+  // [n_h][6] decisions per type, then the call's event block (kEvN slots):
+  // four counters (base point-pair evaluations, base distance evaluations,
+  // policy consultations, policy overrides), the token deposits and
+  // withdrawals (two doubles), the order histogram [3][16] of the DH, DL and
+  // H2L pairs; then the block's copy taken at the start of each chunk.
+  unsigned long long* hcount = BUF(unsigned long long, "hcount", (int64_t)n_h * 6 + 2 * kEvN);
   unsigned long long* chunk_ev = hcount + n_h * 6;
+  dc.tok = use_tokens ? reinterpret_cast<double*>(chunk_ev + kEvTok) : nullptr;
   DT_HIP(hipMemsetAsync(Gest, 0, sizeof(double) * n_h * nQ, st));
   DT_HIP(hipMemsetAsync(pL, 0, sizeof(int32_t) * n_h * nQ, st));
   if (lco) DT_HIP(hipMemsetAsync(lco, 0, sizeof(double) * n_h * nQ * C, st));
   DT_HIP(hipMemsetAsync(gx, 0, sizeof(double) * n_h * Mq, st));
   DT_HIP(hipMemsetAsync(gdh, 0, sizeof(double) * n_h * Mq, st));
-  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 8), st));
+  DT_HIP(hipMemsetAsync(hcount, 0, sizeof(unsigned long long) * (n_h * 6 + 2 * kEvN), st));
   float* rec = nullptr;  // base-case reference records, built on first use
   bool rec_ready = false;
   BaseRecordsArgs ra;
@@ -669,7 +694,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       // Undo the chunk's decisions: lower-bound sums, counters and trace.
       DT_HIP(hipMemsetAsync(Gest + (int64_t)hc0 * nQ, 0, sizeof(double) * nh * nQ, st));
       DT_HIP(hipMemsetAsync(hcount + hc0 * 6, 0, sizeof(unsigned long long) * nh * 6, st));
-      DT_HIP(hipMemcpyAsync(chunk_ev, chunk_ev + 4, 4 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+      DT_HIP(hipMemcpyAsync(chunk_ev, chunk_ev + kEvN, kEvN * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                            st));
       DT_HIP(hipStreamSynchronize(st));
       ctx->trace.resize(trace0);
       ctx->trace_feat.resize(trace0 / 6 * kPolicyIn);
@@ -685,7 +711,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   } while (0)
     const double ta = now_ms();
     // the event counters run over the whole call; a retried chunk restores them
-    DT_HIP(hipMemcpyAsync(chunk_ev + 4, chunk_ev, 4 * sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+    DT_HIP(hipMemcpyAsync(chunk_ev + kEvN, chunk_ev, kEvN * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                          st));
     FrontierLevel cur, nxt;
     int64_t nseg = nh, npair = nh;
     CHUNK_ALLOC(level_bufs(0, nseg, npair, cur));
@@ -831,6 +858,13 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       nfirst = tot.v[17];
       ++level;
     }
+    // orders of the chunk's DH, DL and H2L pairs (the work-list entries)
+    for (int x = 0; x < 3 && use_fmm; ++x)
+      if (used_ent[x] > 0) {
+        hipLaunchKernelGGL(order_hist_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(used_ent[x], 256), 1024)),
+                           dim3(256), 0, st, wl.ent[x], used_ent[x], chunk_ev + kEvHist + 16 * x);
+        DT_HIP(hipGetLastError());
+      }
     const double tb0 = now_ms();
     t_trav += tb0 - ta;
     max_level = std::max(max_level, level);
@@ -1098,9 +1132,9 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
   {
     hipError_t pe = hipSuccess;
     auto* hc = static_cast<unsigned long long*>(
-        ctx->ws.get_pinned("stats_counts", sizeof(unsigned long long) * (n_h * 6 + 4), &pe));
+        ctx->ws.get_pinned("stats_counts", sizeof(unsigned long long) * (n_h * 6 + kEvN), &pe));
     if (!hc) DT_FAIL(GS_ENOMEM, "pinned host allocation failed for the statistics");
-    DT_HIP(hipMemcpyAsync(hc, hcount, sizeof(unsigned long long) * (n_h * 6 + 4), hipMemcpyDeviceToHost, st));
+    DT_HIP(hipMemcpyAsync(hc, hcount, sizeof(unsigned long long) * (n_h * 6 + kEvN), hipMemcpyDeviceToHost, st));
     ctx->stats_pending = hc;
     ctx->stats_pending_nh = n_h;
   }

@@ -24,6 +24,9 @@ struct DecideConst {
   double explore = 0.0;  // logging: probability of taking the direct path
                          // instead of the rule's series choice
   double eps_alg = 0.0;
+  // [2]: token deposits and withdrawals of the call's decisions, summed in
+  // weight units (section 5: a negative need is a deposit); may be null
+  double* tok = nullptr;
   int tensor = 0;  // 1: O(p^D) expansions (tensor index sets) and their bounds
   double bconst[kMaxPlimit + 1];  // C(D+p-1, D-1) / sqrt(F(p)), Lemma 4
   double binomD[kMaxPlimit + 1];  // C(D+p-1, D), Lemma 6
@@ -43,7 +46,7 @@ struct SegCount {
   int64_t v[18];  // [0] next-level pairs, [1] next-level segments,
                   // [2..5] DH, DL, H2L, BASE entries, [6..9] group flags,
                   // [10] FD pairs, [11] SPLIT pairs, [12] base-case point
-                  // pairs, [13] policy consultations, [14] policy fallbacks,
+                  // pairs, [13] policy consultations, [14] policy overrides,
                   // [15] DH slices, [16] DL slices, [17] next-level
                   // segments of at least kLongSegment pairs
 };

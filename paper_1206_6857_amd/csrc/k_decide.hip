@@ -338,6 +338,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   if (c.mono && qt.wmin[Q] > L) L = qt.wmin[Q];
 
   double t = cur.T[s];
+  double tdep = 0.0, twd = 0.0;  // this segment's token deposits and withdrawals
   double Lp = cur.Lp[s];
   double gest = gest_in;
   bool any_fd = false;
@@ -500,7 +501,12 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         // else split
         const unsigned long long bit = 1ull << j;
         const bool base = !fd && (base_ok & bit);
-        if (c.use_tokens) t = fd ? t - pv.x : (base ? t + WRj : t);
+        if (c.use_tokens) {
+          t = fd ? t - pv.x : (base ? t + WRj : t);
+          const double dv = fd ? -pv.x : (base ? WRj : 0.0);  // the token change
+          tdep = tdep + (dv > 0.0 ? dv : 0.0);
+          twd = twd + (dv < 0.0 ? -dv : 0.0);
+        }
         m_fd |= fd ? bit : 0ull;
         m_base |= base ? bit : 0ull;
         gest = gest + (fd ? pv.w : 0.0);
@@ -527,7 +533,7 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         // The learned policy: the cheapest predicted of the admitted actions
         // (each series method whose bound admits an order, at its smallest
         // such order, and recursion, always admitted); ties go to the earlier
-        // of DH, DL, H2L, recurse.  A fallback is counted when the overall
+        // of DH, DL, H2L, recurse.  An override is counted when the overall
         // cheapest prediction was not admitted.
         rule = false;
         const int kj = rl(kstar, j);
@@ -609,9 +615,17 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
         if (GEN && c.log_feas && lane == j) my_feas = 0x8000 | q0 | (q1 << 4) | (q2 << 8);
       }
       if (cd >= 0) {
-        if (c.use_tokens) t = t - rl(needv, xs * P + p - 1);
+        if (c.use_tokens) {
+          const double v = rl(needv, xs * P + p - 1);
+          t = t - v;
+          tdep = tdep + (v < 0.0 ? -v : 0.0);
+          twd = twd + (v > 0.0 ? v : 0.0);
+        }
       } else if (base_ok & (1ull << j)) {
-        if (c.use_tokens) t = t + WRj;
+        if (c.use_tokens) {
+          t = t + WRj;
+          tdep = tdep + WRj;
+        }
         cd = BASE;
       } else {
         cd = SPLIT;
@@ -658,6 +672,10 @@ __global__ __launch_bounds__(64) void decide_kernel(int S, int n_first, Frontier
   }
   if (lane != 0) return;
   if (any_fd) *gest_at = gest;
+  if (c.tok) {
+    if (tdep != 0.0) atomicAdd(c.tok, tdep);
+    if (twd != 0.0) atomicAdd(c.tok + 1, twd);
+  }
   cur.T[s] = t;
   cur.Lp[s] = Lp;
   SegCount sc;

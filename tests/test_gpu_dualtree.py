@@ -64,6 +64,30 @@ def _inputs(D, N, M, seed):
     return r, w, (r if M is None else q)
 
 
+def _check_stats(st, ref, method, pair_evals):
+    """The call's statistics against the oracle's run: the histogram of the
+    chosen orders (Figure 6) bit-exact from the oracle's trace, and the token
+    deposits and withdrawals (section 5) from its ledger of resolved pairs,
+    within the rounding of a sum taken in another order."""
+    from oracle.bounds import need
+    hist = np.zeros((3, 16), dtype=np.int64)
+    for hk, lvl, Q, R, code, p in ref.trace:
+        if code in (DT.DH, DT.DL, DT.H2L):
+            hist[code - DT.DH, p] += 1
+    got = np.array([[st.p_hist[x][p] for p in range(16)] for x in range(3)])
+    assert np.array_equal(got, hist), (got, hist)
+    dep = wd = 0.0
+    if method != "dfd":
+        W = float(ref.rtree.W[0])
+        for hk, Q, R, code, E, L, WR, t in ref.ledger:
+            v = -WR if code == DT.BASE else need(E, WR, L, W, ref.eps_alg)
+            dep += max(-v, 0.0)
+            wd += max(v, 0.0)
+    assert abs(st.tokens_deposited - dep) <= 1e-10 * max(dep, 1e-300), (st.tokens_deposited, dep)
+    assert abs(st.tokens_withdrawn - wd) <= 1e-10 * max(wd, 1e-300), (st.tokens_withdrawn, wd)
+    assert st.pair_evals_per_s == pytest.approx(pair_evals / (st.t_total_ms * 1e-3), rel=1e-12)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_dualtree_parity(case):
     name, D, N, M, hs, leaf, method = case[:7]
@@ -76,7 +100,8 @@ def test_dualtree_parity(case):
     G = c.gauss_sum(q, r, w, hs, 0.01, method=method, leaf_size=leaf, keep_trace=1, plimit=plimit,
                     fmm_mask=mask)
     ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, method=method, trace=True,
-                      plimit=plimit or None, fmm_mask=mask)
+                      plimit=plimit or None, fmm_mask=mask, ledger=True)
+    _check_stats(c.stats(), ref, method, q.shape[0] * r.shape[0] * len(hs))
     if mask != 7:
         # the restricted method carries the series prunes of the run
         code = {1: 1, 2: 2, 4: 3}[mask]

@@ -163,6 +163,25 @@ def test_policy_log_records_match_oracle():
     assert np.abs((g[:, 16:20] - T) * Mk).max() <= 1e-5
 
 
+def test_log_path_writes_the_records(tmp_path):
+    """gauss_sum with log_pairs and log_path writes the call's records to the
+    file; gs_policy_train reads that file and fits the same network as
+    training on the records held in the context."""
+    banner("policy log_path")
+    r, w, _ = mixture((33, 2), 1200, 2, 4, (0.02, 0.1))
+    hs = np.array([0.02, 0.1, 0.4])
+    c = ctx()
+    path = tmp_path / "log.bin"
+    c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, log_pairs=1, log_path=str(path))
+    rec, _ = c.policy_log()
+    assert path.exists() and rec.shape[0] > 20
+    loss_file = c.policy_train(log_path=path, steps=50, batch=256, seed=3)
+    p_file = c.policy_params()
+    loss_mem = c.policy_train(rec, steps=50, batch=256, seed=3)
+    assert loss_file == loss_mem
+    assert np.array_equal(p_file, c.policy_params())
+
+
 def test_learned_policy_is_certified_and_keeps_theorem_2():
     banner("learned policy replay")
     c = ctx()
@@ -174,7 +193,7 @@ def test_learned_policy_is_certified_and_keeps_theorem_2():
     r2, w2, _ = mixture((42, 3), 3000, 3, 6, (0.02, 0.1))
     G = c.gauss_sum(r2, r2, w2, hs, 0.01, leaf_size=32, policy="learned", keep_trace=1)
     st = c.stats()
-    assert st.policy_calls > 0
+    assert st.policy_calls > 0 and 0 <= st.policy_overrides <= st.policy_calls
     tr = c.get_trace()
     ref = DT.dualtree(r2, r2, w2, hs, 0.01, leaf_size=32, trace=True, replay=_pair_trace_replay(tr))
     assert np.array_equal(_sorted(ref.trace), _sorted(tr))
