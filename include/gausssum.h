@@ -384,6 +384,40 @@ gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alp
  * root and with an independent exp of the same definition. */
 gs_status gs_decision_arith(gs_ctx* ctx, const double* x, const double* y, int64_t n, double* out);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * gs_exhaustive_noalloc computes what gauss_sum computes with method =
+ * GS_EXHAUSTIVE (the plain sum of section 1 over all M*N pairs, same kernels,
+ * same launch configuration, bit-identical results) but makes no device
+ * allocation: no hipMalloc, no hipFree, no allocating library call.  Its
+ * intermediates (a validation flag, the largest weight, float reference
+ * records, partial sums per reference split) live in one fixed device array
+ * of the library of GS_NOALLOC_SCRATCH_BYTES, which every device the library
+ * runs on holds until the process ends.
+ *   queries [M][D], refs [N][D], weights [N], G_out [n_h][M]: device pointers
+ *            on the context's device (queries may equal refs); the caller
+ *            allocates them
+ *   bandwidths [n_h]: host pointer
+ * The call runs on the context's stream and returns after the results are
+ * written (it reads back one validation flag before the sum).
+ * Scratch needed: 256 + 4 N ceil((2D+1)/4)*4 bytes of records (each rounded
+ * up to 256) + 8 S n_h M bytes of partial sums, where S, the reference
+ * splits, is at most 1 + 2048 / ceil(M/256); so S M <= 524288 + M.
+ * Errors: GS_EINVAL as for gauss_sum (sizes, NaN or infinite coordinates,
+ * weights <= 0, bandwidths <= 0) and when an array is not where stated;
+ * GS_EOVERFLOW when the call needs more scratch than the array holds (the
+ * message gives both sizes).  Every call on one device shares that device's
+ * array and leaves the last call's contents in it: calls that overlap on one
+ * device (two contexts, two threads, or two streams) race and must be
+ * serialised by the caller. */
+#define GS_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+gs_status gs_exhaustive_noalloc(gs_ctx* ctx, const double* queries, int64_t M, const double* refs,
+                                const double* weights, int64_t N, int32_t D,
+                                const double* bandwidths, int32_t n_h, double* G_out);
+
 #ifdef __cplusplus
 }
 #endif

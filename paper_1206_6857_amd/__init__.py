@@ -156,6 +156,33 @@ class Context:
         self._check(st)
         return out
 
+    def exhaustive_noalloc(self, queries, refs, weights, bandwidths, out):
+        """gs_exhaustive_noalloc: the exhaustive sum with no device allocation
+        by the library.  queries, refs, weights and out are float64 device
+        tensors (out [n_h][M]); bandwidths a host array."""
+        lib = _lib.load()
+        same = queries is refs
+        r = _Arr(refs)
+        q = r if same else _Arr(queries)
+        w = _Arr(weights)
+        hb = _Arr(np.atleast_1d(np.asarray(bandwidths, dtype=np.float64)))
+        o = _Arr(out, writable=True)
+        if len(r.shape) != 2 or len(q.shape) != 2:
+            raise ValueError("queries and refs must be 2-D [n][D]")
+        M, D = q.shape
+        N = r.shape[0]
+        n_h = hb.shape[0]
+        if r.shape[1] != D:
+            raise ValueError("queries and refs must have the same dimension (%d, %d)" % (D, r.shape[1]))
+        if _numel(w) != N:
+            raise ValueError("weights must hold one value per reference point (%d, got %d)" % (N, _numel(w)))
+        if tuple(o.shape) != (n_h, M):
+            raise ValueError("out must have shape (%d, %d), got %s" % (n_h, M, tuple(o.shape)))
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self._check(lib.gs_exhaustive_noalloc(self._h, q.ptr, M, r.ptr, w.ptr, N, D, hb.ptr, n_h, o.ptr))
+        return out
+
     def stats(self):
         s = GsStats()
         s.struct_size = ctypes.sizeof(GsStats)

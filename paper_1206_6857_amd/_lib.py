@@ -28,7 +28,8 @@ EXPORTED = ["gs_default_options", "gs_create", "gs_destroy", "gauss_sum", "gs_ge
             "gs_policy_get_cost_model", "gs_policy_get_log", "gs_policy_write_log",
             "gs_policy_train", "gs_policy_train_records", "gs_policy_gradient",
             "gs_policy_predict", "gs_policy_get_params", "gs_policy_set_params",
-            "gs_policy_save", "gs_policy_load", "gs_lscv"]
+            "gs_policy_save", "gs_policy_load", "gs_lscv", "gs_exhaustive_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 POLICY_PARAMS = 5508          # W1[64][16] b1[64] W2[64][64] b2[64] W3[4][64] b3[4]
 POLICY_PARAM_FLOATS = 5542    # + mu_x[16] sd_x[16] mu_y sd_y
@@ -127,6 +128,8 @@ def load():
     lib.gs_decision_arith.restype = i32
     lib.gs_lscv.argtypes = [P, P, i64, i32, P, i32, f64, P, P, ctypes.POINTER(GsOptions)]
     lib.gs_lscv.restype = i32
+    lib.gs_exhaustive_noalloc.argtypes = [P, P, i64, P, P, i64, i32, P, i32, P]
+    lib.gs_exhaustive_noalloc.restype = i32
     pf = ctypes.POINTER(ctypes.c_float)
     lib.gs_default_train_opts.argtypes = [ctypes.POINTER(GsTrainOpts)]
     lib.gs_default_train_opts.restype = None

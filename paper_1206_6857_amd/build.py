@@ -36,6 +36,7 @@ SOURCES = [
     ("k_policy.hip", []),
     ("k_lscv.hip", []),
     ("policy.cpp", []),
+    ("noalloc.hip", []),
     ("dualtree.hip", NO_CONTRACT),
     ("capi.cpp", NO_CONTRACT),
 ]

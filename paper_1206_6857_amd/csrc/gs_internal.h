@@ -28,6 +28,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 hipError_t launch_stage_points(const double* x_rowmajor, int64_t n, int D, double* x_soa,
                                double* x_aos, int* bad_flag, hipStream_t s);
 hipError_t launch_check_positive(const double* v, int64_t n, int* bad_flag, hipStream_t s);
+// Raises bit 0 of *bad_flag if any of v[n] is NaN or infinite.
+hipError_t launch_check_finite(const double* v, int64_t n, int* bad_flag, hipStream_t s);
 // dst[i][d] = src[perm[i]][d];  dst[i] = src[perm[i]];  *out_bits = bits of max(w) (w > 0).
 hipError_t launch_gather_rows(const double* src, const int32_t* perm, int64_t n, int D, double* dst,
                               hipStream_t s);
@@ -43,8 +45,10 @@ int exhaustive_record_stride(int D);
 // wmax_bits receives the largest weight (bit pattern of a positive double).
 hipError_t launch_exhaustive_records(const double* x_aos, const double* w, int64_t n, int D,
                                      float* rec, unsigned long long* wmax_bits, hipStream_t s);
-// partial[n_split][n_h][M]; G_out[n_h][M].
+// partial[n_split][n_h][M]; G_out[n_h][M].  The first is an upper bound for
+// any D, the second the exact count launch_exhaustive uses for this D.
 size_t exhaustive_partial_elems(int64_t M, int64_t N, int n_h);
+size_t exhaustive_partial_elems_exact(int64_t M, int64_t N, int D, int n_h);
 hipError_t launch_exhaustive(const double* xq_aos, int64_t M, const float* rec, int64_t N, int D,
                              const double* bandwidths_host, int n_h,
                              const unsigned long long* wmax_bits, double* partial, double* G_out,

@@ -223,9 +223,15 @@ hipError_t launch_exhaustive_records(const double* x_aos, const double* w, int64
 }
 
 size_t exhaustive_partial_elems(int64_t M, int64_t N, int n_h) {
-  int rs = 0;  // chunk depends on D; use the smallest chunk for a safe upper bound
-  (void)rs;
+  // the chunk depends on D; the smallest chunk gives a safe upper bound
   return (size_t)splits_for(M, N, 16) * (size_t)n_h * (size_t)M;
+}
+
+size_t exhaustive_partial_elems_exact(int64_t M, int64_t N, int D, int n_h) {
+  const int chunk = chunk_for(exhaustive_record_stride(D));
+  const int n_split = splits_for(M, N, chunk);
+  const int64_t rps = ceil_div(ceil_div(N, n_split), chunk) * chunk;
+  return (size_t)ceil_div(N, rps) * (size_t)n_h * (size_t)M;
 }
 
 hipError_t launch_exhaustive(const double* xq, int64_t M, const float* rec, int64_t N, int D,

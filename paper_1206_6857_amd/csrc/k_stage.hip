@@ -32,6 +32,13 @@ __global__ void check_positive_kernel(const double* __restrict__ v, int64_t n,
   if (!(a > 0.0) || !isfinite(a)) atomicOr(bad_flag, 2);
 }
 
+__global__ void check_finite_kernel(const double* __restrict__ v, int64_t n,
+                                    int* __restrict__ bad_flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!isfinite(v[i])) atomicOr(bad_flag, 1);
+}
+
 hipError_t launch_stage_points(const double* x, int64_t n, int D, double* x_soa, double* x_aos,
                                int* bad_flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -44,6 +51,13 @@ hipError_t launch_check_positive(const double* v, int64_t n, int* bad_flag, hipS
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(check_positive_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, v,
                      n, bad_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* v, int64_t n, int* bad_flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, v, n,
+                     bad_flag);
   return hipGetLastError();
 }
 
@@ -67,6 +81,8 @@ __global__ void gather_kernel(const double* __restrict__ src, const int32_t* __r
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[perm[i]];
 }
+
+__global__ void clear_bits_kernel(unsigned long long* __restrict__ out_bits) { *out_bits = 0ull; }
 
 // Largest of positive doubles (their bit patterns order the same way): each
 // thread a strided share, a block maximum, then one atomic per block.
@@ -110,8 +126,7 @@ hipError_t launch_gather(const double* src, const int32_t* perm, int64_t n, doub
 
 hipError_t launch_max_positive(const double* w, int64_t n, unsigned long long* out_bits,
                                hipStream_t s) {
-  hipError_t e = hipMemsetAsync(out_bits, 0, sizeof(unsigned long long), s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(clear_bits_kernel, dim3(1), dim3(1), 0, s, out_bits);
   const int64_t blocks = std::min<int64_t>(ceil_div(n, 1024), 256);
   hipLaunchKernelGGL(max_bits_kernel, dim3((unsigned)blocks), dim3(1024), 0, s, w, n, out_bits);
   return hipGetLastError();
