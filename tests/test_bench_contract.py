@@ -20,14 +20,18 @@ def test_several_gpus_are_refused():
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
 
 
-@pytest.mark.parametrize("D", [1, 3, 16])
-def test_issue_slot_models(D):
-    flops, slots = bench.base_tile_model(D)
-    assert flops == 3 * D + 5 and slots == 2 * D + 2 + bench.EXP_SLOTS
-    f2, s2 = bench.fused_base_model(D, 10.0, 25.0)
-    assert f2 == 10.0 * 3 * D + 25.0 * 5
-    assert s2 == 10.0 * 2 * D + 25.0 * (2 + bench.EXP_SLOTS)
-    assert bench.alu_peak_pairs_per_s(D) == bench.LANE_SLOTS_PER_S / slots
+def test_work_models_against_hand_counts():
+    """The roofline's work model, checked against counts made by hand: a D=3
+    launch with 14.65e9 kernel evaluations and 5.60e9 squared distances is
+    3*3*5.60e9 + 4*14.65e9 = 1.090e11 flops; its non-packed issue slots are
+    6*5.60e9 + 4*14.65e9 = 9.22e10."""
+    assert abs(bench.method_flops(3, 5.60e9, 14.65e9) - 1.090e11) < 1e6
+    assert abs(bench.issue_slots(3, 5.60e9, 14.65e9) - 9.22e10) < 1e6
+    # the split-float exhaustive tiles: 4 slots per dimension of a distance
+    assert bench.issue_slots(16, 1.0, 0.0, 4.0) == 64.0
+    # the published FP32 peak and the non-packed issue rate: 256 CU x 64 lanes x 2.4 GHz
+    assert bench.LANE_SLOTS_PER_S == 256 * 64 * 2.4e9
+    assert abs(2 * 2 * bench.LANE_SLOTS_PER_S / 1e12 - bench.FP32_PEAK_TFLOPS) < 0.1
 
 
 def test_traffic_profile_needs_matching_source(tmp_path):
@@ -36,8 +40,11 @@ def test_traffic_profile_needs_matching_source(tmp_path):
     src.write_bytes(b"kernel source")
     h = hashlib.sha256(b"kernel source").hexdigest()[:16]
     prof = tmp_path / "p.txt"
-    prof.write_text("k_base.hip sha256 prefix: %s\ntraffic_bytes_per_launch base_fused_kernel<3> = 1234\n" % h)
-    assert bench.measured_traffic(str(src), str(prof)) == 1234.0
+    prof.write_text("k_base.hip sha256 prefix: %s\ntraffic_bytes_per_launch base_fused_kernel<3> = 1234\n"
+                    "traffic_bytes_per_launch base_fused_kernel<5> = 99\n" % h)
+    assert bench.measured_traffic(str(src), str(prof), "base_fused_kernel<3>") == 1234.0
+    assert bench.measured_traffic(str(src), str(prof), "base_fused_kernel<5>") == 99.0
+    assert bench.measured_traffic(str(src), str(prof), "base_fused_kernel<8>") is None
     src.write_bytes(b"changed kernel source")
-    assert bench.measured_traffic(str(src), str(prof)) is None
-    assert bench.measured_traffic(str(src), str(tmp_path / "missing.txt")) is None
+    assert bench.measured_traffic(str(src), str(prof), "base_fused_kernel<3>") is None
+    assert bench.measured_traffic(str(src), str(tmp_path / "missing.txt"), "base_fused_kernel<3>") is None
