@@ -29,7 +29,14 @@
 // the distance from x_q to R's bounding box (a lower bound of |x_q - x_r|, so
 // each scaled term is <= 1 and far pairs stay out of the float underflow
 // range); the leaf-pair sum is unscaled in double precision.  Weights are
-// stored divided by the largest weight.
+// stored divided by the largest weight.  Where the box distance is a poor
+// bound (a query inside a large, sparsely filled box, e.g. in 8 dimensions),
+// every scaled term can still underflow: a leaf pair whose scaled sum ends
+// below 2^-60 for any lane and bandwidth is swept again for the whole wave
+// with each lane's shift taken from its smallest squared distance to the
+// leaf's points (one distance-only sweep), so that its largest term is 1.
+// Padding records sit far away (coordinates 1e18, weight 0): their terms are
+// exactly 0 and they never give the smallest distance.
 #include <cstring>  // rocprim uses memset without including it
 #include <rocprim/rocprim.hpp>
 
@@ -49,6 +56,15 @@ constexpr int kBaseWaves = 4;                 // waves per workgroup of base_fus
 constexpr int kReduceThreads = 256;           // base_reduce_kernel
 constexpr uint64_t kAgeStep = 30000;          // 300 us of the 100 MHz real-time clock
 constexpr int kEntryCost = 256;               // issue slots of an entry's set-up (box distance, mask)
+
+constexpr float kFarPad = 1e18f;  // coordinate of the padding records
+
+// Every record of the array set to a padding record: far coordinates, weight 0.
+__global__ void pad_records_kernel(float* __restrict__ rec, int64_t n_floats, int D, int rs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_floats) return;
+  rec[i] = (int)(i % rs) < D ? kFarPad : 0.0f;
+}
 
 __global__ void pad_counts_kernel(const int32_t* __restrict__ left, const int32_t* __restrict__ count,
                                   int n_nodes, int32_t* __restrict__ padded) {
@@ -224,6 +240,31 @@ __device__ __forceinline__ void sweep(const float* __restrict__ p, int nb, const
   }
 }
 
+// Smallest |u_q - u_r|^2 over the records of a leaf (padding records are far
+// away and never the smallest).
+template <int D, int RS, int BR>
+__device__ __forceinline__ float sweep_min(const float* __restrict__ p, int nb, const float* uq) {
+  constexpr int NF = RS * BR;
+  constexpr int NV = (NF + 15) / 16;
+  float m2 = INFINITY;
+  for (int b = 0; b < nb; ++b, p += NF) {
+    f16v v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = *reinterpret_cast<const f16v*>(p + 16 * i);
+#pragma unroll
+    for (int j = 0; j < BR; ++j) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const float dd = uq[d] - v[(j * RS + d) / 16][(j * RS + d) % 16];
+        d2 = fmaf(dd, dd, d2);
+      }
+      m2 = fminf(m2, d2);
+    }
+  }
+  return m2;
+}
+
 // Any D: one record at a time.
 template <int NA>
 __device__ __forceinline__ void sweep_any(const float* __restrict__ p, int n, int D, int rs,
@@ -239,6 +280,32 @@ __device__ __forceinline__ void sweep_any(const float* __restrict__ p, int n, in
 #pragma unroll
     for (int a = 0; a < NA; ++a)
       part[a] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[a], shiftc[a])), part[a]);
+  }
+}
+
+__device__ __forceinline__ float sweep_min_any(const float* __restrict__ p, int n, int D, int rs,
+                                               const float* uq) {
+  float m2 = INFINITY;
+  for (int r = 0; r < n; ++r, p += rs) {
+    float d2 = 0.0f;
+    for (int d = 0; d < D; ++d) {
+      const float dd = uq[d] - p[d];
+      d2 = fmaf(dd, dd, d2);
+    }
+    m2 = fminf(m2, d2);
+  }
+  return m2;
+}
+
+template <int DT>
+__device__ __forceinline__ float sweep_leaf_min(const float* __restrict__ rec, int rs, int D, int rn_padded,
+                                                const float* uq) {
+  if constexpr (DT > 0) {
+    constexpr int RS = (DT + 4) / 4 * 4;
+    constexpr int BR = RS == 4 ? 4 : RS == 8 ? 2 : 1;
+    return sweep_min<DT, RS, BR>(rec, rn_padded / BR, uq);
+  } else {
+    return sweep_min_any(rec, rn_padded, D, rs, uq);
   }
 }
 
@@ -357,15 +424,32 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
       }
       const float* rp = rec + (int64_t)rec_off[R] * rs;
       const int rnp = (rt.count[R] + kPad - 1) / kPad * kPad;
-      switch (na) {
-        case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-        default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+      for (int pass = 0; pass < 2; ++pass) {
+        switch (na) {
+          case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+          default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+        }
+        if (pass == 1) break;
+        // Rescue (file comment): a sum below 2^-60 on any lane of the wave
+        // sends the whole wave through the leaf again with shifts from the
+        // lanes' smallest distances.
+        bool low = false;
+#pragma unroll
+        for (int j = 0; j < kHB; ++j)
+          if (j < na && part[j] < 0x1p-60f) low = true;
+        if (!__any(low)) break;
+        const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
+#pragma unroll
+        for (int j = 0; j < kHB; ++j) {
+          shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
+          part[j] = 0.0f;
+        }
       }
       {
         unsigned mm = m;
@@ -462,7 +546,10 @@ size_t base_records_temp_bytes(int n_nodes) {
 }
 
 hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(a.rec, 0, sizeof(float) * a.rec_capacity * base_record_stride(a.D), s);
+  const int64_t n_floats = a.rec_capacity * base_record_stride(a.D);
+  hipLaunchKernelGGL(pad_records_kernel, dim3((unsigned)ceil_div(n_floats, 256)), dim3(256), 0, s, a.rec, n_floats,
+                     a.D, base_record_stride(a.D));
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pad_counts_kernel, dim3((unsigned)ceil_div(a.n_nodes, 256)), dim3(256), 0, s, a.left,
                      a.count, a.n_nodes, a.padded);

@@ -12,6 +12,8 @@ Theorem 2 against the FP64 exhaustive sum):
 * bandwidths far below and far above the point spacing (every pair a base
   case; every pair pruned by finite difference at the root);
 * the largest dimension the library accepts (D = 64);
+* a query inside a sparsely filled leaf box whose every term lies below the
+  float range (the base tiles' underflow rescue);
 * the most bandwidths one call accepts (4096).
 """
 import numpy as np
@@ -68,11 +70,23 @@ def _case(name):
     if name == "extreme_bandwidths":
         r, w, _ = mixture((8, 2), 1500, 2, 4, (0.02, 0.1))
         return r, r, w, np.array([1e-6, 1e4]), 32, True
+    if name == "sparse_box_underflow":
+        # two tight clusters at opposite corners of [0,1]^8, one leaf; a query at
+        # the centre lies inside the leaf's box (box distance 0) but at squared
+        # distance 2 from every point: at h = 0.1 and 0.07 every term is e^-100
+        # and e^-204, below the float range unless the shift comes from the
+        # points themselves
+        rng = _rng(10)
+        r = np.concatenate([rng.normal(0.0, 0.01, (100, 8)), rng.normal(1.0, 0.01, (100, 8))])
+        q = np.concatenate([np.full((1, 8), 0.5), rng.normal(0.0, 0.01, (2, 8)), rng.normal(0.6, 0.05, (5, 8))])
+        w = rng.uniform(0.5, 1.5, 200)
+        return q, r, w, np.array([0.07, 0.1, 0.3]), 256, False
     raise KeyError(name)
 
 
 CASES = ["one_ref_one_query", "one_point_mono", "all_points_equal", "coarse_lattice", "single_leaf_tree",
-         "one_point_leaves", "flat_dimension", "one_query", "extreme_bandwidths", "max_dimension"]
+         "one_point_leaves", "flat_dimension", "one_query", "extreme_bandwidths", "max_dimension",
+         "sparse_box_underflow"]
 
 
 @pytest.mark.parametrize("method", ["dito", "dfto"])

@@ -56,6 +56,13 @@ CASES = [
     ("d6_dfto_bi", 6, 900, 300, [0.1, 0.5, 3.0], 32, "dfto"),
     # an order limit without compiled tensor kernels: the generic kernels
     ("d3_dfto_plimit4_generic", 3, 1500, None, [1e-2, 0.05, 0.2, 1.0], 32, "dfto", 4),
+    # the leaf sizes the autotuner picks at the benchmark's sizes, on inputs large
+    # enough for several query batches per work unit (leaf 256: four batches of 64)
+    # and runs cut into several slices whose partial sums are added afterwards
+    ("d3_leaf256_mid", 3, 20000, None, list(np.logspace(-3, 0, 10)), 256, "dito"),
+    ("d3_leaf128_mid", 3, 12000, None, list(np.logspace(-3, 0, 10)), 128, "dito"),
+    ("d5_leaf128_mid", 5, 8000, None, list(np.logspace(-3, 0, 8)), 128, "dito"),
+    ("d8_leaf256_mid_bi", 8, 9000, 3000, list(np.logspace(-2, 0.3, 6)), 256, "dito"),
 ]
 
 
