@@ -133,7 +133,7 @@ def timed(ctx, sets, steps, warmup, opts_of):
             log("warm-up %d %s %s" % (i, s.wl.name, opts_of(s)))
     torch.cuda.synchronize()
     per = [dict(t=0.0, k_ms=np.zeros(12), k_launches=np.zeros(12, dtype=np.int64), base_evals=0,
-                dist_evals=0) for _ in sets]
+                dist_evals=0, mfma_evals=0) for _ in sets]
     t0 = time.perf_counter()
     for _ in range(steps):
         for s, acc in zip(sets, per):
@@ -147,6 +147,7 @@ def timed(ctx, sets, steps, warmup, opts_of):
             acc["k_launches"] += np.array(st.k_launches[:])
             acc["base_evals"] += st.base_pair_evals
             acc["dist_evals"] += st.base_dist_evals
+            acc["mfma_evals"] += st.base_mfma_pair_evals
             acc["leaf"], acc["method"] = st.tuned_leaf_size, st.tuned_method
         log("step %s: %s" % (opts_of(sets[0]), ", ".join("%s %.1f ms" % (s.wl.name, a["t"] * 1e3)
                                                             for s, a in zip(sets, per))))
@@ -230,7 +231,9 @@ def main():
     result["per_set"] = {}
     for s, a in zip(sets, per):
         entry = {"ms_per_step": a["t"] * 1e3, "value": s.pair_evals / a["t"],
-                 "base_pair_evals_frac": a["base_evals"] / max(1, args.steps) / s.pair_evals}
+                 "base_pair_evals_frac": a["base_evals"] / max(1, args.steps) / s.pair_evals,
+                 "base_evals_per_distance": a["base_evals"] / max(1, a["dist_evals"]),
+                 "mfma_distance_frac": a["mfma_evals"] / max(1, a["base_evals"])}
         n = a["k_launches"][_lib.K_BASE]
         if n > 0:
             ms = a["k_ms"][_lib.K_BASE]

@@ -170,6 +170,10 @@ typedef struct gs_stats {
   double pair_evals_per_s;  /* M N n_h / t_total_ms: the call's rate in point-pair
                                evaluations per second equivalent (section 7's measure
                                of a whole sweep, preprocessing included) */
+  int64_t base_mfma_pair_evals; /* of base_pair_evals, those whose squared distance came
+                               from the matrix cores (the norm expansion, admitted per
+                               leaf pair and bandwidth where its rounding stays below
+                               2^-12 of a term); the rest use the difference form */
 } gs_stats;
 
 /* Kernel classes of gs_stats.k_ms. */

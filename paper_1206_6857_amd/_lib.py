@@ -75,7 +75,7 @@ class GsStats(ctypes.Structure):
                 ("tuned_method", ctypes.c_int32), ("autotune_trials", ctypes.c_int32),
                 ("workspace_requests", ctypes.c_int64), ("p_hist", (ctypes.c_int64 * 16) * 3),
                 ("tokens_deposited", ctypes.c_double), ("tokens_withdrawn", ctypes.c_double),
-                ("pair_evals_per_s", ctypes.c_double)]
+                ("pair_evals_per_s", ctypes.c_double), ("base_mfma_pair_evals", ctypes.c_int64)]
 K_BASE, K_EXHAUSTIVE, K_DECIDE, K_SERIES, K_POST, K_TREE, K_MOMENTS, K_DH, K_DL, K_H2L = range(10)
 
 

@@ -34,7 +34,8 @@ namespace gs {
 // histogram [3][16] of the DH, DL and H2L pairs.
 constexpr int kEvTok = 4;
 constexpr int kEvHist = 6;
-constexpr int kEvN = kEvHist + 3 * 16;
+constexpr int kEvMfma = kEvHist + 3 * 16;
+constexpr int kEvN = kEvMfma + 1;
 
 namespace {
 
@@ -442,6 +443,7 @@ void finish_dualtree_stats(gs_ctx_base* ctx) {
   std::memcpy(&S.tokens_withdrawn, hc + n_h * 6 + kEvTok + 1, sizeof(double));
   for (int x = 0; x < 3; ++x)
     for (int p = 0; p < 16; ++p) S.p_hist[x][p] = (int64_t)hc[n_h * 6 + kEvHist + 16 * x + p];
+  S.base_mfma_pair_evals = (int64_t)hc[n_h * 6 + kEvMfma];
   ctx->stats_pending = nullptr;
 }
 
@@ -940,6 +942,18 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
         rec = BUF(float, "base_rec", ra.rec_capacity * base_record_stride(D));
         ra.rec = rec;
       }
+      if (base_uses_mfma(D) && !ra.mrec) {
+        // set together once all three are allocated: a failed request here is
+        // retried whole
+        const int64_t groups = base_mfma_groups_capacity(N, nR);
+        float* mrec = BUF(float, "base_mrec", groups * base_mfma_group_floats(D));
+        int32_t* mgrp_off = BUF(int32_t, "base_mgrp_off", nR);
+        float* rmax2 = BUF(float, "base_rmax2", nR);
+        ra.mgroups_capacity = groups;
+        ra.mgrp_off = mgrp_off;
+        ra.rmax2 = rmax2;
+        ra.mrec = mrec;
+      }
       ba.grp = wl.grp[3];
       ba.n_groups = (int)used_grp[3];
       ba.ent = wl.ent[3];
@@ -954,6 +968,10 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.xq_perm = xq_perm;
       ba.rec = rec;
       ba.rec_off = ra.rec_off;
+      ba.mrec = ra.mrec;
+      ba.mgrp_off = ra.mgrp_off;
+      ba.rmax2 = ra.rmax2;
+      ba.mfma_evals = chunk_ev + kEvMfma;
       ba.max_leaf = opt.leaf_size;
       ba.D = D;
       ba.Mq = (int)Mq;

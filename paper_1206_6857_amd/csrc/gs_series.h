@@ -135,9 +135,19 @@ struct BaseRecordsArgs {
   int32_t* rec_off = nullptr;  // [n_nodes] out
   float* rec = nullptr;        // [rec_capacity][base_record_stride(D)] out
   int64_t rec_capacity = 0;
+  // MFMA distance records (when base_uses_mfma(D); else mrec = nullptr): per
+  // leaf, groups of 32 references [base_mfma_group_floats(D)] from
+  // mgrp_off[leaf]; rmax2[leaf] = largest |x_r - c_leaf|^2 of its points
+  float* mrec = nullptr;
+  int64_t mgroups_capacity = 0;  // base_mfma_groups_capacity
+  int32_t* mgrp_off = nullptr;   // [n_nodes] out
+  float* rmax2 = nullptr;        // [n_nodes] out
   void* temp = nullptr;
   size_t temp_bytes = 0;
 };
+bool base_uses_mfma(int D);
+int64_t base_mfma_groups_capacity(int64_t n_points, int n_nodes);
+int base_mfma_group_floats(int D);
 int64_t base_records_capacity(int64_t n_points, int n_nodes);
 size_t base_records_temp_bytes(int n_nodes);
 hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s);
@@ -156,6 +166,10 @@ struct BaseFusedArgs {
   const double* xq_perm = nullptr;  // [M][D], query tree order
   const float* rec = nullptr;       // reference records (BaseRecordsArgs)
   const int32_t* rec_off = nullptr;
+  const float* mrec = nullptr;      // MFMA distance records (BaseRecordsArgs; may be null)
+  const int32_t* mgrp_off = nullptr;
+  const float* rmax2 = nullptr;
+  unsigned long long* mfma_evals = nullptr;  // += point-pair evaluations with MFMA distances
   int D = 0, Mq = 0;
   const float* s2 = nullptr;        // log2(e) / 2h^2 per bandwidth
   const unsigned long long* wmax_bits = nullptr;

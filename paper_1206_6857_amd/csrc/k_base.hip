@@ -31,10 +31,10 @@
 // range); the leaf-pair sum is unscaled in double precision.  Weights are
 // stored divided by the largest weight.  Where the box distance is a poor
 // bound (a query inside a large, sparsely filled box, e.g. in 8 dimensions),
-// every scaled term can still underflow: a leaf pair whose scaled sum ends
-// below 2^-60 for any lane and bandwidth is swept again for the whole wave
-// with each lane's shift taken from its smallest squared distance to the
-// leaf's points (one distance-only sweep), so that its largest term is 1.
+// every scaled term can still underflow: for a bandwidth whose scaled sum ends
+// below 2^-60 on any lane, the wave sweeps the leaf again with each lane's
+// shift taken from its smallest squared distance to the leaf's points (one
+// distance-only sweep), so that the largest term is 1.
 // Padding records sit far away (coordinates 1e18, weight 0): their terms are
 // exactly 0 and they never give the smallest distance.
 #include <cstring>  // rocprim uses memset without including it
@@ -51,7 +51,7 @@ namespace {
 constexpr int kW = 64;
 constexpr int kHB = 8;   // bandwidths per block
 constexpr int kPad = 4;  // records per leaf are padded to a multiple of this
-constexpr int kResidentWaves = 6 * 4 * 256;  // base_fused_kernel: 6 waves per SIMD
+constexpr int kResidentWaves = 4 * 4 * 256;  // base_fused_kernel: 4 waves per SIMD
 constexpr int kBaseWaves = 4;                 // waves per workgroup of base_fused_kernel
 constexpr int kReduceThreads = 256;           // base_reduce_kernel
 constexpr uint64_t kAgeStep = 30000;          // 300 us of the 100 MHz real-time clock
@@ -59,11 +59,82 @@ constexpr int kEntryCost = 256;               // issue slots of an entry's set-u
 
 constexpr float kFarPad = 1e18f;  // coordinate of the padding records
 
+// MFMA distance records (file comment): groups of kMG references; a group
+// holds, for k = 0, 2, 4, ..: 64 floats (a_k of its 32 references, then
+// a_{k+1}), then the 32 weights.  a = (-2 u_r, 1, |u_r|^2, 0 padding).
+constexpr int kMG = 32;
+constexpr float kFarNorm = 1e30f;  // |u_r|^2 of a padding reference
+__host__ __device__ constexpr int mfma_k2(int D) { return (D + 3) / 2 * 2; }
+__host__ __device__ constexpr int mfma_group_floats(int D) { return kMG * mfma_k2(D) + kMG; }
+// Dimensions whose compiled base tiles take distances from MFMA.
+constexpr bool mfma_dim(int DT) { return DT >= 2; }
+// Rounding bound of the expansion |u_q|^2 + |u_r|^2 - 2 u_q.u_r in float:
+// the two norms carry at most D units in the last place of themselves, the
+// products and the sum of the K2 augmented terms at most K2 of their absolute
+// sum, which is <= (|u_q| + |u_r|)^2; one more for the bound's own rounding.
+template <int D>
+constexpr int kMfmaErrC = D + mfma_k2(D) + 2;
+// Largest relative error of a kernel term admitted from the expansion.
+constexpr float kMfmaTau = 0x1p-12f;
+
 // Every record of the array set to a padding record: far coordinates, weight 0.
 __global__ void pad_records_kernel(float* __restrict__ rec, int64_t n_floats, int D, int rs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_floats) return;
   rec[i] = (int)(i % rs) < D ? kFarPad : 0.0f;
+}
+
+// Every MFMA record group set to padding references: a = (0, 1, 1e30, 0),
+// weight 0, so that a padding reference's squared distance is ~1e30 and its
+// term exactly 0.
+__global__ void mfma_pad_kernel(float* __restrict__ mrec, int64_t n_floats, int D) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_floats) return;
+  const int gf = mfma_group_floats(D), k2 = mfma_k2(D);
+  const int pos = (int)(i % gf);
+  float v = 0.0f;
+  if (pos < kMG * k2) {
+    const int k = 2 * (pos / 64) + (pos % 64) / kMG;
+    v = k == D ? 1.0f : k == D + 1 ? kFarNorm : 0.0f;
+  }
+  mrec[i] = v;
+}
+
+// Groups per leaf (0 for internal nodes), and the leaves' largest |u_r|^2 cleared.
+__global__ void mfma_groups_kernel(const int32_t* __restrict__ left, const int32_t* __restrict__ count,
+                                   int n_nodes, int32_t* __restrict__ ngroups, float* __restrict__ rmax2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  ngroups[i] = left[i] < 0 ? (count[i] + kMG - 1) / kMG : 0;
+  rmax2[i] = 0.0f;
+}
+
+// One thread per reference point: its augmented vector and weight in its
+// leaf's groups, and the leaf's largest |u_r|^2 (the same float coordinates
+// as the difference-form records).
+__global__ void mfma_records_kernel(const double* __restrict__ xr, const double* __restrict__ wr,
+                                    const int32_t* __restrict__ leaf_of_pos, const int32_t* __restrict__ begin,
+                                    const int32_t* __restrict__ mgrp_off, const double* __restrict__ rctr,
+                                    int64_t n, int D, const unsigned long long* __restrict__ wmax_bits,
+                                    float* __restrict__ mrec, float* __restrict__ rmax2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int L = leaf_of_pos[i];
+  const int idx = (int)(i - begin[L]);
+  const int k2 = mfma_k2(D);
+  float* g = mrec + (int64_t)(mgrp_off[L] + idx / kMG) * mfma_group_floats(D);
+  const int row = idx % kMG;
+  const double* c = rctr + (int64_t)L * D;
+  float nr = 0.0f;
+  for (int d = 0; d < D; ++d) {
+    const float u = (float)(xr[i * D + d] - c[d]);
+    nr = fmaf(u, u, nr);
+    g[(d / 2) * 64 + (d % 2) * kMG + row] = -2.0f * u;
+  }
+  g[(D / 2) * 64 + (D % 2) * kMG + row] = 1.0f;
+  g[((D + 1) / 2) * 64 + ((D + 1) % 2) * kMG + row] = nr;
+  g[kMG * k2 + row] = (float)(wr[i] / __longlong_as_double((long long)*wmax_bits));
+  atomicMax(reinterpret_cast<unsigned*>(rmax2) + L, __float_as_uint(nr));
 }
 
 __global__ void pad_counts_kernel(const int32_t* __restrict__ left, const int32_t* __restrict__ count,
@@ -322,6 +393,87 @@ __device__ __forceinline__ void sweep_leaf(const float* __restrict__ rec, int rs
   }
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Sweep of one reference leaf with squared distances from the MFMA norm
+// expansion, for NA bandwidths and the wave's 64 queries in two halves of 32:
+// in half s, lane l takes query (l % 32) + 32 s and the references of rows
+// 8 j + 4 (l / 32) + i (j, i < 4) of each 32-reference group, for which one
+// v_mfma_f32_32x32x2f32 per pair of augmented coordinates leaves
+// |u_q - u_r|^2 - T_q in its 16 accumulator registers (A: the group's records
+// (-2 u_r, 1, |u_r|^2), B: the queries' (u_q, |u_q|^2 - T_q, 1), with T_q the
+// query's squared distance to the leaf's box, so that every exponent
+// -s_h (|u_q - u_r|^2 - T_q) is <= 0 up to rounding).  Both halves use each
+// group's records while they are in registers; at the end the two lanes of a
+// query add their partial sums and the query's own lane keeps them.
+template <int D, int NA>
+__device__ __forceinline__ void mfma_sweep(const float* __restrict__ mg, int ngroups, int nsub, const float* uq,
+                                           float nqt, const float* shc, float* part) {
+  constexpr int K2 = mfma_k2(D), KM = K2 / 2, GF = mfma_group_floats(D);
+  const int lane = threadIdx.x & (kW - 1);
+  const int half = lane >> 5;
+  float bq[2][KM], p[2][NA];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int src = (lane & 31) + 32 * s;
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+      const int k0 = 2 * m, k1 = 2 * m + 1;
+      const float v0 = k0 < D ? uq[k0 < D ? k0 : 0] : k0 == D ? nqt : k0 == D + 1 ? 1.0f : 0.0f;
+      const float v1 = k1 < D ? uq[k1 < D ? k1 : 0] : k1 == D ? nqt : k1 == D + 1 ? 1.0f : 0.0f;
+      const float e0 = __shfl(v0, src, kW);
+      const float e1 = __shfl(v1, src, kW);
+      bq[s][m] = half ? e1 : e0;
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) p[s][j] = 0.0f;
+  }
+  const float* g = mg;
+  for (int gi = 0; gi < ngroups; ++gi, g += GF) {
+    float a[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) a[m] = g[m * 64 + lane];
+    float4 w4[4];
+#pragma unroll
+    for (int j4 = 0; j4 < 4; ++j4) w4[j4] = *reinterpret_cast<const float4*>(g + kMG * K2 + 8 * j4 + 4 * half);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {  // unrolled: s is a constant in each copy
+      if (s >= nsub) break;
+      f32x16 c = {};
+#pragma unroll
+      for (int m = 0; m < KM; ++m) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m], bq[s][m], c, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float wr = w4[i / 4][i % 4];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) p[s][j] = fmaf(wr, __builtin_amdgcn_exp2f(-c[i] * shc[j]), p[s][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const float v = p[s][j] + __shfl_xor(p[s][j], 32, kW);
+      if (half == s) part[j] = v;
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void mfma_sweep_leaf(int na, const float* __restrict__ mg, int ngroups, int nsub,
+                                                const float* uq, float nqt, const float* shc, float* part) {
+  switch (na) {
+    case 1: mfma_sweep<DT, 1>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 2: mfma_sweep<DT, 2>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 3: mfma_sweep<DT, 3>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 4: mfma_sweep<DT, 4>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 5: mfma_sweep<DT, 5>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 6: mfma_sweep<DT, 6>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    case 7: mfma_sweep<DT, 7>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+    default: mfma_sweep<DT, 8>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+  }
+}
+
 // Persistent waves (six per SIMD: four already keep the VALU busy; the
 // register budget allows eight) take work units from a queue counter until
 // none is left, heaviest slices first (slice_cost_kernel): unit u is query batch
@@ -339,20 +491,22 @@ __device__ __forceinline__ void sweep_leaf(const float* __restrict__ rec, int rs
 // catches up instead of becoming the tail.  Workgroups hold kBaseWaves
 // independent waves (no LDS, no barrier).
 template <int DT>
-__global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu(8))) void base_fused_kernel(
+__global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu(4))) void base_fused_kernel(
     const int4* __restrict__ slices, const int32_t* __restrict__ order, int n_slices,
     const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey,
     const uint8_t* __restrict__ umask, int rbits, int hbits, int hc0, int hc1, NodeView qt, NodeView rt,
     const int32_t* __restrict__ rec_off, const double* __restrict__ xq_perm, const float* __restrict__ rec,
+    const int32_t* __restrict__ mgrp_off, const float* __restrict__ mrec, const float* __restrict__ rmax2,
     int Drt, int rs_rt, const float* __restrict__ s2, const unsigned long long* __restrict__ wmax_bits,
     int Mq, int qmax, double* __restrict__ partial, double* __restrict__ gx,
-    int32_t* __restrict__ queue) {
+    int32_t* __restrict__ queue, unsigned long long* __restrict__ mfma_evals) {
   constexpr int DC = DT > 0 ? DT : kMaxD;
   const int D = DT > 0 ? DT : Drt;
   const int rs = DT > 0 ? (DT + 4) / 4 * 4 : rs_rt;
   const int QB = qmax / kW;
   const int n_units = n_slices * QB;
   const int lane = threadIdx.x & (kW - 1);
+  unsigned long long mfma_pairs = 0;  // point-pair evaluations from MFMA distances (uniform)
   for (;;) {
   int grab = 0;
   if (lane == 0) grab = atomicAdd(queue, 1);
@@ -372,10 +526,6 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
   if (base < qn) {
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
-    double xq[DC];
-#pragma unroll
-    for (int d = 0; d < DC; ++d)
-      if (d < D) xq[d] = xq_perm[(int64_t)qpos * D + d];
     double acc[kHB];
 #pragma unroll
     for (int k = 0; k < kHB; ++k) acc[k] = 0.0;
@@ -394,6 +544,12 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
       const double* cR = rt.ctr + (int64_t)R * D;
       const double* lR = rt.lo + (int64_t)R * D;
       const double* hR = rt.hi + (int64_t)R * D;
+      // the query's coordinates are read for every entry (from cache) rather
+      // than held in registers across the unit
+      double xq[DC];
+#pragma unroll
+      for (int d = 0; d < DC; ++d)
+        if (d < D) xq[d] = xq_perm[(int64_t)qpos * D + d];
       float uq[DC];
       double box2 = 0.0;
 #pragma unroll
@@ -407,62 +563,109 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
           box2 += gap * gap;
         }
       }
-      // Compact the entry's bandwidths: j-th set bit of m -> shc[j]
-      // (uniform), shiftc[j] = the lane's underflow shift for it.
-      const int na = __builtin_popcount(m);
-      float shc[kHB], shiftc[kHB], part[kHB];
-      {
-        unsigned mm = m;
+      // Bandwidths whose squared distances may come from the MFMA norm
+      // expansion (file comment): the expansion's rounding error is at most
+      // kMfmaErrC 2^-24 (|u_q| + |u_r|)^2, which moves a term's exponent by at
+      // most that times s_h; a bandwidth is admitted when the resulting
+      // relative error of every term is below kMfmaTau.
+      unsigned safe = 0;
+      float nq = 0.0f;
+      const float tq = (float)box2;  // the box shift T_q of the MFMA path
+      if (mfma_dim(DT) && mrec != nullptr) {
 #pragma unroll
-        for (int j = 0; j < kHB; ++j) {
-          const int k = mm ? __builtin_ctz(mm) : 0;
-          mm &= mm - 1;
-          shc[j] = s2[h0 + k];
-          shiftc[j] = (float)box2 * shc[j];
-          part[j] = 0.0f;
-        }
+        for (int d = 0; d < DC; ++d) nq = fmaf(uq[d], uq[d], nq);
+        float mx = nq;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kW));
+        const float rr = sqrtf(rmax2[R]) + sqrtf(mx);
+        const float bnd = (float)kMfmaErrC<DT> * 0x1p-24f * 0.6931472f * 1.0001f * (rr * rr);
+#pragma unroll
+        for (int k = 0; k < kHB; ++k)
+          if (((m >> k) & 1u) && bnd * s2[h0 + k] <= kMfmaTau) safe |= 1u << k;
+        safe = __builtin_amdgcn_readfirstlane(safe);
       }
       const float* rp = rec + (int64_t)rec_off[R] * rs;
       const int rnp = (rt.count[R] + kPad - 1) / kPad * kPad;
-      for (int pass = 0; pass < 2; ++pass) {
-        switch (na) {
-          case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-          default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+      for (int sub = 0; sub < 2; ++sub) {
+        const unsigned bits = sub == 0 ? safe : (m & ~safe);
+        if (bits == 0) continue;
+        const bool use_mfma = sub == 0;
+        // Compact the subset's bandwidths: j-th set bit -> shc[j] (uniform),
+        // shiftc[j] = the lane's underflow shift for it.
+        const int na = __builtin_popcount(bits);
+        float shc[kHB], shiftc[kHB], part[kHB], old[kHB];
+        {
+          unsigned mm = bits;
+#pragma unroll
+          for (int j = 0; j < kHB; ++j) {
+            const int k = mm ? __builtin_ctz(mm) : 0;
+            mm &= mm - 1;
+            shc[j] = s2[h0 + k];
+            shiftc[j] = (float)box2 * shc[j];
+            part[j] = 0.0f;
+            old[j] = 0.0f;
+          }
         }
-        if (pass == 1) break;
-        // Rescue (file comment): a sum below 2^-60 on any lane of the wave
-        // sends the whole wave through the leaf again with shifts from the
-        // lanes' smallest distances.
-        bool low = false;
+        if (use_mfma) mfma_pairs += (unsigned long long)na * (unsigned long long)rt.count[R] *
+                                    (unsigned long long)(qn - base < kW ? qn - base : kW);
+        unsigned low = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+          if (pass == 0 && use_mfma) {
+            if constexpr (mfma_dim(DT))
+              mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
+                                  (rt.count[R] + kMG - 1) / kMG, qn - base > kMG ? 2 : 1, uq, nq - tq, shc,
+                                  part);
+          } else {
+            switch (na) {
+              case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+              default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+            }
+          }
+          if (pass == 1) break;
+          // Rescue (file comment): a bandwidth whose sum is below 2^-60 on any
+          // active lane takes shifts from the lanes' smallest distances, and
+          // the wave sweeps the leaf again (difference form); the other
+          // bandwidths keep their first sweep, so a bandwidth's result does
+          // not depend on which other bandwidths share the entry.
 #pragma unroll
-        for (int j = 0; j < kHB; ++j)
-          if (j < na && part[j] < 0x1p-60f) low = true;
-        if (!__any(low)) break;
-        const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
+          for (int j = 0; j < kHB; ++j)
+            if (j < na && __any(active && part[j] < 0x1p-60f)) low |= 1u << j;
+          if (low == 0) break;
+          const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
 #pragma unroll
-        for (int j = 0; j < kHB; ++j) {
-          shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
-          part[j] = 0.0f;
+          for (int j = 0; j < kHB; ++j) {
+            if ((low >> j) & 1u) shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
+            old[j] = part[j];
+            part[j] = 0.0f;
+          }
         }
-      }
-      {
-        unsigned mm = m;
+        if (low != 0) {
 #pragma unroll
-        for (int j = 0; j < kHB; ++j) {
-          if (mm == 0) break;
-          const int k = __builtin_ctz(mm);
-          mm &= mm - 1;
-          const float fi = floorf(shiftc[j]);
-          const double v = ldexp((double)(part[j] * __builtin_amdgcn_exp2f(fi - shiftc[j])), -(int)fi);
+          for (int j = 0; j < kHB; ++j)
+            if (!((low >> j) & 1u)) part[j] = old[j];
+        }
+        {
+          unsigned mm = bits;
 #pragma unroll
-          for (int t = 0; t < kHB; ++t)
-            if (t == k) acc[t] += v;
+          for (int j = 0; j < kHB; ++j) {
+            if (mm == 0) break;
+            const int k = __builtin_ctz(mm);
+            mm &= mm - 1;
+            // the MFMA path's terms are scaled by 2^(T_q s_h), formed
+            // exactly in double; the difference form's by 2^shiftc
+            const double sc = use_mfma && !((low >> j) & 1u) ? (double)tq * (double)shc[j] : (double)shiftc[j];
+            const double fi = floor(sc);
+            const double v = ldexp((double)(part[j] * __builtin_amdgcn_exp2f((float)(fi - sc))), -(int)fi);
+#pragma unroll
+            for (int t = 0; t < kHB; ++t)
+              if (t == k) acc[t] += v;
+          }
         }
       }
     }
@@ -480,6 +683,7 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
     }
   }
   }  // next slice
+  if (lane == 0 && mfma_pairs) atomicAdd(mfma_evals, mfma_pairs);
 }
 
 // Runs of several slices: gx = sum of the slices' partials in slice order.
@@ -525,8 +729,8 @@ void launch_fused_t(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t 
   hipLaunchKernelGGL((base_fused_kernel<DT>), dim3((unsigned)nb), dim3(kW * kBaseWaves), 0, s, a.slices, a.mpos,
                      p.n_slices,
                      a.run_start, a.ukey, a.umask, p.rbits, p.hbits, a.hc0, a.hc1, a.qt,
-                     a.rt, a.rec_off, a.xq_perm, a.rec, a.D, base_record_stride(a.D), a.s2, a.wmax_bits,
-                     a.Mq, p.qmax, a.partial, a.gx, a.counters + 4);
+                     a.rt, a.rec_off, a.xq_perm, a.rec, a.mgrp_off, a.mrec, a.rmax2, a.D, base_record_stride(a.D),
+                     a.s2, a.wmax_bits, a.Mq, p.qmax, a.partial, a.gx, a.counters + 4, a.mfma_evals);
 }
 
 }  // namespace
@@ -545,7 +749,29 @@ size_t base_records_temp_bytes(int n_nodes) {
   return b;
 }
 
+bool base_uses_mfma(int D) { return D == 2 || D == 3 || D == 4 || D == 5 || D == 8 || D == 16; }
+
+int64_t base_mfma_groups_capacity(int64_t n_points, int n_nodes) { return n_points / kMG + n_nodes + 1; }
+
+int base_mfma_group_floats(int D) { return mfma_group_floats(D); }
+
 hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s) {
+  if (a.mrec) {
+    // MFMA records: padding everywhere, group offsets per leaf, then the points
+    const int64_t mf = a.mgroups_capacity * mfma_group_floats(a.D);
+    hipLaunchKernelGGL(mfma_pad_kernel, dim3((unsigned)ceil_div(mf, 256)), dim3(256), 0, s, a.mrec, mf, a.D);
+    hipLaunchKernelGGL(mfma_groups_kernel, dim3((unsigned)ceil_div(a.n_nodes, 256)), dim3(256), 0, s, a.left,
+                       a.count, a.n_nodes, a.padded, a.rmax2);
+    size_t mbytes = a.temp_bytes;
+    hipError_t me = rocprim::exclusive_scan(a.temp, mbytes, a.padded, a.mgrp_off, 0, (size_t)a.n_nodes,
+                                            rocprim::plus<int32_t>(), s);
+    if (me != hipSuccess) return me;
+    hipLaunchKernelGGL(mfma_records_kernel, dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, s, a.xr_perm,
+                       a.wr_perm, a.leaf_of_pos, a.begin, a.mgrp_off, a.rctr, a.n, a.D, a.wmax_bits, a.mrec,
+                       a.rmax2);
+    me = hipGetLastError();
+    if (me != hipSuccess) return me;
+  }
   const int64_t n_floats = a.rec_capacity * base_record_stride(a.D);
   hipLaunchKernelGGL(pad_records_kernel, dim3((unsigned)ceil_div(n_floats, 256)), dim3(256), 0, s, a.rec, n_floats,
                      a.D, base_record_stride(a.D));

@@ -341,3 +341,27 @@ def test_kernel_timing_modes():
     with pytest.raises(g.GaussSumError) as e:
         c.gauss_sum(r, r, w, hs, 0.01, kernel_timing=3)
     assert e.value.status == _lib.GS_EINVAL
+
+
+def test_base_tiles_mfma_and_difference_paths():
+    """The base tiles take a bandwidth's squared distances from the MFMA norm
+    expansion only where its rounding bound admits it, else from the
+    difference form; on a set whose bandwidths run from far below to far above
+    the leaf extents both paths carry work, and the values stay within the
+    rounding tolerance of the oracle's run with the same decisions.  Each
+    bandwidth's path and value do not depend on the other bandwidths of the
+    call (a chunked sweep gives the same values)."""
+    banner("base tiles mfma paths")
+    r, w, _ = mixture((93, 5), 6000, 5, 6, (0.01, 0.1), weights=(0.5, 1.5))
+    hs = np.logspace(-3, 0.3, 12)
+    c = ctx()
+    G = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=128, keep_trace=1)
+    st = c.stats()
+    assert 0 < st.base_mfma_pair_evals < st.base_pair_evals, (st.base_mfma_pair_evals, st.base_pair_evals)
+    ref = DT.dualtree(r, r, w, hs, 0.01, leaf_size=128, trace=True)
+    assert np.array_equal(c.pair_counts(len(hs)), ref.counts)
+    exact = gauss_sum_exhaustive(r, r, w, hs)
+    assert (np.abs(G - ref.G) / exact).max() <= TOL_ROUND
+    assert (np.abs(G - exact) / exact).max() <= 0.01
+    G1 = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=128, h_chunk=1)
+    assert (np.abs(G1 - G) / exact).max() <= 1e-12
