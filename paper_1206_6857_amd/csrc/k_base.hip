@@ -474,6 +474,21 @@ __device__ __forceinline__ void mfma_sweep_leaf(int na, const float* __restrict_
   }
 }
 
+template <int DT>
+__device__ __forceinline__ void sweep_leaf_na(int na, const float* __restrict__ rp, int rs, int D, int rnp,
+                                              const float* uq, const float* shc, const float* shiftc, float* part) {
+  switch (na) {
+    case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+    default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
+  }
+}
+
 // Persistent waves (six per SIMD: four already keep the VALU busy; the
 // register budget allows eight) take work units from a queue counter until
 // none is left, heaviest slices first (slice_cost_kernel): unit u is query batch
@@ -506,6 +521,7 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
   const int QB = qmax / kW;
   const int n_units = n_slices * QB;
   const int lane = threadIdx.x & (kW - 1);
+  __shared__ double acc_lds[kBaseWaves * kHB * kW];
   unsigned long long mfma_pairs = 0;  // point-pair evaluations from MFMA distances (uniform)
   for (;;) {
   int grab = 0;
@@ -526,9 +542,11 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
   if (base < qn) {
     const bool active = base + lane < qn;
     const int qpos = qb + base + (active ? lane : 0);
-    double acc[kHB];
+    // the unit's sums per bandwidth live in LDS, not registers: they are
+    // touched once per entry, and registers are what the sweeps need
+    double* acc = acc_lds + (threadIdx.x / kW) * kHB * kW + lane;
 #pragma unroll
-    for (int k = 0; k < kHB; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kHB; ++k) acc[k * kW] = 0.0;
     for (int e = sd.y; e < sd.z; ++e) {
       if (prio < 3) {
         const uint64_t age = __builtin_amdgcn_s_memrealtime() - t_unit;
@@ -593,7 +611,7 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
         // Compact the subset's bandwidths: j-th set bit -> shc[j] (uniform),
         // shiftc[j] = the lane's underflow shift for it.
         const int na = __builtin_popcount(bits);
-        float shc[kHB], shiftc[kHB], part[kHB], old[kHB];
+        float shc[kHB], shiftc[kHB], part[kHB];
         {
           unsigned mm = bits;
 #pragma unroll
@@ -603,69 +621,53 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
             shc[j] = s2[h0 + k];
             shiftc[j] = (float)box2 * shc[j];
             part[j] = 0.0f;
-            old[j] = 0.0f;
           }
         }
         if (use_mfma) mfma_pairs += (unsigned long long)na * (unsigned long long)rt.count[R] *
                                     (unsigned long long)(qn - base < kW ? qn - base : kW);
-        unsigned low = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-          if (pass == 0 && use_mfma) {
-            if constexpr (mfma_dim(DT))
-              mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
-                                  (rt.count[R] + kMG - 1) / kMG, qn - base > kMG ? 2 : 1, uq, nq - tq, shc,
-                                  part);
-          } else {
-            switch (na) {
-              case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-              default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-            }
-          }
-          if (pass == 1) break;
-          // Rescue (file comment): a bandwidth whose sum is below 2^-60 on any
-          // active lane takes shifts from the lanes' smallest distances, and
-          // the wave sweeps the leaf again (difference form); the other
-          // bandwidths keep their first sweep, so a bandwidth's result does
-          // not depend on which other bandwidths share the entry.
-#pragma unroll
-          for (int j = 0; j < kHB; ++j)
-            if (j < na && __any(active && part[j] < 0x1p-60f)) low |= 1u << j;
-          if (low == 0) break;
-          const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
-#pragma unroll
-          for (int j = 0; j < kHB; ++j) {
-            if ((low >> j) & 1u) shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
-            old[j] = part[j];
-            part[j] = 0.0f;
-          }
-        }
-        if (low != 0) {
-#pragma unroll
-          for (int j = 0; j < kHB; ++j)
-            if (!((low >> j) & 1u)) part[j] = old[j];
-        }
-        {
+        // Adds the sums of the subset's j-th bandwidths selected by jmask to
+        // the unit's accumulators, unscaled in double: the MFMA path's terms
+        // carry the factor 2^(T_q s_h) (formed exactly in double), the
+        // difference form's 2^shiftc.
+        auto accumulate = [&](unsigned jmask, bool mfma_scaled) {
           unsigned mm = bits;
 #pragma unroll
           for (int j = 0; j < kHB; ++j) {
             if (mm == 0) break;
             const int k = __builtin_ctz(mm);
             mm &= mm - 1;
-            // the MFMA path's terms are scaled by 2^(T_q s_h), formed
-            // exactly in double; the difference form's by 2^shiftc
-            const double sc = use_mfma && !((low >> j) & 1u) ? (double)tq * (double)shc[j] : (double)shiftc[j];
+            if (!((jmask >> j) & 1u)) continue;
+            const double sc = mfma_scaled ? (double)tq * (double)shc[j] : (double)shiftc[j];
             const double fi = floor(sc);
-            const double v = ldexp((double)(part[j] * __builtin_amdgcn_exp2f((float)(fi - sc))), -(int)fi);
-#pragma unroll
-            for (int t = 0; t < kHB; ++t)
-              if (t == k) acc[t] += v;
+            acc[k * kW] += ldexp((double)(part[j] * __builtin_amdgcn_exp2f((float)(fi - sc))), -(int)fi);
           }
+        };
+        if (use_mfma) {
+          if constexpr (mfma_dim(DT))
+            mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
+                                (rt.count[R] + kMG - 1) / kMG, qn - base > kMG ? 2 : 1, uq, nq - tq, shc, part);
+        } else {
+          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, shiftc, part);
+        }
+        // Rescue (file comment): a bandwidth whose sum is below 2^-60 on any
+        // active lane takes shifts from the lanes' smallest distances, and the
+        // wave sweeps the leaf again (difference form); the other bandwidths
+        // keep their first sweep, so a bandwidth's result does not depend on
+        // which other bandwidths share the entry.
+        unsigned low = 0;
+#pragma unroll
+        for (int j = 0; j < kHB; ++j)
+          if (j < na && __any(active && part[j] < 0x1p-60f)) low |= 1u << j;
+        accumulate(~low, use_mfma);
+        if (low != 0) {
+          const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
+#pragma unroll
+          for (int j = 0; j < kHB; ++j) {
+            if ((low >> j) & 1u) shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
+            part[j] = 0.0f;
+          }
+          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, shiftc, part);
+          accumulate(low, false);
         }
       }
     }
@@ -674,11 +676,11 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
         const double wscale = __longlong_as_double((long long)*wmax_bits);
 #pragma unroll
         for (int k = 0; k < kHB; ++k)
-          if (h0 + k >= hc0 && h0 + k < hc1) gx[(int64_t)(h0 + k) * Mq + qpos] = acc[k] * wscale;
+          if (h0 + k >= hc0 && h0 + k < hc1) gx[(int64_t)(h0 + k) * Mq + qpos] = acc[k * kW] * wscale;
       } else {
         double* pp = partial + (int64_t)sd.w * kHB * qmax + base + lane;
 #pragma unroll
-        for (int k = 0; k < kHB; ++k) pp[(int64_t)k * qmax] = acc[k];
+        for (int k = 0; k < kHB; ++k) pp[(int64_t)k * qmax] = acc[k * kW];
       }
     }
   }
