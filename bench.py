@@ -39,9 +39,10 @@ FP32_PEAK_TFLOPS = 157.3
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
 # Non-packed FP32 issue: one VALU instruction per lane per clock per SIMD lane.
 LANE_SLOTS_PER_S = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_HZ   # 3.93e13
-# Issue cost of one v_exp_f32 in VALU slots, relative to an FMA; measured on
-# gfx950 (half the FMA rate).
-EXP_SLOTS = 2.0
+# Issue cost of one v_exp_f32 in VALU slots, relative to an FMA, measured on
+# gfx950 in the tiles' mix (one exp2 beside one multiply and two FMAs: 1.65;
+# alone it runs at half the FMA rate).
+EXP_SLOTS = 1.65
 
 HEADLINE_DIMS = (2, 3, 5, 8)
 
@@ -56,8 +57,9 @@ def method_flops(D, dist_evals, pair_evals):
 
 def issue_slots(D, dist_evals, pair_evals, dist_slots_per_dim=2.0):
     """Non-packed VALU issue slots of the same work: dist_slots_per_dim per
-    dimension of each squared distance (difference + FMA; 4 for the split-float
-    exhaustive tiles), and per kernel evaluation one FMA (exponent), one exp2
+    dimension of each squared distance formed on the VALU (difference + FMA; 4
+    for the split-float exhaustive tiles; distances from the matrix cores take
+    none), and per kernel evaluation one multiply or FMA (exponent), one exp2
     (EXP_SLOTS) and one FMA (accumulation)."""
     return dist_slots_per_dim * D * dist_evals + (2.0 + EXP_SLOTS) * pair_evals
 
@@ -247,7 +249,9 @@ def main():
     if n_base > 0:
         ms = sum(a["k_ms"][_lib.K_BASE] for a in per)
         flops = sum(method_flops(s.D, a["dist_evals"], a["base_evals"]) for s, a in zip(sets, per))
-        slots = sum(issue_slots(s.D, a["dist_evals"], a["base_evals"]) for s, a in zip(sets, per))
+        # distances on the VALU only for the kernel evaluations the MFMA path did not take
+        slots = sum(issue_slots(s.D, a["dist_evals"] * (1.0 - a["mfma_evals"] / max(1, a["base_evals"])),
+                                a["base_evals"]) for s, a in zip(sets, per))
         achieved = flops / (ms * 1e-3) / 1e12
         issue_peak = LANE_SLOTS_PER_S * flops / slots / 1e12
         traffic = []
@@ -269,7 +273,8 @@ def main():
                                 "flops": flops / n_base},
             "issue_model": {"peak_tflops": issue_peak, "frac": achieved / issue_peak,
                             "note": "non-packed FP32 issue (3.93e13 lane-slots/s) at this kernel's "
-                                    "mix: 2D slots per distance, 2 + %g per kernel evaluation" % EXP_SLOTS}}
+                                    "mix: 2D slots per distance formed on the VALU (MFMA distances: "
+                                    "none), 2 + %g per kernel evaluation" % EXP_SLOTS}}
 
     # ---- the plain GPU exhaustive path on the same sets (one step: ~20 s per set)
     if not args.no_exhaustive:
