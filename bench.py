@@ -109,9 +109,12 @@ def log(*parts):
 class Set:
     """One workload resident on the device, with its output buffer."""
 
-    def __init__(self, wl, dev):
+    def __init__(self, wl, dev, ctx):
         import torch
         self.wl = wl
+        self.ctx = ctx          # shared by the sets (one device workspace)
+        self.policy = "rule"
+        self.params = None      # this set's trained policy parameters
         self.M, self.N, self.D, self.n_h = wl.queries.shape[0], wl.refs.shape[0], wl.D, len(wl.bandwidths)
         self.rd = torch.from_numpy(wl.refs).to(dev)
         self.qd = self.rd if wl.monochromatic else torch.from_numpy(wl.queries).to(dev)
@@ -120,18 +123,34 @@ class Set:
         self.out = torch.empty((self.n_h, self.M), dtype=torch.float64, device=dev)
         self.pair_evals = float(self.M) * self.N * self.n_h
 
-    def call(self, ctx, **kw):
-        ctx.gauss_sum(self.qd, self.rd, self.wd, self.hd, self.wl.eps, out=self.out, **kw)
+    def call(self, **kw):
+        if kw.get("policy") == "learned":
+            self.ctx.policy_set_params(self.params)  # host-side; uploaded with the call
+        self.ctx.gauss_sum(self.qd, self.rd, self.wd, self.hd, self.wl.eps, out=self.out, **kw)
+
+    def train_policy(self, workload, scale):
+        """The learned pair policy of this set's context, trained on the records
+        of a smaller draw of the same workload recipe (another draw; logging
+        and training are parameter selection, outside every timed region)."""
+        tr = workload(4, D=self.D, scale=scale, draw=1)
+        t0 = time.perf_counter()
+        self.ctx.gauss_sum(tr.refs, tr.refs, tr.weights, tr.bandwidths, tr.eps, leaf_size=256, log_pairs=1,
+                           log_explore=0.3)
+        rec, _ = self.ctx.policy_log()
+        loss = self.ctx.policy_train(rec, steps=1500, batch=4096, seed=1)
+        self.params = self.ctx.policy_params()
+        self.train_info = {"trained_on": tr.name + " (another draw)", "records": int(rec.shape[0]),
+                           "loss": loss, "train_s": time.perf_counter() - t0}
 
 
-def timed(ctx, sets, steps, warmup, opts_of):
+def timed(sets, steps, warmup, opts_of):
     """warmup untimed steps, then `steps` timed steps; a step is one blocking
     gauss_sum call per set.  Returns the step time, per-set times and the
     per-set sums of the base / exhaustive tile timers and work counters."""
     import torch
     for i in range(warmup):
         for s in sets:
-            s.call(ctx, **opts_of(s))
+            s.call(**opts_of(s))
             log("warm-up %d %s %s" % (i, s.wl.name, opts_of(s)))
     torch.cuda.synchronize()
     per = [dict(t=0.0, k_ms=np.zeros(12), k_launches=np.zeros(12, dtype=np.int64), base_evals=0,
@@ -142,9 +161,9 @@ def timed(ctx, sets, steps, warmup, opts_of):
             ts = time.perf_counter()
             # HIP events around the dominant tiles only (kernel_timing=2):
             # timing every kernel class adds tens of event records per call
-            s.call(ctx, kernel_timing=2, **opts_of(s))
+            s.call(kernel_timing=2, **opts_of(s))
             acc["t"] += time.perf_counter() - ts
-            st = ctx.stats()
+            st = s.ctx.stats()
             acc["k_ms"] += np.array(st.k_ms[:])
             acc["k_launches"] += np.array(st.k_launches[:])
             acc["base_evals"] += st.base_pair_evals
@@ -175,6 +194,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the DFTO, DFDO, DFD and LSCV legs")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")
     ap.add_argument("--leg-steps", type=int, default=10, help="timed steps of each leg")
+    ap.add_argument("--policy", choices=("auto", "rule", "learned"), default="auto",
+                    help="pair policy of the headline sets; auto (default): per set the faster of the "
+                         "rule and the learned policy, timed once each after the warm-up (the policy "
+                         "is trained on a 5%% draw of the set's recipe; untimed parameter selection)")
     ap.add_argument("--leaf-size", type=int, default=0,
                     help="kd-tree leaf size; 0 (default): chosen by the library's autotuner "
                          "during the warm-up steps")
@@ -195,8 +218,8 @@ def main():
 
     dev = torch.device("cuda:0")
     dims = [int(x) for x in args.dims.split(",") if x]
-    sets = [Set(workload(4, D=D), dev) for D in dims]
     ctx = g.Context(0)
+    sets = [Set(workload(4, D=D), dev, ctx) for D in dims]
     tune = dict(leaf_size=args.leaf_size) if args.leaf_size > 0 else dict(autotune=1)
 
     if args.calib_copy_mib > 0:
@@ -206,8 +229,40 @@ def main():
         torch.cuda.synchronize()
         del xc, yc
 
+    # ---- parameter selection (untimed): leaf size by the library's autotuner,
+    # then, per set, the pair policy
+    policy_ab = {}
+    for s in sets:
+        s.call(method="dualtree", **tune)
+        s.leaf = s.ctx.stats().tuned_leaf_size
+        s.method = s.ctx.stats().tuned_method
+        log("tuned %s: method %d leaf %d" % (s.wl.name, s.method, s.leaf))
+        if args.policy == "rule" or s.method != g.GS_DUALTREE:
+            continue
+        s.train_policy(workload, 0.05)
+        if args.policy == "learned":
+            s.policy = "learned"
+            continue
+        t = {}
+        for pol in ("rule", "learned", "rule", "learned"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.call(method="dualtree", leaf_size=s.leaf, policy=pol)
+            torch.cuda.synchronize()
+            t[pol] = min(t.get(pol, 1e30), time.perf_counter() - t0)
+        s.policy = "learned" if t["learned"] < t["rule"] else "rule"
+        policy_ab[s.wl.name] = {"rule_ms": t["rule"] * 1e3, "learned_ms": t["learned"] * 1e3,
+                                "speedup_vs_rule": t["rule"] / t["learned"], **s.train_info}
+        log("policy %s: rule %.1f ms, learned %.1f ms -> %s" % (s.wl.name, t["rule"] * 1e3, t["learned"] * 1e3,
+                                                               s.policy))
+
+    def headline_opts(s):
+        if s.method != g.GS_DUALTREE:
+            return dict(method="exhaustive")
+        return dict(method="dualtree", leaf_size=s.leaf, policy=s.policy)
+
     # ---- headline: the dual-tree sweep of every set
-    t_dt, per = timed(ctx, sets, args.steps, args.warmup, lambda s: dict(method="dualtree", **tune))
+    t_dt, per = timed(sets, args.steps, args.warmup, headline_opts)
     pair_evals = sum(s.pair_evals for s in sets)
     names = {g.GS_DUALTREE: "dualtree", g.GS_EXHAUSTIVE: "exhaustive"}
     result = {
@@ -228,6 +283,7 @@ def main():
                    "eps": sets[0].wl.eps, "autotune": args.leaf_size <= 0,
                    "method": {s.wl.name: names.get(a["method"], "?") for s, a in zip(sets, per)},
                    "leaf_size": {s.wl.name: int(a["leaf"]) for s, a in zip(sets, per)},
+                   "policy": {s.wl.name: s.policy for s in sets},
                    "parallelism": "single-gpu"},
     }
     result["per_set"] = {}
@@ -242,6 +298,8 @@ def main():
             entry["base_kernel_ms"] = ms / max(1, args.steps)
             entry["base_tflops"] = method_flops(s.D, a["dist_evals"], a["base_evals"]) / (ms * 1e-3) / 1e12
         result["per_set"][s.wl.name] = entry
+    if policy_ab:
+        result["policy_ab"] = policy_ab
 
     # Dominant kernel of the step: the bandwidth-fused base tiles, all sets
     # (HIP events on the library's stream around each launch, timed steps only).
@@ -278,7 +336,7 @@ def main():
 
     # ---- the plain GPU exhaustive path on the same sets (one step: ~20 s per set)
     if not args.no_exhaustive:
-        t_ex, per_ex = timed(ctx, sets, 1, 0, lambda s: dict(method="exhaustive"))
+        t_ex, per_ex = timed(sets, 1, 0, lambda s: dict(method="exhaustive"))
         ex = {"value": pair_evals / t_ex, "ms_per_step": t_ex * 1e3, "steps": 1}
         ms = sum(a["k_ms"][_lib.K_EXHAUSTIVE] for a in per_ex)
         if ms > 0:
@@ -296,9 +354,9 @@ def main():
 
     # ---- the D=3, 10^5-point, 10-bandwidth workload and the paper's variants on it
     if not args.no_legs:
-        small = Set(workload(1), dev)
+        small = Set(workload(1), dev, ctx)
         ls = args.leg_steps
-        t1, p1 = timed(ctx, [small], ls, 1, lambda s: dict(method="dualtree", **tune))
+        t1, p1 = timed([small], ls, 1, lambda s: dict(method="dualtree", **tune))
         leaf = int(p1[0]["leaf"])
         leg = {"workload": small.wl.name, "ms_per_step": t1 * 1e3, "value": small.pair_evals / t1,
                "leaf_size": leaf, "method": names.get(p1[0]["method"], "?"),
@@ -307,14 +365,14 @@ def main():
         leg["pairs"] = {k: int(pc[:, i].sum()) for i, k in enumerate(["FD", "DH", "DL", "H2L", "BASE", "SPLIT"])}
         if p1[0]["method"] == g.GS_DUALTREE:
             fixed = dict(leaf_size=leaf, autotune=0)
-            t_sr, p_sr = timed(ctx, [small], ls, 1, lambda s: dict(method="dualtree", node_bounds="sphere_rect",
+            t_sr, p_sr = timed([small], ls, 1, lambda s: dict(method="dualtree", node_bounds="sphere_rect",
                                                                       **fixed))
             leg["sphere_rect_bounds"] = {"ms_per_step": t_sr * 1e3, "speedup_vs_box": t1 / t_sr,
                                          "base_pair_evals_frac": p_sr[0]["base_evals"] / ls / small.pair_evals}
             if not args.no_variants:
                 variants = {}
                 for m in ("dfto", "dfdo", "dfd"):
-                    t_m, p_m = timed(ctx, [small], ls, 1, lambda s, m=m: dict(method=m, **fixed))
+                    t_m, p_m = timed([small], ls, 1, lambda s, m=m: dict(method=m, **fixed))
                     pc_m = ctx.pair_counts(small.n_h)
                     variants[m] = {"ms_per_step": t_m * 1e3, "time_vs_dito": t_m / t1,
                                    "pairs": {k: int(pc_m[:, i].sum())
@@ -342,8 +400,9 @@ def main():
                               log_explore=0.3)
                 rec, _ = ctx.policy_log()
                 loss = ctx.policy_train(rec, steps=1500, batch=4096, seed=1)
+                small.params = ctx.policy_params()
                 t_train = time.perf_counter() - t0
-                t_lp, _ = timed(ctx, [small], ls, 1, lambda s: dict(method="dualtree", policy="learned", **fixed))
+                t_lp, _ = timed([small], ls, 1, lambda s: dict(method="dualtree", policy="learned", **fixed))
                 st_lp = ctx.stats()
                 leg["learned_policy"] = {
                     "ms_per_step": t_lp * 1e3, "speedup_vs_rule": t1 / t_lp,
@@ -351,7 +410,7 @@ def main():
                     "policy_calls": int(st_lp.policy_calls), "policy_overrides": int(st_lp.policy_overrides),
                     "trained_on": tr.name + " (another draw)"}
         if not args.no_exhaustive:
-            t_e1, _ = timed(ctx, [small], ls, 1, lambda s: dict(method="exhaustive"))
+            t_e1, _ = timed([small], ls, 1, lambda s: dict(method="exhaustive"))
             leg["exhaustive_ms_per_step"] = t_e1 * 1e3
             leg["dualtree_over_exhaustive"] = t_e1 / t1
         result["legs"] = {small.wl.name: leg}

@@ -385,7 +385,8 @@ gs_status gs_tensor_indices(int32_t D, int32_t p, int64_t* n_terms, int32_t* alp
  * 0 below -700), out[1][i] = x[i] / y[i], out[2][i] = sqrt(y[i]).  Host
  * pointers x[n], y[n], out[3][n]; 1 <= n <= 2^24, else GS_EINVAL.  Tests
  * compare these bits with the host's correctly rounded division and square
- * root and with an independent exp of the same definition. */
+ * root and with an independent exp of the same definition.  Its device buffers
+ * are freed before it returns. */
 gs_status gs_decision_arith(gs_ctx* ctx, const double* x, const double* y, int64_t n, double* out);
 
 /* ---------------------------------------------------------------------------

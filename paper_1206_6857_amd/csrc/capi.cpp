@@ -65,6 +65,13 @@ void* Workspace::get_pinned(const std::string& name, size_t bytes, hipError_t* e
   return b.p;
 }
 
+void Workspace::release(const std::string& name) {
+  auto it = bufs.find(name);
+  if (it == bufs.end()) return;
+  if (it->second.p) (void)hipFree(it->second.p);
+  bufs.erase(it);
+}
+
 void Workspace::release_all() {
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
@@ -380,6 +387,16 @@ gs_status gs_decision_arith(gs_ctx* ctx, const double* x, const double* y, int64
   if (n < 1 || n > (int64_t)1 << 24) GS_FAIL(ctx, GS_EINVAL, "n must be in [1, 2^24]");
   GS_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
+  // a test entry point: its buffers (up to 640 MiB) are freed when it returns
+  struct Release {
+    gs_ctx* c;
+    ~Release() {
+      (void)hipStreamSynchronize(c->stream);
+      c->ws.release("arith_x");
+      c->ws.release("arith_y");
+      c->ws.release("arith_out");
+    }
+  } release{ctx};
   double* dx = WS(double, "arith_x", n);
   double* dy = WS(double, "arith_y", n);
   double* dout = WS(double, "arith_out", 3 * n);

@@ -25,6 +25,7 @@ struct Workspace {
   std::map<std::string, Buf> pinned;  // page-locked host buffers (hipHostMalloc)
   void* get(const std::string& name, size_t bytes, gs_ctx_base* ctx, hipError_t* err);
   void* get_pinned(const std::string& name, size_t bytes, hipError_t* err);
+  void release(const std::string& name);  // frees one named device buffer (no-op if absent)
   void release_all();
 };
 
