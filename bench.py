@@ -369,6 +369,10 @@ def main():
                                                                       **fixed))
             leg["sphere_rect_bounds"] = {"ms_per_step": t_sr * 1e3, "speedup_vs_box": t1 / t_sr,
                                          "base_pair_evals_frac": p_sr[0]["base_evals"] / ls / small.pair_evals}
+            # best-first walk of every query node's list (decreasing dmin^2)
+            t_ff, p_ff = timed([small], ls, 1, lambda s: dict(method="dualtree", pair_order="far_first", **fixed))
+            leg["far_first_order"] = {"ms_per_step": t_ff * 1e3, "speedup_vs_tree": t1 / t_ff,
+                                      "base_pair_evals_frac": p_ff[0]["base_evals"] / ls / small.pair_evals}
             if not args.no_variants:
                 variants = {}
                 for m in ("dfto", "dfdo", "dfd"):

@@ -124,9 +124,18 @@ typedef struct gs_options {
                                gs_policy_train) before returning; NULL (default): keep
                                them in the context only (gs_policy_get_log).  The
                                library does not keep the pointer. */
+  int32_t pair_order;       /* the order in which the token walk takes a query node's
+                               reference list at each level: GS_ORDER_TREE (default:
+                               left to right, the order of the recursion of Figure 1)
+                               or GS_ORDER_FAR_FIRST (a best-first order in the spirit
+                               of the priority-queue traversal of section 1: decreasing
+                               squared box distance (with node_bounds, the tighter
+                               bound), ties by reference node, so that far prunings
+                               deposit their tokens before near pairs spend them) */
 } gs_options;
 
 enum { GS_BOUNDS_BOX = 0, GS_BOUNDS_SPHERE_RECT = 1 };
+enum { GS_ORDER_TREE = 0, GS_ORDER_FAR_FIRST = 1 };
 
 typedef struct gs_stats {
   int32_t struct_size;      /* set by the caller to sizeof(gs_stats) */

@@ -107,7 +107,7 @@ class Context:
         'learned'), leaf_size, plimit, monochromatic, eps_round_share,
         keep_trace, log_pairs, log_path, log_explore, blocking, fmm_mask,
         kernel_timing, h_chunk, max_frontier, node_bounds ('box', 'sphere_rect'),
-        autotune, debug_fail_alloc."""
+        pair_order ('tree', 'far_first'), autotune, debug_fail_alloc."""
         lib = _lib.load()
         same = queries is refs
         r = _Arr(refs)
@@ -143,6 +143,8 @@ class Context:
                 v = _lib.POLICIES[v] if isinstance(v, str) else int(v)
             elif k == "node_bounds":
                 v = _lib.NODE_BOUNDS[v] if isinstance(v, str) else int(v)
+            elif k == "pair_order":
+                v = _lib.PAIR_ORDERS[v] if isinstance(v, str) else int(v)
             elif k == "log_path" and v is not None:
                 v = str(v).encode()
             if not hasattr(opt, k):

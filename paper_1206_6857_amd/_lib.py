@@ -18,6 +18,8 @@ METHODS = {"dualtree": GS_DUALTREE, "dito": GS_DUALTREE, "exhaustive": GS_EXHAUS
 POLICIES = {"rule": GS_RULE, "learned": GS_LEARNED}
 GS_BOUNDS_BOX, GS_BOUNDS_SPHERE_RECT = 0, 1
 NODE_BOUNDS = {"box": GS_BOUNDS_BOX, "sphere_rect": GS_BOUNDS_SPHERE_RECT}
+GS_ORDER_TREE, GS_ORDER_FAR_FIRST = 0, 1
+PAIR_ORDERS = {"tree": GS_ORDER_TREE, "far_first": GS_ORDER_FAR_FIRST}
 STATUS_NAMES = {0: "GS_OK", -1: "GS_EINVAL", -2: "GS_ENOMEM", -3: "GS_EDEVICE",
                 -4: "GS_EOVERFLOW", -5: "GS_EINTERNAL"}
 
@@ -47,7 +49,7 @@ class GsOptions(ctypes.Structure):
                 ("eps_round_share", ctypes.c_double), ("max_frontier", ctypes.c_int64),
                 ("log_explore", ctypes.c_double), ("autotune", ctypes.c_int32),
                 ("node_bounds", ctypes.c_int32), ("debug_fail_alloc", ctypes.c_int32),
-                ("log_path", ctypes.c_char_p)]
+                ("log_path", ctypes.c_char_p), ("pair_order", ctypes.c_int32)]
 
 
 class GsCostModel(ctypes.Structure):

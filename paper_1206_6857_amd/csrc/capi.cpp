@@ -553,8 +553,8 @@ static std::string autotune_key(const gs_options& o, int D, bool mono, int64_t M
     hmax = std::max(hmax, h);
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d/%d/%ld/%ld/%zu/%ld/%ld/%ld", o.method, o.policy,
-                o.plimit, o.fmm_mask, o.node_bounds, D, mono ? 1 : 0, std::lround(2.0 * std::log2((double)M)),
+  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%d/%d/%d/%d/%ld/%ld/%zu/%ld/%ld/%ld", o.method, o.policy,
+                o.plimit, o.fmm_mask, o.node_bounds, o.pair_order, D, mono ? 1 : 0, std::lround(2.0 * std::log2((double)M)),
                 std::lround(2.0 * std::log2((double)N)), hs.size(), std::lround(4.0 * std::log10(hmin)),
                 std::lround(4.0 * std::log10(hmax)), std::lround(8.0 * std::log10(eps)));
   return buf;
@@ -591,6 +591,8 @@ gs_status gauss_sum(gs_ctx* ctx, const double* queries, int64_t M, const double*
   if (opt.node_bounds != GS_BOUNDS_BOX && opt.node_bounds != GS_BOUNDS_SPHERE_RECT)
     GS_FAIL(ctx, GS_EINVAL, "node_bounds must be GS_BOUNDS_BOX or GS_BOUNDS_SPHERE_RECT");
   if (opt.max_frontier < 0) GS_FAIL(ctx, GS_EINVAL, "max_frontier must be >= 0");
+  if (opt.pair_order != GS_ORDER_TREE && opt.pair_order != GS_ORDER_FAR_FIRST)
+    GS_FAIL(ctx, GS_EINVAL, "pair_order must be GS_ORDER_TREE or GS_ORDER_FAR_FIRST");
   if (opt.debug_fail_alloc < 0) GS_FAIL(ctx, GS_EINVAL, "debug_fail_alloc must be >= 0");
   if (!(opt.eps_round_share >= 0.0 && opt.eps_round_share < 1.0))
     GS_FAIL(ctx, GS_EINVAL, "eps_round_share must be in [0, 1)");

@@ -763,7 +763,14 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       float* pfeat = nullptr;
       int16_t* pfeas = nullptr;
       const size_t tb = scan_counts_temp_bytes((int)nseg);
+      double* ff_d2 = nullptr;
+      int32_t* ff_R = nullptr;
+      const bool far_first = opt.pair_order == GS_ORDER_FAR_FIRST && level > 0;
       CHUNK_ALLOC(([&]() -> gs_status {
+        if (far_first) {
+          ff_d2 = BUF(double, "ff_d2", npair);
+          ff_R = BUF(int32_t, "ff_R", npair);
+        }
         code = BUF(int8_t, "p_code", npair);
         pord = BUF(int8_t, "p_ord", npair);
         cnt = BUF(SegCount, "seg_cnt", nseg);
@@ -780,6 +787,8 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       const PolicyPairs pp{cur.h, cur.Q, cur.seg, cur.R, d_hs, d_invh};
       {
         KernelTimer kt(ctx, ctx->kernel_timing, GS_K_DECIDE, st);
+        // best-first walk of each query node's list (option pair_order)
+        if (far_first) DT_HIP(launch_far_first_order((int)npair, cur, qtv, rtv, D, dc.node_bounds, ff_d2, ff_R, st));
         if (use_policy) DT_HIP(launch_policy_infer_pairs((int)npair, pp, pqt, prt, D, pmodel, scores, st));
         if (log_pairs) DT_HIP(launch_policy_features((int)npair, pp, pqt, prt, D, pfeat, st));
         DT_HIP(launch_decide((int)nseg, (int)nfirst, cur, qtv, rtv, d_inv2h2, d_inv4h2, d_invh, nQ, dc, code, pord,

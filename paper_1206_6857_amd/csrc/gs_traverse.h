@@ -99,6 +99,11 @@ struct LevelOffsets {
 // n_first: entries of cur.first (every segment of at least kLongSegment pairs).
 // prep: scratch of 5 * npair doubles (the pair prepass), npair: the level's
 // pairs.
+// Reorders every segment's pairs of the level in place (cur.R) by decreasing
+// dmin^2, ties by increasing R; d2 and r_tmp are npair scratch elements.
+hipError_t launch_far_first_order(int npair, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
+                                  int D, int node_bounds, double* d2, int32_t* r_tmp, hipStream_t s);
+
 hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
                          const double* inv2h2, const double* inv4h2, const double* invh, int nQ,
                          const DecideConst& c, int8_t* code, int8_t* porder, double* Gest,

@@ -201,16 +201,10 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 // the pair that involve its nodes' boxes, in the same arithmetic as the walk
 // would form them.  prep is [5][npair]: W_R K(dmax), K(dmin), K(dmax),
 // exp(-dmin^2 / 4h^2) (the bounds' Gaussian factor), W_R.
-__global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel cur, TreeView qt,
-                                                        TreeView rt, const double* __restrict__ inv2h2,
-                                                        const double* __restrict__ inv4h2, int D,
-                                                        int node_bounds, double* __restrict__ prep) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npair) return;
-  const int sg = cur.seg[i];
-  const int h = cur.h[sg];
-  const int Q = cur.Q[sg];
-  const int R = cur.R[i];
+// Squared-distance bounds of the node pair (Q, R): the box bounds, or with
+// node_bounds the tighter of those and the bounding-ball bounds.
+__device__ __forceinline__ void pair_bounds(int Q, int R, const TreeView& qt, const TreeView& rt, int D,
+                                            int node_bounds, double* dmin2_out, double* dmax2_out) {
   double dmin2, dmax2;
   box_dist2(qt.lo + (int64_t)Q * D, qt.hi + (int64_t)Q * D, rt.lo + (int64_t)R * D,
             rt.hi + (int64_t)R * D, D, &dmin2, &dmax2);
@@ -235,6 +229,22 @@ __global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel
     const double f2 = far * far;
     if (f2 < dmax2) dmax2 = f2;
   }
+  *dmin2_out = dmin2;
+  *dmax2_out = dmax2;
+}
+
+__global__ __launch_bounds__(256) void pair_prep_kernel(int npair, FrontierLevel cur, TreeView qt,
+                                                        TreeView rt, const double* __restrict__ inv2h2,
+                                                        const double* __restrict__ inv4h2, int D,
+                                                        int node_bounds, double* __restrict__ prep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npair) return;
+  const int sg = cur.seg[i];
+  const int h = cur.h[sg];
+  const int Q = cur.Q[sg];
+  const int R = cur.R[i];
+  double dmin2, dmax2;
+  pair_bounds(Q, R, qt, rt, D, node_bounds, &dmin2, &dmax2);
   const double i2 = inv2h2[h];
   const double kmax = own_exp(-dmax2 * i2);
   const double kmin = own_exp(-dmin2 * i2);
@@ -861,6 +871,49 @@ hipError_t launch_decision_arith(const double* x, const double* y, int64_t n, do
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(decision_arith_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, out);
   return hipGetLastError();
+}
+
+// Far-first order of each segment (a best-first walk of a query node's
+// reference list): decreasing dmin^2, ties by increasing R.  Pair i's
+// position is the number of pairs of its segment that precede it in that
+// order (every R occurs once per segment, so positions are a permutation).
+__global__ __launch_bounds__(256) void far_first_key_kernel(int npair, FrontierLevel cur, TreeView qt,
+                                                            TreeView rt, int D, int node_bounds,
+                                                            double* __restrict__ d2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npair) return;
+  double dmin2, dmax2;
+  pair_bounds(cur.Q[cur.seg[i]], cur.R[i], qt, rt, D, node_bounds, &dmin2, &dmax2);
+  d2[i] = dmin2;
+}
+
+__global__ __launch_bounds__(256) void far_first_place_kernel(int npair, FrontierLevel cur,
+                                                              const double* __restrict__ d2,
+                                                              int32_t* __restrict__ r_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npair) return;
+  const int sg = cur.seg[i];
+  const int o = cur.off[sg], n = cur.len[sg];
+  const double di = d2[i];
+  const int Ri = cur.R[i];
+  int rank = 0;
+  for (int j = o; j < o + n; ++j) {
+    const double dj = d2[j];
+    const int Rj = cur.R[j];
+    rank += (dj > di || (dj == di && Rj < Ri)) ? 1 : 0;
+  }
+  r_out[o + rank] = Ri;
+}
+
+hipError_t launch_far_first_order(int npair, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,
+                                  int D, int node_bounds, double* d2, int32_t* r_tmp, hipStream_t s) {
+  if (npair <= 0) return hipSuccess;
+  const dim3 grid((unsigned)ceil_div(npair, 256));
+  hipLaunchKernelGGL(far_first_key_kernel, grid, dim3(256), 0, s, npair, cur, qt, rt, D, node_bounds, d2);
+  hipLaunchKernelGGL(far_first_place_kernel, grid, dim3(256), 0, s, npair, cur, d2, r_tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(cur.R, r_tmp, sizeof(int32_t) * npair, hipMemcpyDeviceToDevice, s);
 }
 
 hipError_t launch_decide(int S, int n_first, const FrontierLevel& cur, const TreeView& qt, const TreeView& rt,

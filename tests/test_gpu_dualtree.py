@@ -173,6 +173,47 @@ def test_dualtree_sphere_rect_parity(case):
     assert (np.abs(G - exact) / exact).max() <= 0.01
 
 
+FAR_FIRST_CASES = [
+    # (name, D, N, M, hs, leaf, method, node_bounds)
+    ("d2", 2, 1500, None, [1e-3, 0.01, 0.05, 0.2, 1.0], 32, "dito", "box"),
+    ("d3", 3, 1500, None, [1e-3, 0.01, 0.05, 0.2, 1.0], 32, "dito", "box"),
+    ("d3_bi_leaf64", 3, 1300, 600, [0.02, 0.1, 0.5], 64, "dito", "box"),
+    ("d5", 5, 1000, None, [0.01, 0.1, 0.5, 3.0], 32, "dito", "box"),
+    ("d3_dfto", 3, 1500, None, [1e-3, 1e-2, 0.05, 0.2, 1.0], 32, "dfto", "box"),
+    ("d3_dfdo", 3, 1200, None, [1e-2, 0.1, 1.0], 32, "dfdo", "box"),
+    ("d2_sphere_rect", 2, 1500, None, [0.01, 0.05, 0.2, 1.0], 32, "dito", "sphere_rect"),
+]
+
+
+@pytest.mark.parametrize("case", FAR_FIRST_CASES, ids=[c[0] for c in FAR_FIRST_CASES])
+def test_dualtree_far_first_parity(case):
+    """The best-first walk (pair_order="far_first": every query node's list in
+    decreasing dmin^2, ties by reference node, at every level): the decision
+    trace bit-exact with the oracle's run in the same order, values within
+    rounding of it, Theorem 2; and the order does change decisions."""
+    name, D, N, M, hs, leaf, method, nb = case
+    banner("dualtree far_first", name)
+    r, w, q = _inputs(D, N, M, 110 + D)
+    hs = np.array(hs)
+    c = ctx()
+    G = c.gauss_sum(q, r, w, hs, 0.01, leaf_size=leaf, keep_trace=1, method=method, node_bounds=nb,
+                    pair_order="far_first")
+    ref = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, trace=True, method=method, node_bounds=nb,
+                      pair_order="far_first")
+    got = c.get_trace().astype(np.int64)
+    want = np.array(ref.trace, dtype=np.int64).reshape(-1, 6)
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    assert got.shape == want.shape, (got.shape, want.shape)
+    assert np.array_equal(key(got), key(want))
+    assert np.array_equal(c.pair_counts(len(hs)), ref.counts)
+    exact = gauss_sum_exhaustive(q, r, w, hs)
+    assert (np.abs(G - ref.G) / exact).max() <= TOL_ROUND
+    assert (np.abs(G - exact) / exact).max() <= 0.01
+    tree = DT.dualtree(q, r, w, hs, 0.01, leaf_size=leaf, method=method, node_bounds=nb)
+    if method != "dfd":
+        assert not np.array_equal(tree.counts, ref.counts)
+
+
 def test_dualtree_torch_device_and_repeat():
     import torch
     banner("dualtree torch repeat")
