@@ -331,8 +331,9 @@ def main():
                                 "flops": flops / n_base},
             "issue_model": {"peak_tflops": issue_peak, "frac": achieved / issue_peak,
                             "note": "non-packed FP32 issue (3.93e13 lane-slots/s) at this kernel's "
-                                    "mix: 2D slots per distance formed on the VALU (MFMA distances: "
-                                    "none), 2 + %g per kernel evaluation" % EXP_SLOTS}}
+                                    "mix: 2D slots per distance formed on the VALU (none for the "
+                                    "distances the MFMA path forms), 2 + %g per kernel evaluation"
+                                    % EXP_SLOTS}}
 
     # ---- the plain GPU exhaustive path on the same sets (one step: ~20 s per set)
     if not args.no_exhaustive:

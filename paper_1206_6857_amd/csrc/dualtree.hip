@@ -969,7 +969,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.n_entries = ne;
       ba.n_qnodes = nQ;
       ba.n_rnodes = nR;
-      ba.n_hblocks = (n_h + 7) / 8;
+      ba.n_hblocks = (n_h + kBaseHB - 1) / kBaseHB;
       ba.hc0 = hc0;
       ba.hc1 = hc1;
       ba.qt = qv;
@@ -991,9 +991,9 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.key = BUF(unsigned long long, "bf_key", ne);
       ba.key_sorted = BUF(unsigned long long, "bf_skey", ne);
       ba.ukey = BUF(unsigned long long, "bf_ukey", ne);
-      ba.bit = BUF(uint8_t, "bf_bit", ne);
-      ba.bit_sorted = BUF(uint8_t, "bf_sbit", ne);
-      ba.umask = BUF(uint8_t, "bf_umask", ne);
+      ba.bit = BUF(BaseMask, "bf_bit", ne);
+      ba.bit_sorted = BUF(BaseMask, "bf_sbit", ne);
+      ba.umask = BUF(BaseMask, "bf_umask", ne);
       ba.flag = BUF(int32_t, "bf_flag", ne);
       ba.pos = BUF(int32_t, "bf_pos", ne);
       ba.mflag = BUF(int32_t, "bf_mflag", ne);
@@ -1002,7 +1002,7 @@ gs_status run_dualtree(gs_ctx_base* ctx, const DeviceInputs& in, const std::vect
       ba.slices = BUF(int4, "bf_slices", base_max_slices(ne));
       const int nslots = base_partial_slots(opt.leaf_size);
       ba.slots = BUF(int4, "bf_slots", nslots);
-      ba.partial = BUF(double, "bf_partial", (int64_t)nslots * 8 * ceil_div(opt.leaf_size, 64) * 64);
+      ba.partial = BUF(double, "bf_partial", base_partial_doubles(opt.leaf_size));
       ba.counters = BUF(int32_t, "bf_counters", 8);
       {
         hipError_t pe = hipSuccess;

@@ -117,7 +117,11 @@ hipError_t launch_leaf_post_fast(int D, int P, bool tensor, const NodeView& qt, 
                                  const double* Gest, const double* lco, const int32_t* pL,
                                  double* G_out, hipStream_t s);
 
-// Base cases (DITOBase), fused over blocks of 8 bandwidths.
+// Base cases (DITOBase), fused over blocks of kBaseHB bandwidths: a base
+// entry is (Q, R, block) with the block's bandwidths that chose the base case
+// in a kBaseHB-bit mask, so that one squared distance serves all of them.
+constexpr int kBaseHB = 16;
+typedef uint16_t BaseMask;
 int base_record_stride(int D);
 
 // Reference records for the base tiles: per leaf, its points' float
@@ -177,11 +181,11 @@ struct BaseFusedArgs {
   unsigned long long* dist_evals = nullptr;  // += point pairs of the regrouped entries
   // scratch: n_entries elements each (run_start n_entries + 1)
   unsigned long long *key = nullptr, *key_sorted = nullptr, *ukey = nullptr;
-  uint8_t *bit = nullptr, *bit_sorted = nullptr, *umask = nullptr;
+  BaseMask *bit = nullptr, *bit_sorted = nullptr, *umask = nullptr;
   int32_t *flag = nullptr, *pos = nullptr, *mflag = nullptr, *mpos = nullptr, *run_start = nullptr;
   int4* slices = nullptr;    // base_max_slices(n_entries)
   int4* slots = nullptr;     // base_partial_slots(max_leaf)
-  double* partial = nullptr; // base_partial_slots(max_leaf) * 8 * round_up(max_leaf, 64)
+  double* partial = nullptr; // base_partial_doubles(max_leaf)
   int32_t* counters = nullptr;  // 8: unique entries, runs, slices, partial slots used, slice queue
   int32_t* host_counters = nullptr;  // 4, page-locked host memory: the plan's readbacks
   void* temp = nullptr;
@@ -195,6 +199,8 @@ struct BaseFusedPlan {
 size_t base_fused_temp_bytes(int64_t n_entries);
 int64_t base_max_slices(int64_t n_entries);
 int base_partial_slots(int max_leaf);
+// doubles of the partial-sum array: slots * kBaseHB * round_up(max_leaf, 64)
+int64_t base_partial_doubles(int max_leaf);
 // Regroups the entries into runs and slices (synchronises the stream twice).
 hipError_t plan_base_fused(const BaseFusedArgs& a, BaseFusedPlan* p, hipStream_t s);
 hipError_t launch_base_fused(const BaseFusedArgs& a, const BaseFusedPlan& p, hipStream_t s);

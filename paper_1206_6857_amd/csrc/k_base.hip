@@ -5,9 +5,12 @@
 //
 // The traversal records base pairs per (h, Q).  The same leaf pair is usually
 // a base case for several neighbouring bandwidths, and |x_q - x_r|^2 does not
-// depend on h, so the entries are regrouped by (Q, block of 8 bandwidths, R)
-// with an 8-bit mask of the block's bandwidths that need the pair: a radix sort
-// of (Q, block, R) keys, then an OR reduction by key.  A run is the set of
+// depend on h, so the entries are regrouped by (Q, block of 16 bandwidths, R)
+// with a 16-bit mask of the block's bandwidths that need the pair: a radix
+// sort of (Q, block, R) keys, then an OR reduction by key.  (On mixtures of
+// 10^6 points with 64 log-spaced bandwidths a leaf pair is a base case for
+// 11 of a block's 16 bandwidths on average at D = 8, 8.7 at D = 5, against
+// 6.9 and 5.9 of 8 with blocks of 8.)  A run is the set of
 // regrouped entries of one (Q, block); runs are cut into slices of at most S
 // entries, S chosen so that there are many more slices than SIMDs (the runs of
 // dense clusters hold hundreds of entries, the others a few).
@@ -49,7 +52,7 @@ namespace gs {
 namespace {
 
 constexpr int kW = 64;
-constexpr int kHB = 8;   // bandwidths per block
+constexpr int kHB = kBaseHB;  // bandwidths per block
 constexpr int kPad = 4;  // records per leaf are padded to a multiple of this
 constexpr int kResidentWaves = 4 * 4 * 256;  // base_fused_kernel: 4 waves per SIMD
 constexpr int kBaseWaves = 4;                 // waves per workgroup of base_fused_kernel
@@ -160,16 +163,16 @@ __global__ void base_records_kernel(const double* __restrict__ xr, const double*
   for (int k = D + 1; k < rs; ++k) o[k] = 0.0f;
 }
 
-// One workgroup per base group {h, Q, first, n}: key (Q, h / 8, R), bit h % 8.
+// One workgroup per base group {h, Q, first, n}: key (Q, h / kHB, R), bit h % kHB.
 __global__ void fuse_keys_kernel(const int4* __restrict__ grp, int ng, const int32_t* __restrict__ ent,
                                  int rbits, int hbits, unsigned long long* __restrict__ key,
-                                 uint8_t* __restrict__ bit) {
+                                 BaseMask* __restrict__ bit) {
   const int gi = blockIdx.x;
   if (gi >= ng) return;
   const int4 g = grp[gi];
   const unsigned long long hb = (unsigned long long)(g.x / kHB);
   const unsigned long long hi = ((unsigned long long)g.y << (hbits + rbits)) | (hb << rbits);
-  const uint8_t b = (uint8_t)(1u << (g.x % kHB));
+  const BaseMask b = (BaseMask)(1u << (g.x % kHB));
   for (int e = threadIdx.x; e < g.w; e += blockDim.x) {
     key[g.z + e] = hi | (unsigned long long)(ent[g.z + e] >> 4);
     bit[g.z + e] = b;
@@ -177,7 +180,7 @@ __global__ void fuse_keys_kernel(const int4* __restrict__ grp, int ng, const int
 }
 
 struct BitOr {
-  __device__ __host__ uint8_t operator()(uint8_t a, uint8_t b) const { return (uint8_t)(a | b); }
+  __device__ __host__ BaseMask operator()(BaseMask a, BaseMask b) const { return (BaseMask)(a | b); }
 };
 
 // Run heads (first entry of each (Q, block)) and the number of point pairs
@@ -262,7 +265,7 @@ __global__ void slices_kernel(const int32_t* __restrict__ run_start, const int32
 // the queue runs dry are light ones.
 __global__ void slice_cost_kernel(const int4* __restrict__ slices, int n_slices,
                                   const unsigned long long* __restrict__ ukey,
-                                  const uint8_t* __restrict__ umask, int rbits, const int32_t* __restrict__ rcount,
+                                  const BaseMask* __restrict__ umask, int rbits, const int32_t* __restrict__ rcount,
                                   int D, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_slices) return;
@@ -282,13 +285,15 @@ __global__ void slice_cost_kernel(const int4* __restrict__ slices, int n_slices,
 typedef float f16v __attribute__((ext_vector_type(16), aligned(16)));
 
 // Sweep of one reference leaf for NA bandwidths: for every record r,
-//   part[j] += w_r exp2(shiftc[j] - |u_q - u_r|^2 shc[j]),  j < NA.
+//   part[j] += w_r exp2(-(|u_q - u_r|^2 - t2) shc[j]),  j < NA,
+// with t2 the lane's shift in squared-distance units (the sum is scaled by
+// 2^(t2 shc[j]), which the caller takes out exactly in double).
 // p: the leaf's padded records, nb batches of BR records of RS floats; a
 // batch is read as whole 16-float vectors (up to 15 floats past the batch,
 // inside the record array's tail).
 template <int D, int NA, int RS, int BR>
 __device__ __forceinline__ void sweep(const float* __restrict__ p, int nb, const float* uq,
-                                      const float* shc, const float* shiftc, float* part) {
+                                      const float* shc, float t2, float* part) {
   constexpr int NF = RS * BR;
   constexpr int NV = (NF + 15) / 16;
   for (int b = 0; b < nb; ++b, p += NF) {
@@ -304,9 +309,9 @@ __device__ __forceinline__ void sweep(const float* __restrict__ p, int nb, const
         d2 = fmaf(dd, dd, d2);
       }
       const float wr = v[(j * RS + D) / 16][(j * RS + D) % 16];
+      const float e = d2 - t2;
 #pragma unroll
-      for (int a = 0; a < NA; ++a)
-        part[a] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[a], shiftc[a])), part[a]);
+      for (int a = 0; a < NA; ++a) part[a] = fmaf(wr, __builtin_amdgcn_exp2f(-e * shc[a]), part[a]);
     }
   }
 }
@@ -339,8 +344,7 @@ __device__ __forceinline__ float sweep_min(const float* __restrict__ p, int nb, 
 // Any D: one record at a time.
 template <int NA>
 __device__ __forceinline__ void sweep_any(const float* __restrict__ p, int n, int D, int rs,
-                                          const float* uq, const float* shc, const float* shiftc,
-                                          float* part) {
+                                          const float* uq, const float* shc, float t2, float* part) {
   for (int r = 0; r < n; ++r, p += rs) {
     float d2 = 0.0f;
     for (int d = 0; d < D; ++d) {
@@ -348,9 +352,9 @@ __device__ __forceinline__ void sweep_any(const float* __restrict__ p, int n, in
       d2 = fmaf(dd, dd, d2);
     }
     const float wr = p[D];
+    const float e = d2 - t2;
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
-      part[a] = fmaf(wr, __builtin_amdgcn_exp2f(fmaf(-d2, shc[a], shiftc[a])), part[a]);
+    for (int a = 0; a < NA; ++a) part[a] = fmaf(wr, __builtin_amdgcn_exp2f(-e * shc[a]), part[a]);
   }
 }
 
@@ -382,115 +386,132 @@ __device__ __forceinline__ float sweep_leaf_min(const float* __restrict__ rec, i
 
 template <int DT, int NA>
 __device__ __forceinline__ void sweep_leaf(const float* __restrict__ rec, int rs, int D, int rn_padded,
-                                           const float* uq, const float* shc, const float* shiftc,
-                                           float* part) {
+                                           const float* uq, const float* shc, float t2, float* part) {
   if constexpr (DT > 0) {
     constexpr int RS = (DT + 4) / 4 * 4;
     constexpr int BR = RS == 4 ? 4 : RS == 8 ? 2 : 1;
-    sweep<DT, NA, RS, BR>(rec, rn_padded / BR, uq, shc, shiftc, part);
+    sweep<DT, NA, RS, BR>(rec, rn_padded / BR, uq, shc, t2, part);
   } else {
-    sweep_any<NA>(rec, rn_padded, D, rs, uq, shc, shiftc, part);
+    sweep_any<NA>(rec, rn_padded, D, rs, uq, shc, t2, part);
   }
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Sweep of one reference leaf with squared distances from the MFMA norm
-// expansion, for NA bandwidths and the wave's 64 queries in two halves of 32:
-// in half s, lane l takes query (l % 32) + 32 s and the references of rows
-// 8 j + 4 (l / 32) + i (j, i < 4) of each 32-reference group, for which one
-// v_mfma_f32_32x32x2f32 per pair of augmented coordinates leaves
-// |u_q - u_r|^2 - T_q in its 16 accumulator registers (A: the group's records
-// (-2 u_r, 1, |u_r|^2), B: the queries' (u_q, |u_q|^2 - T_q, 1), with T_q the
-// query's squared distance to the leaf's box, so that every exponent
-// -s_h (|u_q - u_r|^2 - T_q) is <= 0 up to rounding).  Both halves use each
-// group's records while they are in registers; at the end the two lanes of a
-// query add their partial sums and the query's own lane keeps them.
+// expansion, for NA bandwidths and the wave's 64 queries in two halves of 32,
+// one half after the other: in half s, lane l takes query (l % 32) + 32 s and
+// the references of rows 8 j + 4 (l / 32) + i (j, i < 4) of each 32-reference
+// group, for which one v_mfma_f32_32x32x2f32 per pair of augmented
+// coordinates leaves |u_q - u_r|^2 - T_q in its 16 accumulator registers (A:
+// the group's records (-2 u_r, 1, |u_r|^2), B: the queries' (u_q,
+// |u_q|^2 - T_q, 1), with T_q the query's squared distance to the leaf's box,
+// so that every exponent -s_h (|u_q - u_r|^2 - T_q) is <= 0 up to rounding).
+// At the end of a half the two lanes of a query add their partial sums; a
+// bandwidth whose sum is below 2^-60 for any of the half's queries is left to
+// the rescue (bit j of the returned mask, shifted by 16 for the second half),
+// and the query's own lane adds the others to its accumulators acc[k * 64]
+// (k: the block index of the j-th bandwidth of `bits`), unscaled by
+// 2^(T_q s_h) in double.  Only one half's NA sums are live at a time (the
+// group's records are read again for the second half, from cache).
 template <int D, int NA>
-__device__ __forceinline__ void mfma_sweep(const float* __restrict__ mg, int ngroups, int nsub, const float* uq,
-                                           float nqt, const float* shc, float* part) {
+__device__ __forceinline__ unsigned mfma_sweep(const float* __restrict__ mg, int ngroups, int nsub,
+                                               const float* uq, float nqt, const float* shc, unsigned bits,
+                                               double* acc, float tq, int qrem) {
   constexpr int K2 = mfma_k2(D), KM = K2 / 2, GF = mfma_group_floats(D);
   const int lane = threadIdx.x & (kW - 1);
   const int half = lane >> 5;
-  float bq[2][KM], p[2][NA];
+  float v[K2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
+  for (int k = 0; k < K2; ++k) v[k] = k < D ? uq[k < D ? k : 0] : k == D ? nqt : k == D + 1 ? 1.0f : 0.0f;
+  unsigned lows = 0;
+  for (int s = 0; s < nsub; ++s) {
     const int src = (lane & 31) + 32 * s;
+    float bq[KM];
 #pragma unroll
     for (int m = 0; m < KM; ++m) {
-      const int k0 = 2 * m, k1 = 2 * m + 1;
-      const float v0 = k0 < D ? uq[k0 < D ? k0 : 0] : k0 == D ? nqt : k0 == D + 1 ? 1.0f : 0.0f;
-      const float v1 = k1 < D ? uq[k1 < D ? k1 : 0] : k1 == D ? nqt : k1 == D + 1 ? 1.0f : 0.0f;
-      const float e0 = __shfl(v0, src, kW);
-      const float e1 = __shfl(v1, src, kW);
-      bq[s][m] = half ? e1 : e0;
+      const float e0 = __shfl(v[2 * m], src, kW);
+      const float e1 = __shfl(v[2 * m + 1], src, kW);
+      bq[m] = half ? e1 : e0;
     }
+    float p[NA];
 #pragma unroll
-    for (int j = 0; j < NA; ++j) p[s][j] = 0.0f;
-  }
-  const float* g = mg;
-  for (int gi = 0; gi < ngroups; ++gi, g += GF) {
-    float a[KM];
+    for (int j = 0; j < NA; ++j) p[j] = 0.0f;
+    const float* g = mg;
+    for (int gi = 0; gi < ngroups; ++gi, g += GF) {
+      float a[KM];
 #pragma unroll
-    for (int m = 0; m < KM; ++m) a[m] = g[m * 64 + lane];
-    float4 w4[4];
+      for (int m = 0; m < KM; ++m) a[m] = g[m * 64 + lane];
+      float4 w4[4];
 #pragma unroll
-    for (int j4 = 0; j4 < 4; ++j4) w4[j4] = *reinterpret_cast<const float4*>(g + kMG * K2 + 8 * j4 + 4 * half);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {  // unrolled: s is a constant in each copy
-      if (s >= nsub) break;
+      for (int j4 = 0; j4 < 4; ++j4)
+        w4[j4] = *reinterpret_cast<const float4*>(g + kMG * K2 + 8 * j4 + 4 * half);
       f32x16 c = {};
 #pragma unroll
-      for (int m = 0; m < KM; ++m) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m], bq[s][m], c, 0, 0, 0);
+      for (int m = 0; m < KM; ++m) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m], bq[m], c, 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const float wr = w4[i / 4][i % 4];
 #pragma unroll
-        for (int j = 0; j < NA; ++j) p[s][j] = fmaf(wr, __builtin_amdgcn_exp2f(-c[i] * shc[j]), p[s][j]);
+        for (int j = 0; j < NA; ++j) p[j] = fmaf(wr, __builtin_amdgcn_exp2f(-c[i] * shc[j]), p[j]);
       }
     }
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
+    unsigned lo = 0;
+    const bool act = (lane & 31) + 32 * s < qrem;  // the half's query of this lane exists
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const float v = p[s][j] + __shfl_xor(p[s][j], 32, kW);
-      if (half == s) part[j] = v;
+      p[j] += __shfl_xor(p[j], 32, kW);
+      if (__any(act && p[j] < 0x1p-60f)) lo |= 1u << j;
     }
+    if (half == s) {
+      unsigned mm = bits;
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        const int k = __builtin_ctz(mm);
+        mm &= mm - 1;
+        if ((lo >> j) & 1u) continue;
+        const double sc = (double)tq * (double)shc[j];
+        const double fi = floor(sc);
+        acc[k * kW] += ldexp((double)(p[j] * __builtin_amdgcn_exp2f((float)(fi - sc))), -(int)fi);
+      }
+    }
+    lows |= lo << (16 * s);
+  }
+  return lows;
 }
 
-template <int DT>
-__device__ __forceinline__ void mfma_sweep_leaf(int na, const float* __restrict__ mg, int ngroups, int nsub,
-                                                const float* uq, float nqt, const float* shc, float* part) {
-  switch (na) {
-    case 1: mfma_sweep<DT, 1>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 2: mfma_sweep<DT, 2>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 3: mfma_sweep<DT, 3>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 4: mfma_sweep<DT, 4>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 5: mfma_sweep<DT, 5>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 6: mfma_sweep<DT, 6>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    case 7: mfma_sweep<DT, 7>(mg, ngroups, nsub, uq, nqt, shc, part); break;
-    default: mfma_sweep<DT, 8>(mg, ngroups, nsub, uq, nqt, shc, part); break;
+// The NA = 1..kHB specialisations: each spends exactly one exp2 per needed
+// (point pair, bandwidth).
+#define GS_NA_CASES(F)                                                                              \
+  switch (na) {                                                                                     \
+    case 1: F(1); break;   case 2: F(2); break;   case 3: F(3); break;   case 4: F(4); break;       \
+    case 5: F(5); break;   case 6: F(6); break;   case 7: F(7); break;   case 8: F(8); break;       \
+    case 9: F(9); break;   case 10: F(10); break; case 11: F(11); break; case 12: F(12); break;     \
+    case 13: F(13); break; case 14: F(14); break; case 15: F(15); break; default: F(16); break;      \
   }
+static_assert(kHB == 16, "GS_NA_CASES lists kHB cases");
+
+template <int DT>
+__device__ __forceinline__ unsigned mfma_sweep_leaf(int na, const float* __restrict__ mg, int ngroups, int nsub,
+                                                    const float* uq, float nqt, const float* shc, unsigned bits,
+                                                    double* acc, float tq, int qrem) {
+  unsigned lows = 0;
+#define GS_MFMA_CASE(NA) lows = mfma_sweep<DT, NA>(mg, ngroups, nsub, uq, nqt, shc, bits, acc, tq, qrem)
+  GS_NA_CASES(GS_MFMA_CASE)
+#undef GS_MFMA_CASE
+  return lows;
 }
 
 template <int DT>
 __device__ __forceinline__ void sweep_leaf_na(int na, const float* __restrict__ rp, int rs, int D, int rnp,
-                                              const float* uq, const float* shc, const float* shiftc, float* part) {
-  switch (na) {
-    case 1: sweep_leaf<DT, 1>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 2: sweep_leaf<DT, 2>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 3: sweep_leaf<DT, 3>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 4: sweep_leaf<DT, 4>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 5: sweep_leaf<DT, 5>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 6: sweep_leaf<DT, 6>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    case 7: sweep_leaf<DT, 7>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-    default: sweep_leaf<DT, 8>(rp, rs, D, rnp, uq, shc, shiftc, part); break;
-  }
+                                              const float* uq, const float* shc, float t2, float* part) {
+#define GS_SWEEP_CASE(NA) sweep_leaf<DT, NA>(rp, rs, D, rnp, uq, shc, t2, part)
+  GS_NA_CASES(GS_SWEEP_CASE)
+#undef GS_SWEEP_CASE
 }
 
-// Persistent waves (six per SIMD: four already keep the VALU busy; the
-// register budget allows eight) take work units from a queue counter until
+// Persistent waves (four per SIMD: the MFMA sweeps use up to 128 registers,
+// and four already keep the VALU busy) take work units from a queue counter until
 // none is left, heaviest slices first (slice_cost_kernel): unit u is query batch
 // u % QB (64 queries) of slice u / QB, QB = qmax / 64.  There are several
 // units per wave, so a SIMD whose units were light takes more of them and
@@ -509,7 +530,7 @@ template <int DT>
 __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu(4))) void base_fused_kernel(
     const int4* __restrict__ slices, const int32_t* __restrict__ order, int n_slices,
     const int32_t* __restrict__ run_start, const unsigned long long* __restrict__ ukey,
-    const uint8_t* __restrict__ umask, int rbits, int hbits, int hc0, int hc1, NodeView qt, NodeView rt,
+    const BaseMask* __restrict__ umask, int rbits, int hbits, int hc0, int hc1, NodeView qt, NodeView rt,
     const int32_t* __restrict__ rec_off, const double* __restrict__ xq_perm, const float* __restrict__ rec,
     const int32_t* __restrict__ mgrp_off, const float* __restrict__ mrec, const float* __restrict__ rmax2,
     int Drt, int rs_rt, const float* __restrict__ s2, const unsigned long long* __restrict__ wmax_bits,
@@ -608,10 +629,9 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
         const unsigned bits = sub == 0 ? safe : (m & ~safe);
         if (bits == 0) continue;
         const bool use_mfma = sub == 0;
-        // Compact the subset's bandwidths: j-th set bit -> shc[j] (uniform),
-        // shiftc[j] = the lane's underflow shift for it.
+        // Compact the subset's bandwidths: j-th set bit -> shc[j] (uniform).
         const int na = __builtin_popcount(bits);
-        float shc[kHB], shiftc[kHB], part[kHB];
+        float shc[kHB], part[kHB];
         {
           unsigned mm = bits;
 #pragma unroll
@@ -619,17 +639,17 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
             const int k = mm ? __builtin_ctz(mm) : 0;
             mm &= mm - 1;
             shc[j] = s2[h0 + k];
-            shiftc[j] = (float)box2 * shc[j];
             part[j] = 0.0f;
           }
         }
         if (use_mfma) mfma_pairs += (unsigned long long)na * (unsigned long long)rt.count[R] *
                                     (unsigned long long)(qn - base < kW ? qn - base : kW);
         // Adds the sums of the subset's j-th bandwidths selected by jmask to
-        // the unit's accumulators, unscaled in double: the MFMA path's terms
-        // carry the factor 2^(T_q s_h) (formed exactly in double), the
-        // difference form's 2^shiftc.
-        auto accumulate = [&](unsigned jmask, bool mfma_scaled) {
+        // the unit's accumulators, unscaled in double: a sweep with shift t2
+        // (squared-distance units; T_q folded into the MFMA operands is the
+        // same shift) leaves its terms scaled by 2^(t2 s_h), and t2 s_h is
+        // formed exactly in double.
+        auto accumulate = [&](unsigned jmask, float t2) {
           unsigned mm = bits;
 #pragma unroll
           for (int j = 0; j < kHB; ++j) {
@@ -637,37 +657,42 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
             const int k = __builtin_ctz(mm);
             mm &= mm - 1;
             if (!((jmask >> j) & 1u)) continue;
-            const double sc = mfma_scaled ? (double)tq * (double)shc[j] : (double)shiftc[j];
+            const double sc = (double)t2 * (double)shc[j];
             const double fi = floor(sc);
             acc[k * kW] += ldexp((double)(part[j] * __builtin_amdgcn_exp2f((float)(fi - sc))), -(int)fi);
           }
         };
-        if (use_mfma) {
-          if constexpr (mfma_dim(DT))
-            mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
-                                (rt.count[R] + kMG - 1) / kMG, qn - base > kMG ? 2 : 1, uq, nq - tq, shc, part);
-        } else {
-          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, shiftc, part);
-        }
         // Rescue (file comment): a bandwidth whose sum is below 2^-60 on any
-        // active lane takes shifts from the lanes' smallest distances, and the
-        // wave sweeps the leaf again (difference form); the other bandwidths
-        // keep their first sweep, so a bandwidth's result does not depend on
-        // which other bandwidths share the entry.
-        unsigned low = 0;
-#pragma unroll
-        for (int j = 0; j < kHB; ++j)
-          if (j < na && __any(active && part[j] < 0x1p-60f)) low |= 1u << j;
-        accumulate(~low, use_mfma);
-        if (low != 0) {
+        // active lane (of a half, on the MFMA path) takes its shift from the
+        // lane's smallest distance, and the wave sweeps the leaf again
+        // (difference form); the other bandwidths keep their first sweep, so
+        // a bandwidth's result does not depend on which other bandwidths share
+        // the entry.
+        auto rescue = [&](unsigned lanelow) {
           const float m2 = sweep_leaf_min<DT>(rp, rs, D, rnp, uq);
+          const float t2 = fmaxf(tq, m2);
 #pragma unroll
-          for (int j = 0; j < kHB; ++j) {
-            if ((low >> j) & 1u) shiftc[j] = fmaxf(shiftc[j], m2 * shc[j]);
-            part[j] = 0.0f;
+          for (int j = 0; j < kHB; ++j) part[j] = 0.0f;
+          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, t2, part);
+          accumulate(lanelow, t2);
+        };
+        if (use_mfma) {
+          if constexpr (mfma_dim(DT)) {
+            const int qrem = qn - base;
+            const unsigned lows =
+                mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
+                                    (rt.count[R] + kMG - 1) / kMG, qrem > kMG ? 2 : 1, uq, nq - tq, shc, bits,
+                                    acc, tq, qrem);
+            if (lows != 0) rescue(lane >= 32 ? lows >> 16 : lows & 0xffffu);
           }
-          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, shiftc, part);
-          accumulate(low, false);
+        } else {
+          sweep_leaf_na<DT>(na, rp, rs, D, rnp, uq, shc, tq, part);
+          unsigned low = 0;
+#pragma unroll
+          for (int j = 0; j < kHB; ++j)
+            if (j < na && __any(active && part[j] < 0x1p-60f)) low |= 1u << j;
+          accumulate(~low, tq);
+          if (low != 0) rescue(low);
         }
       }
     }
@@ -794,11 +819,11 @@ hipError_t launch_base_records(const BaseRecordsArgs& a, hipStream_t s) {
 size_t base_fused_temp_bytes(int64_t n) {
   size_t b1 = 0, b2 = 0, b3 = 0;
   (void)rocprim::radix_sort_pairs((void*)nullptr, b1, (const unsigned long long*)nullptr,
-                                  (unsigned long long*)nullptr, (const uint8_t*)nullptr,
-                                  (uint8_t*)nullptr, (size_t)n, 0, 64);
+                                  (unsigned long long*)nullptr, (const BaseMask*)nullptr,
+                                  (BaseMask*)nullptr, (size_t)n, 0, 64);
   (void)rocprim::reduce_by_key((void*)nullptr, b2, (const unsigned long long*)nullptr,
-                               (const uint8_t*)nullptr, (size_t)n, (unsigned long long*)nullptr,
-                               (uint8_t*)nullptr, (int32_t*)nullptr, BitOr(),
+                               (const BaseMask*)nullptr, (size_t)n, (unsigned long long*)nullptr,
+                               (BaseMask*)nullptr, (int32_t*)nullptr, BitOr(),
                                rocprim::equal_to<unsigned long long>());
   (void)rocprim::exclusive_scan((void*)nullptr, b3, (const int32_t*)nullptr, (int32_t*)nullptr, 0,
                                 (size_t)n, rocprim::plus<int32_t>());
@@ -809,10 +834,15 @@ size_t base_fused_temp_bytes(int64_t n) {
 }
 
 // Partial-sum slots of one call: 4 * 16384 * 64 / qmax, so the partials take
-// 4 * 16384 * 64 * 8 doubles (256 MiB) whatever the leaf size.
+// 4 * 16384 * 64 * kHB doubles (512 MiB) whatever the leaf size.
 int base_partial_slots(int max_leaf) {
   const int qmax = (int)ceil_div(std::max(1, max_leaf), kW) * kW;
   return 4 * 16384 * kW / qmax;
+}
+
+int64_t base_partial_doubles(int max_leaf) {
+  const int qmax = (int)ceil_div(std::max(1, max_leaf), kW) * kW;
+  return (int64_t)base_partial_slots(max_leaf) * kHB * qmax;
 }
 
 // Entries per slice: about base_partial_slots / 2 slices in all, at least 8

@@ -237,11 +237,11 @@ def _sorted_trace(c):
 def test_dualtree_bandwidth_chunks():
     """Bandwidths never interact in the traversal: any split of the sweep
     (h_chunk) makes the same decisions; values differ only by the summation
-    order of the base tiles.  10 bandwidths span two base-tile blocks of 8, and
-    chunks of 3 split both blocks across chunks."""
+    order of the base tiles.  20 bandwidths span two base-tile blocks of 16,
+    and chunks of 3 and 7 split both blocks across chunks."""
     banner("dualtree chunks")
     r, w, _ = mixture((91, 3), 3000, 3, 8, (0.01, 0.1))
-    hs = np.logspace(-3, 0, 10)
+    hs = np.logspace(-3, 0, 20)
     c = ctx()
     G0 = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=32, keep_trace=1)
     tr0 = _sorted_trace(c)
