@@ -16,8 +16,9 @@ step).  Beside it: the plain GPU exhaustive path on the same sets (one step),
 the roofline of the dominant kernel (the base-case tiles; HIP events on the
 library's stream over the timed steps), the D=3, 10^5-point, 10-bandwidth
 workload with the paper's other dual-tree variants (DFTO, DFDO, DFD), node
-bounds, LSCV and the learned pair policy, and the CPU oracle's rate on a
-bounded sample of the headline sets.
+bounds, pair order, LSCV and the learned pair policy, and the CPU oracle's
+rate on a bounded sample of the headline sets (its exhaustive sum, and its
+dual-tree in both traversal modes on a 2,000-point draw).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -99,6 +100,30 @@ def cpu_baseline(sets, n_queries_per_set, seed=0):
             "sample": "FP64 exhaustive oracle, %d random queries of each of %s x all references x "
                       "all bandwidths (%.3g pair-evals in %.1f s)"
                       % (n_queries_per_set, ", ".join(w.name for w in sets), evals, t)}
+
+
+def cpu_dualtree_baseline(workload_fn, D=3, scale=0.002, leaf=64):
+    """The oracle's own dual-tree (FP64, one core) on a small draw of the
+    headline recipe, in its frontier mode (the library's schedule) and its
+    paper mode (the depth-first recursion of Figures 1 and 7): time per call
+    and pair-evals/s equivalent.  A draw this small is all the pure-Python
+    traversal finishes in seconds, so its rate says nothing about 10^6 points."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.dualtree import dualtree
+    wl = workload_fn(4, D=D, scale=scale)
+    n = wl.refs.shape[0]
+    out = {}
+    with threadpool_limits(limits=1):
+        for mode in ("level", "depth_first"):
+            t0 = time.perf_counter()
+            dualtree(wl.refs, wl.refs, wl.weights, wl.bandwidths, wl.eps, leaf_size=leaf, traversal=mode)
+            t = time.perf_counter() - t0
+            out["frontier" if mode == "level" else "paper"] = {
+                "value": float(n) * n * len(wl.bandwidths) / t, "unit": "pair-evals/s", "seconds": t}
+    out.update({"cores": 1, "kind": "oracle",
+                "sample": "oracle dual-tree on %s (another size of the same recipe), leaf %d" % (wl.name, leaf)})
+    return out
 
 
 def log(*parts):
@@ -423,6 +448,7 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline([s.wl for s in sets], args.cpu_queries)
+        result["cpu_baseline"]["dualtree"] = cpu_dualtree_baseline(workload)
     ctx.close()
     print(json.dumps(result), flush=True)
 
