@@ -384,6 +384,49 @@ def test_kernel_timing_modes():
     assert e.value.status == _lib.GS_EINVAL
 
 
+FULL_BLOCK_CASES = [
+    # (D, N, log10 h range, seed): 20 bandwidths, leaf 128; the leaf pairs' base
+    # cases span 1..16 bandwidths of the first 16-bandwidth block (hundreds of
+    # entries with all 16), and 1..4 of the second
+    (3, 6000, (-2.0, -0.5), 94),
+    (5, 5000, (-1.6, -0.2), 95),
+    (8, 4000, (-1.2, 0.0), 96),
+]
+
+
+@pytest.mark.parametrize("case", FULL_BLOCK_CASES, ids=["d%d" % c[0] for c in FULL_BLOCK_CASES])
+def test_base_tiles_full_bandwidth_blocks(case):
+    """Base entries whose masks fill whole 16-bandwidth blocks (every mask size
+    1..16 occurs, on the MFMA and the difference-form paths): decisions
+    bit-exact with the oracle, values within the rounding tolerance of its G~,
+    Theorem 2 against the exhaustive sum, and a chunked sweep (chunks of 7
+    split the first block) gives the same values."""
+    D, N, (lo, hi), seed = case
+    banner("base tiles full blocks", D)
+    r, w, _ = mixture((seed, D), N, D, 6, (0.01, 0.1), weights=(0.5, 1.5))
+    hs = np.logspace(lo, hi, 20)
+    c = ctx()
+    G = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=128, keep_trace=1)
+    st = c.stats()
+    got = _sorted_trace(c)
+    ref = DT.dualtree(r, r, w, hs, 0.01, leaf_size=128, trace=True)
+    want = np.array(ref.trace, dtype=np.int64).reshape(-1, 6)
+    assert np.array_equal(got, want[np.lexsort(want.T[::-1])])
+    assert np.array_equal(c.pair_counts(len(hs)), ref.counts)
+    # the base cases of one (Q, R) fill a whole block somewhere
+    base = want[want[:, 4] == 4]
+    per_block = {}
+    for h, _, q, rr, _, _ in base:
+        per_block[(q, rr, h // 16)] = per_block.get((q, rr, h // 16), 0) + 1
+    assert max(per_block.values()) == 16
+    assert 0 < st.base_mfma_pair_evals < st.base_pair_evals, (st.base_mfma_pair_evals, st.base_pair_evals)
+    exact = gauss_sum_exhaustive(r, r, w, hs)
+    assert (np.abs(G - ref.G) / exact).max() <= TOL_ROUND
+    assert (np.abs(G - exact) / exact).max() <= 0.01
+    G7 = c.gauss_sum(r, r, w, hs, 0.01, leaf_size=128, h_chunk=7)
+    assert (np.abs(G7 - G) / exact).max() <= 1e-12
+
+
 def test_base_tiles_mfma_and_difference_paths():
     """The base tiles take a bandwidth's squared distances from the MFMA norm
     expansion only where its rounding bound admits it, else from the
