@@ -71,12 +71,16 @@ __host__ __device__ constexpr int mfma_k2(int D) { return (D + 3) / 2 * 2; }
 __host__ __device__ constexpr int mfma_group_floats(int D) { return kMG * mfma_k2(D) + kMG; }
 // Dimensions whose compiled base tiles take distances from MFMA.
 constexpr bool mfma_dim(int DT) { return DT >= 2; }
-// Rounding bound of the expansion |u_q|^2 + |u_r|^2 - 2 u_q.u_r in float:
-// the two norms carry at most D units in the last place of themselves, the
-// products and the sum of the K2 augmented terms at most K2 of their absolute
-// sum, which is <= (|u_q| + |u_r|)^2; one more for the bound's own rounding.
+// Rounding bound of the expansion |u_q|^2 + |u_r|^2 - 2 u_q.u_r in float,
+// in units of 2^-24 (|u_q| + |u_r|)^2: the two norms are summed exactly in
+// double from the same float coordinates the products use and rounded once
+// (one unit for both, |u_q|^2 + |u_r|^2 <= (|u_q| + |u_r|)^2; |u_q|^2 - T_q
+// likewise, T_q being the float shift the unscaling uses); the K2 products
+// and the K2 additions of the MFMA chain at most K2 + 1 units of their
+// absolute sum, which is <= (|u_q| + |u_r|)^2; one more for the bound's own
+// rounding.
 template <int D>
-constexpr int kMfmaErrC = D + mfma_k2(D) + 2;
+constexpr int kMfmaErrC = mfma_k2(D) + 3;
 // Largest relative error of a kernel term admitted from the expansion.
 constexpr float kMfmaTau = 0x1p-12f;
 
@@ -128,12 +132,13 @@ __global__ void mfma_records_kernel(const double* __restrict__ xr, const double*
   float* g = mrec + (int64_t)(mgrp_off[L] + idx / kMG) * mfma_group_floats(D);
   const int row = idx % kMG;
   const double* c = rctr + (int64_t)L * D;
-  float nr = 0.0f;
+  double nrd = 0.0;  // |u_r|^2 of the float coordinates: exact squares, summed in double
   for (int d = 0; d < D; ++d) {
     const float u = (float)(xr[i * D + d] - c[d]);
-    nr = fmaf(u, u, nr);
+    nrd += (double)u * (double)u;
     g[(d / 2) * 64 + (d % 2) * kMG + row] = -2.0f * u;
   }
+  const float nr = (float)nrd;
   g[(D / 2) * 64 + (D % 2) * kMG + row] = 1.0f;
   g[((D + 1) / 2) * 64 + ((D + 1) % 2) * kMG + row] = nr;
   g[kMG * k2 + row] = (float)(wr[i] / __longlong_as_double((long long)*wmax_bits));
@@ -608,12 +613,15 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
       // most that times s_h; a bandwidth is admitted when the resulting
       // relative error of every term is below kMfmaTau.
       unsigned safe = 0;
-      float nq = 0.0f;
+      float nqt = 0.0f;              // |u_q|^2 - T_q, the query's augmented coordinate
       const float tq = (float)box2;  // the box shift T_q of the MFMA path
       if (mfma_dim(DT) && mrec != nullptr) {
+        double nqd = 0.0;  // |u_q|^2 of the float coordinates: exact squares, summed in double
 #pragma unroll
-        for (int d = 0; d < DC; ++d) nq = fmaf(uq[d], uq[d], nq);
-        float mx = nq;
+        for (int d = 0; d < DC; ++d)
+          if (d < D) nqd += (double)uq[d] * (double)uq[d];
+        nqt = (float)(nqd - (double)tq);
+        float mx = (float)nqd;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kW));
         const float rr = sqrtf(rmax2[R]) + sqrtf(mx);
@@ -681,7 +689,7 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
             const int qrem = qn - base;
             const unsigned lows =
                 mfma_sweep_leaf<DT>(na, mrec + (int64_t)mgrp_off[R] * mfma_group_floats(DT),
-                                    (rt.count[R] + kMG - 1) / kMG, qrem > kMG ? 2 : 1, uq, nq - tq, shc, bits,
+                                    (rt.count[R] + kMG - 1) / kMG, qrem > kMG ? 2 : 1, uq, nqt, shc, bits,
                                     acc, tq, qrem);
             if (lows != 0) rescue(lane >= 32 ? lows >> 16 : lows & 0xffffu);
           }
