@@ -659,7 +659,8 @@ __global__ __launch_bounds__(kW * kBaseWaves) __attribute__((amdgpu_waves_per_eu
         // formed exactly in double.
         auto accumulate = [&](unsigned jmask, float t2) {
           unsigned mm = bits;
-#pragma unroll
+          // left rolled: once per entry and bandwidth, and 16 unrolled copies
+          // of its double arithmetic at each call measured slower
           for (int j = 0; j < kHB; ++j) {
             if (mm == 0) break;
             const int k = __builtin_ctz(mm);
