@@ -1,6 +1,7 @@
 """Host-side parts of bench.py: the refusal of several GPUs, the issue-slot
-models behind the roofline, and the reading of the committed HBM-traffic
-profile (it is taken only while the kernel source still matches its hash)."""
+models behind the roofline, the reading of the committed HBM-traffic
+profile (it is taken only while the kernel source still matches its hash),
+and the CPU dual-tree baseline's report."""
 import os
 import subprocess
 import sys
@@ -49,3 +50,18 @@ def test_traffic_profile_needs_matching_source(tmp_path):
     src.write_bytes(b"changed kernel source")
     assert bench.measured_traffic(str(src), str(prof), "base_fused_kernel<3>") is None
     assert bench.measured_traffic(str(src), str(tmp_path / "missing.txt"), "base_fused_kernel<3>") is None
+
+
+def test_cpu_dualtree_baseline_shape():
+    """The CPU baseline's dual-tree leg times the oracle in both traversal
+    modes on one core and reports pair-evals/s equivalent of the draw it ran
+    (here a 500-point draw of the D = 3 recipe)."""
+    from paper_1206_6857_amd.datagen import workload
+    r = bench.cpu_dualtree_baseline(workload, D=3, scale=0.0005, leaf=32)
+    wl = workload(4, D=3, scale=0.0005)
+    n = wl.refs.shape[0]
+    assert r["cores"] == 1 and r["kind"] == "oracle" and wl.name in r["sample"]
+    for mode in ("frontier", "paper"):
+        leg = r[mode]
+        assert leg["unit"] == "pair-evals/s" and leg["seconds"] > 0
+        assert abs(leg["value"] * leg["seconds"] - float(n) * n * len(wl.bandwidths)) < 1e-6 * n * n * 64
